@@ -1,0 +1,143 @@
+"""Seeded synthetic inputs: SU(3) gauge fields, their inverse clover field, sources.
+
+This module holds no solver arithmetic.  It produces the input fields that the
+solver takes as given: the gauge links U, the inverse clover field F (an input
+to the library, see eq. 2.2 of Boku et al., arXiv:1210.7398), and right-hand
+sides.  The paper names no gauge ensemble, so seed-fixed fields of the paper's
+lattice shapes stand in for them.
+
+Interchange layout (numpy, complex128, site n = x + Lx*(y + Ly*(z + Lz*t))):
+  links   [V, 4, 3, 3]   U_mu(n)[a, b], the link from n to n+mu
+  clover  [V, 2, 6, 6]   two chiral 6x6 blocks, row index 3*(alpha-2k)+a
+  spinor  [V, 4, 3]
+"""
+import numpy as np
+
+# Gell-Mann matrices
+_GM = np.zeros((8, 3, 3), np.complex128)
+_GM[0][0, 1] = _GM[0][1, 0] = 1
+_GM[1][0, 1] = -1j
+_GM[1][1, 0] = 1j
+_GM[2][0, 0] = 1
+_GM[2][1, 1] = -1
+_GM[3][0, 2] = _GM[3][2, 0] = 1
+_GM[4][0, 2] = -1j
+_GM[4][2, 0] = 1j
+_GM[5][1, 2] = _GM[5][2, 1] = 1
+_GM[6][1, 2] = -1j
+_GM[6][2, 1] = 1j
+_GM[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+
+
+def volume(L):
+    return int(np.prod(L))
+
+
+def su3_from_normals(h, eps):
+    """exp(i eps H) with H = sum_a h_a lambda_a / 2 (traceless hermitian), via eigh."""
+    H = np.einsum("...a,aij->...ij", h, _GM) * 0.5
+    w, vec = np.linalg.eigh(H)
+    ph = np.exp(1j * eps * w)
+    return np.einsum("...ij,...j,...kj->...ik", vec, ph, vec.conj())
+
+
+def gauge_field(L, eps, seed):
+    """U_mu(n) = exp(i eps H), H Gaussian traceless hermitian, drawn as normals of shape
+    (Lt, Lz, Ly, Lx, 4, 8) from numpy's default_rng(seed); returns [V, 4, 3, 3]."""
+    Lx, Ly, Lz, Lt = L
+    rng = np.random.default_rng(seed)
+    V = volume(L)
+    U = np.empty((V, 4, 3, 3), np.complex128)
+    h = rng.normal(size=(Lt, Lz, Ly, Lx, 4, 8)).reshape(V, 4, 8)
+    chunk = 1 << 18
+    for s in range(0, V, chunk):
+        U[s : s + chunk] = su3_from_normals(h[s : s + chunk], eps)
+    return U
+
+
+def unit_gauge(L):
+    V = volume(L)
+    return np.broadcast_to(np.eye(3, dtype=np.complex128), (V, 4, 3, 3)).copy()
+
+
+def random_su3_field(V, seed, eps=1.0):
+    """One SU(3) matrix per site (for gauge transformations)."""
+    rng = np.random.default_rng(seed)
+    return su3_from_normals(rng.normal(size=(V, 8)), eps)
+
+
+def gaussian_spinor(L, seed):
+    """Complex Gaussian source: Re and Im i.i.d. N(0,1) per component, [V, 4, 3]."""
+    rng = np.random.default_rng(seed)
+    V = volume(L)
+    return (rng.normal(size=(V, 4, 3)) + 1j * rng.normal(size=(V, 4, 3))).astype(np.complex128)
+
+
+def point_source(L, spin, colour, site=0):
+    V = volume(L)
+    b = np.zeros((V, 4, 3), np.complex128)
+    b[site, spin, colour] = 1.0
+    return b
+
+
+# --- chiral gamma basis used by the whole project (gamma5 = diag(1,1,-1,-1)) ------------
+_PAULI = np.array([[[0, 1], [1, 0]], [[0, -1j], [1j, 0]], [[1, 0], [0, -1]]], np.complex128)
+
+
+def gamma_matrices():
+    g = np.zeros((4, 4, 4), np.complex128)
+    for k in range(3):
+        g[k, :2, 2:] = -1j * _PAULI[k]
+        g[k, 2:, :2] = 1j * _PAULI[k]
+    g[3, :2, 2:] = np.eye(2)
+    g[3, 2:, :2] = np.eye(2)
+    return g
+
+
+def _shift(f, L, mu, step):
+    """Field at n + step*mu (periodic), for f of shape [V, ...]."""
+    Lx, Ly, Lz, Lt = L
+    axis = 3 - mu
+    g = f.reshape((Lt, Lz, Ly, Lx) + f.shape[1:])
+    return np.roll(g, -step, axis=axis).reshape(f.shape)
+
+
+def clover_inverse(L, U, csw, kappa):
+    """Inverse clover field F(n) = (1 - c_SW kappa sum_{mu<nu} sigma_mu_nu F_mu_nu(n))^-1 as two
+    chiral 6x6 blocks [V, 2, 6, 6]; F_mu_nu is the four-leaf clover (Q - Q^+)/(8i), traceless,
+    sigma_mu_nu = (i/2)[gamma_mu, gamma_nu].  Periodic gauge field (no fermion phases)."""
+    V = volume(L)
+    g = gamma_matrices()
+    dag = lambda m: np.swapaxes(m.conj(), -1, -2)
+    A = np.zeros((V, 12, 12), np.complex128)
+    A[:] = np.eye(12)
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            Umu = U[:, mu]
+            Unu = U[:, nu]
+            Umu_pnu = _shift(Umu, L, nu, 1)
+            Unu_pmu = _shift(Unu, L, mu, 1)
+            Umu_mmu = _shift(Umu, L, mu, -1)
+            Unu_mmu = _shift(Unu, L, mu, -1)
+            Umu_mmu_pnu = _shift(Umu_mmu, L, nu, 1)
+            Umu_mmu_mnu = _shift(Umu_mmu, L, nu, -1)
+            Unu_mmu_mnu = _shift(Unu_mmu, L, nu, -1)
+            Umu_mnu = _shift(Umu, L, nu, -1)
+            Unu_mnu = _shift(Unu, L, nu, -1)
+            Unu_pmu_mnu = _shift(Unu_pmu, L, nu, -1)
+            Q = Umu @ Unu_pmu @ dag(Umu_pnu) @ dag(Unu)
+            Q += Unu @ dag(Umu_mmu_pnu) @ dag(Unu_mmu) @ Umu_mmu
+            Q += dag(Umu_mmu) @ dag(Unu_mmu_mnu) @ Umu_mmu_mnu @ Unu_mnu
+            Q += dag(Unu_mnu) @ Umu_mnu @ Unu_pmu_mnu @ dag(Umu)
+            Fmn = (Q - dag(Q)) / 8j
+            tr = np.trace(Fmn, axis1=1, axis2=2) / 3.0
+            Fmn -= tr[:, None, None] * np.eye(3)
+            sig = 0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu])
+            A -= csw * kappa * np.einsum("ab,nij->naibj", sig, Fmn).reshape(V, 12, 12)
+    blocks = np.stack([A[:, 0:6, 0:6], A[:, 6:12, 6:12]], axis=1)
+    return np.linalg.inv(blocks)
+
+
+def unit_clover(L):
+    V = volume(L)
+    return np.broadcast_to(np.eye(6, dtype=np.complex128), (V, 2, 6, 6)).copy()
