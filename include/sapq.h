@@ -1,0 +1,192 @@
+/*
+ * sapq.h -- C ABI of libsapq, an MI355X (gfx950) solver for the clover-Wilson
+ * system D x = b with the SAP preconditioner, SSOR block inverses in
+ * locally-lexicographic order, and a nested FP64/low-precision BiCGStab, after
+ * Boku et al., "Multi-block/multi-core SSOR preconditioner for the QCD quark
+ * solver for K computer" (Lattice 2012, arXiv:1210.7398).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers (e.g. a torch tensor's data_ptr())
+ *    unless marked "host".  The library never allocates device memory: the
+ *    caller passes one arena of sapq_arena_bytes() bytes to sapq_create() and
+ *    keeps it alive until sapq_destroy().  The caller owns every buffer.
+ *  - Interchange layout, complex128 as interleaved (re, im) doubles, site index
+ *    n = x + Lx*(y + Ly*(z + Lz*t)):
+ *        spinor  [V][4][3]        spin alpha, colour a
+ *        links   [V][4][3][3]     U_mu(n)[a][b], the link from n to n+mu, mu = x,y,z,t
+ *        clover  [V][2][6][6]     inverse clover F(n): two chiral 6x6 blocks acting on
+ *                                 spins {0,1} and {2,3}; row/column 3*(alpha-2k)+a
+ *    Gamma matrices are the chiral hermitian Euclidean basis with
+ *    gamma_k = [[0, -i sigma_k], [i sigma_k, 0]], gamma_4 = [[0, 1], [1, 0]],
+ *    gamma5 = g1 g2 g3 g4 = diag(1, 1, -1, -1).
+ *  - Work is enqueued on the HIP stream given to sapq_create().  sapq_dslash,
+ *    sapq_ssor, sapq_dk and sapq_sap_precondition are asynchronous; the solvers
+ *    synchronise the stream for their convergence tests and return when done.
+ *  - Every call returns a sapq_status.  On SAPQ_EINVAL / SAPQ_ESHAPE outputs are
+ *    untouched; sapq_last_error() gives a message (thread-local, host string).
+ *  - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef SAPQ_H
+#define SAPQ_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sapq_ctx sapq_ctx;
+
+typedef enum {
+    SAPQ_OK = 0,
+    SAPQ_EINVAL = -1,     /* bad argument (null pointer, bad enum, bad parameter) */
+    SAPQ_ESHAPE = -2,     /* geometry not allowed, see sapq_geom */
+    SAPQ_ENOTSU3 = -3,    /* links are not SU(3) to 1e-10 (2-row storage needs det U = 1) */
+    SAPQ_ENOTCONV = -4,   /* solver stopped at maxit; best iterate and stats returned */
+    SAPQ_EBREAKDOWN = -5, /* BiCGStab breakdown that restarts could not cure */
+    SAPQ_EHIP = -6,       /* a HIP runtime call failed */
+    SAPQ_ENOMEM = -7,     /* the arena is smaller than sapq_arena_bytes() */
+    SAPQ_ESTATE = -8      /* fields not loaded yet */
+} sapq_status;
+
+/* storage precision of the SAP preconditioner and inner solver vectors/fields;
+ * arithmetic is FP32 for FP32/FP16/BF16 storage and FP64 for FP64. */
+typedef enum { SAPQ_FP64 = 0, SAPQ_FP32 = 1, SAPQ_FP16 = 2, SAPQ_BF16 = 3 } sapq_prec;
+
+/* outer iteration (section 2 of the paper: flexible outer BiCGStab around the inner solver) */
+typedef enum { SAPQ_OUTER_FBICGSTAB = 0, SAPQ_OUTER_DEFECT = 1 } sapq_outer;
+
+/*
+ * Geometry.  L: lattice extents (x,y,z,t).  block: SAP block extents; the blocks
+ * are coloured like a checkerboard, E = colour 0 holds the origin (eq. 2.3).
+ * subblock: sub-block extents of the locally-lexicographic ordering (section 3).
+ * bc_sign: +1 periodic, -1 antiperiodic fermion boundary per direction; the sign
+ * multiplies the hops that cross the lattice boundary.
+ * Constraints (else SAPQ_ESHAPE): block[mu] divides L[mu] and L[mu]/block[mu] is
+ * even and >= 2 (so neighbouring blocks always have opposite colours);
+ * subblock[mu] divides block[mu] and is >= 2 (so sites at the same sub-block-local
+ * position never couple); at most 1024 sites in one hyperplane of a block.
+ */
+typedef struct {
+    int L[4];
+    int block[4];
+    int subblock[4];
+    int bc_sign[4];
+} sapq_geom;
+
+/*
+ * Parameters.  kappa: hopping parameter of D (eq. 2.2).  omega: SSOR relaxation;
+ * n_ssor: symmetric (forward + backward) SSOR sweeps from x = 0 per block inverse;
+ * n_sap: N_SAP of eq. (2.4).  tol_inner / maxit_inner: relative residual target and
+ * iteration cap of the inner BiCGStab.  maxit_outer: outer iteration cap.
+ * prec_inner: storage precision of SAP + inner solver (SAPQ_FP32, _FP16, _BF16).
+ * outer: sapq_outer.  flags: SAPQ_FLAG_GUESS | SAPQ_FLAG_PROFILE.
+ */
+typedef struct {
+    double kappa, omega, tol_inner;
+    int n_ssor, n_sap, maxit_inner, maxit_outer;
+    int prec_inner;
+    int outer;
+    int flags;
+} sapq_params;
+
+#define SAPQ_FLAG_GUESS 1   /* sapq_solve starts from the x passed in */
+#define SAPQ_FLAG_PROFILE 2 /* sapq_solve times its kernels with HIP events (see sapq_stats) */
+
+/* Per-solve statistics (host struct). */
+typedef struct {
+    int outer_its;       /* outer iterations (each applies the inner solver once or twice) */
+    int inner_its;       /* inner BiCGStab iterations summed over the solve */
+    int n_msap;          /* M_SAP applications */
+    int n_dslash64;      /* FP64 operator applications */
+    int restarts;        /* true-residual restarts of the outer iteration */
+    int n_hist;          /* entries in relres_hist */
+    double true_relres;  /* |b - D x| / |b| in FP64 at exit */
+    double time_s;       /* wall time of the solve on the host clock */
+    /* with params.flags & SAPQ_FLAG_PROFILE: HIP-event time (ms) summed per kernel kind
+     * and launches per kind, measured on the context's stream during the solve.
+     * kinds: SAPQ_K_PHASE_E, SAPQ_K_PHASE_O, SAPQ_K_FACE, SAPQ_K_DSLASH64, SAPQ_K_BLAS */
+    double kern_ms[8];
+    int kern_n[8];
+    double relres_hist[256];
+} sapq_stats;
+
+enum { SAPQ_K_PHASE_E = 0, SAPQ_K_PHASE_O = 1, SAPQ_K_FACE = 2, SAPQ_K_DSLASH64 = 3, SAPQ_K_BLAS = 4 };
+
+/* Bytes of device arena a context needs (host call; 0 on a bad geometry). */
+size_t sapq_arena_bytes(const sapq_geom *geom, const sapq_params *params);
+
+/*
+ * Create a context.  arena: device memory of >= sapq_arena_bytes() bytes, 256-byte
+ * aligned, owned by the caller.  stream: hipStream_t (NULL = default stream).
+ * Builds the block/sub-block/hyperplane tables on the device.
+ */
+int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, size_t arena_bytes,
+                void *stream, sapq_ctx **out);
+
+/* Change kappa, omega, n_ssor, n_sap, tolerances or outer kind (not prec_inner). */
+int sapq_set_params(sapq_ctx *ctx, const sapq_params *params);
+
+/*
+ * Load the gauge field U (links layout above).  Stores rows 0 and 1 of every link
+ * (row 2 is rebuilt as conj(row0 x row1), section 3 "SIMDzation") in FP64 and in the
+ * inner storage precision.  Returns SAPQ_ENOTSU3 if max |U^+ U - 1| or |det U - 1|
+ * exceeds 1e-10; *max_dev (host, nullable) receives that maximum.
+ */
+int sapq_load_gauge(sapq_ctx *ctx, const double *U, double *max_dev);
+
+/* Load the inverse clover field F of eq. (2.2) (clover layout above; hermitian blocks). */
+int sapq_load_clover_inv(sapq_ctx *ctx, const double *F);
+
+/*
+ * out = D in, eq. (2.2): D = 1 - kappa F(n) sum_mu [(1-gamma_mu) U_mu(n) delta(n+mu,m)
+ * + (1+gamma_mu) U_mu(n-mu)^+ delta(n-mu,m)].  prec: SAPQ_FP64 computes in FP64, otherwise
+ * the fields and vectors are held in that storage precision with FP32 arithmetic.
+ * in, out: spinor layout; may not alias.
+ */
+int sapq_dslash(sapq_ctx *ctx, double *out, const double *in, int prec);
+
+/*
+ * x = A_cc v: the SSOR approximate inverse of the block operator on every block of
+ * colour `colour` (0 = E, 1 = O), section 3 "Inverse of block operator": from x = 0,
+ * n_ssor forward+backward substitution sweeps in locally-lexicographic order.  Runs in
+ * the inner precision.  Sites of the other colour get x = 0.
+ */
+int sapq_ssor(sapq_ctx *ctx, double *x, const double *v, int colour);
+
+/* (x, w) = (K v, D K v) by Algorithm 1 (K of eq. 2.4), in the inner precision. */
+int sapq_dk(sapq_ctx *ctx, double *x, double *w, const double *v);
+
+/*
+ * out = M_SAP in, eq. (2.4): N_SAP cycles of r <- r - D K r, out = sum of the K r;
+ * d_out (nullable) = D M_SAP in, which the recurrence yields as in - r_N.  Inner precision.
+ */
+int sapq_sap_precondition(sapq_ctx *ctx, double *out, double *d_out, const double *in);
+
+/*
+ * e ~ D^-1 r by the inner BiCGStab right-preconditioned with M_SAP (section 2), from
+ * e = 0, to |r - D e| <= tol_inner |r| (recursive residual) or maxit_inner iterations.
+ * *iters (host, nullable) receives the iteration count.  Inner precision.
+ */
+int sapq_inner_solve(sapq_ctx *ctx, double *e, const double *r, int *iters);
+
+/*
+ * Solve D x = b to |b - D x|_2 / |b|_2 <= tol (true residual in FP64), section 2: the
+ * outer FP64 flexible BiCGStab (or defect correction) whose preconditioner is the inner
+ * low-precision BiCGStab with M_SAP.  x: initial guess if params.flags & SAPQ_FLAG_GUESS,
+ * solution on return.  stats (host, nullable).  SAPQ_ENOTCONV leaves the best iterate.
+ */
+int sapq_solve(sapq_ctx *ctx, double *x, const double *b, double tol, sapq_stats *stats);
+
+/* Release the context (host memory only; the arena stays the caller's). */
+void sapq_destroy(sapq_ctx *ctx);
+
+/* Message for the last non-OK return on this thread (host string, never NULL). */
+const char *sapq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAPQ_H */

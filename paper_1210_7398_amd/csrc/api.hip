@@ -1,0 +1,674 @@
+// C ABI of libsapq (declared in include/sapq.h): context set-up, geometry tables,
+// field loading, and the host drivers of M_SAP, the inner BiCGStab and the
+// outer flexible BiCGStab / defect correction.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sapq_impl.h"
+
+namespace sapq {
+
+static thread_local std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+
+size_t elem_bytes(int prec) {
+    switch (prec) {
+    case SAPQ_FP64: return 16;
+    case SAPQ_FP32: return 8;
+    default: return 4;
+    }
+}
+
+void set_sap_lds_limits(Ctx *c);
+
+// ---------------------------------------------------------------- kernel timing
+int prof_begin(Ctx *c, int kind) {
+    Prof &p = c->prof;
+    if (!p.on) return -1;
+    if ((int)p.ev.size() < 2 * (p.used + 1)) {
+        for (int k = 0; k < 2; ++k) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
+            p.ev.push_back(e);
+        }
+        p.kind.resize(p.ev.size() / 2);
+    }
+    int slot = p.used++;
+    p.kind[slot] = kind;
+    (void)hipEventRecord(p.ev[2 * slot], c->stream);
+    return slot;
+}
+
+void prof_end(Ctx *c, int slot) {
+    if (slot >= 0) (void)hipEventRecord(c->prof.ev[2 * slot + 1], c->stream);
+}
+
+// call after the stream has been synchronised
+void prof_harvest(Ctx *c) {
+    Prof &p = c->prof;
+    for (int i = 0; i < p.used; ++i) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1]) == hipSuccess) {
+            p.ms[p.kind[i]] += ms;
+            p.n[p.kind[i]] += 1;
+        }
+    }
+    p.used = 0;
+}
+
+// ---------------------------------------------------------------- geometry tables (host)
+struct HostTables {
+    int Vb = 0, NB = 0, nplanes = 0, max_plane = 0;
+    int nbk[4];
+    std::vector<int> loc_nbr, blk_nbr, plane_start, slot_lex, blk_lex;
+};
+
+static int check_geom(const sapq_geom *g, std::string &why) {
+    for (int m = 0; m < 4; ++m) {
+        int L = g->L[m], B = g->block[m], S = g->subblock[m];
+        if (L <= 0 || B <= 0 || S <= 0) { why = "non-positive extent"; return SAPQ_ESHAPE; }
+        if (L % B) { why = "block does not divide the lattice in direction " + std::to_string(m); return SAPQ_ESHAPE; }
+        int nb = L / B;
+        if (nb < 2 || nb % 2) { why = "blocks per direction must be even and >= 2 (direction " + std::to_string(m) + ")"; return SAPQ_ESHAPE; }
+        if (B % S) { why = "sub-block does not divide the block in direction " + std::to_string(m); return SAPQ_ESHAPE; }
+        if (S < 2) { why = "sub-block extent must be >= 2 (direction " + std::to_string(m) + ")"; return SAPQ_ESHAPE; }
+        if (g->bc_sign[m] != 1 && g->bc_sign[m] != -1) { why = "bc_sign must be +1 or -1"; return SAPQ_EINVAL; }
+    }
+    return SAPQ_OK;
+}
+
+// Slots sorted by hyperplane h = sum_mu (x_mu mod S_mu); inside a plane by the ll key.
+static void build_tables(const sapq_geom *G, HostTables &T) {
+    const int *B = G->block, *S = G->subblock;
+    int Vb = B[0] * B[1] * B[2] * B[3];
+    int ns[4];
+    for (int m = 0; m < 4; ++m) { ns[m] = B[m] / S[m]; T.nbk[m] = G->L[m] / B[m]; }
+    int Nsub = ns[0] * ns[1] * ns[2] * ns[3];
+    struct Key { int h; long ll; int lex; };
+    std::vector<Key> keys(Vb);
+    for (int l = 0; l < Vb; ++l) {
+        int c[4], r = l;
+        for (int m = 0; m < 4; ++m) { c[m] = r % B[m]; r /= B[m]; }
+        int h = 0; long pos = 0, sub = 0, pm = 1, sm = 1;
+        for (int m = 0; m < 4; ++m) {
+            h += c[m] % S[m];
+            pos += (c[m] % S[m]) * pm; pm *= S[m];
+            sub += (c[m] / S[m]) * sm; sm *= ns[m];
+        }
+        keys[l] = {h, pos * Nsub + sub, l};
+    }
+    std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) { return a.h != b.h ? a.h < b.h : a.ll < b.ll; });
+    T.Vb = Vb;
+    T.slot_lex.resize(Vb);
+    std::vector<int> slot_of(Vb);
+    for (int s = 0; s < Vb; ++s) { T.slot_lex[s] = keys[s].lex; slot_of[keys[s].lex] = s; }
+    int H = keys.back().h + 1;
+    T.nplanes = H;
+    T.plane_start.assign(H + 1, 0);
+    for (auto &k : keys) T.plane_start[k.h + 1]++;
+    for (int p = 0; p < H; ++p) T.plane_start[p + 1] += T.plane_start[p];
+    T.max_plane = 0;
+    for (int p = 0; p < H; ++p) T.max_plane = std::max(T.max_plane, T.plane_start[p + 1] - T.plane_start[p]);
+    // in-block neighbours
+    T.loc_nbr.resize(8 * Vb);
+    for (int s = 0; s < Vb; ++s) {
+        int c[4], r = T.slot_lex[s];
+        for (int m = 0; m < 4; ++m) { c[m] = r % B[m]; r /= B[m]; }
+        for (int mu = 0; mu < 4; ++mu)
+            for (int dir = 0; dir < 2; ++dir) {
+                int cc[4] = {c[0], c[1], c[2], c[3]};
+                cc[mu] += dir == 0 ? 1 : -1;
+                bool inside = cc[mu] >= 0 && cc[mu] < B[mu];
+                cc[mu] = (cc[mu] + B[mu]) % B[mu];
+                int l = cc[0] + B[0] * (cc[1] + B[1] * (cc[2] + B[2] * cc[3]));
+                int t = slot_of[l];
+                T.loc_nbr[(2 * mu + dir) * Vb + s] = inside ? t : -1 - t;
+            }
+    }
+    // blocks: E (colour 0) first, then O, each in lexicographic order
+    int NB = T.nbk[0] * T.nbk[1] * T.nbk[2] * T.nbk[3];
+    T.NB = NB;
+    T.blk_lex.clear();
+    for (int col = 0; col < 2; ++col)
+        for (int b = 0; b < NB; ++b) {
+            int r = b, sum = 0;
+            for (int m = 0; m < 4; ++m) { sum += r % T.nbk[m]; r /= T.nbk[m]; }
+            if ((sum & 1) == col) T.blk_lex.push_back(b);
+        }
+    std::vector<int> ib_of(NB);
+    for (int i = 0; i < NB; ++i) ib_of[T.blk_lex[i]] = i;
+    T.blk_nbr.resize(8 * NB);
+    for (int i = 0; i < NB; ++i) {
+        int c[4], r = T.blk_lex[i];
+        for (int m = 0; m < 4; ++m) { c[m] = r % T.nbk[m]; r /= T.nbk[m]; }
+        for (int mu = 0; mu < 4; ++mu)
+            for (int dir = 0; dir < 2; ++dir) {
+                int cc[4] = {c[0], c[1], c[2], c[3]};
+                cc[mu] += dir == 0 ? 1 : -1;
+                bool wrap = cc[mu] < 0 || cc[mu] >= T.nbk[mu];
+                cc[mu] = (cc[mu] + T.nbk[mu]) % T.nbk[mu];
+                int l = cc[0] + T.nbk[0] * (cc[1] + T.nbk[1] * (cc[2] + T.nbk[2] * cc[3]));
+                T.blk_nbr[(2 * mu + dir) * NB + i] = ib_of[l] | (wrap ? WRAP_BIT : 0);
+            }
+    }
+}
+
+// ---------------------------------------------------------------- arena
+struct Arena {
+    char *base;
+    size_t cap, used;
+    void *take(size_t bytes) {
+        size_t off = (used + 255) & ~(size_t)255;
+        used = off + bytes;
+        return base ? (void *)(base + off) : nullptr;
+    }
+};
+
+static const int RED_BLOCKS = 512;
+
+static void carve(Ctx *c, Arena &A, const HostTables &T) {
+    long V = c->V;
+    size_t nv = c->nvec;
+    int pi = c->prm.prec_inner;
+    size_t eb = elem_bytes(pi);
+    auto ints = [&](size_t n) { return (int *)A.take(n * sizeof(int)); };
+    c->g.loc_nbr = ints(T.loc_nbr.size());
+    c->g.blk_nbr = ints(T.blk_nbr.size());
+    c->g.plane_start = ints(T.plane_start.size());
+    c->g.slot_lex = ints(T.slot_lex.size());
+    c->g.blk_lex = ints(T.blk_lex.size());
+    c->U64 = (double2 *)A.take((size_t)V * 24 * 16);
+    c->F64 = (double2 *)A.take((size_t)V * 36 * 16);
+    c->Uin = A.take((size_t)V * 24 * eb);
+    c->Fin = A.take((size_t)V * 36 * eb);
+    double2 **d64[] = {&c->d_b, &c->d_x, &c->d_r, &c->d_rt, &c->d_p, &c->d_v, &c->d_s, &c->d_t, &c->d_ph, &c->d_sh, &c->d_tmp};
+    for (auto p : d64) *p = (double2 *)A.take(nv * 16);
+    void **din[] = {&c->i_r, &c->i_rt, &c->i_p, &c->i_v, &c->i_s, &c->i_t, &c->i_e, &c->i_ph, &c->i_sh, &c->i_rin, &c->i_tmp, &c->sap_r, &c->sap_x};
+    for (auto p : din) *p = A.take(nv * eb);
+    c->ssor_scratch = c->ssor_lds ? nullptr : (float2 *)A.take(nv * 8);
+    c->partials = (double2 *)A.take(RED_BLOCKS * 3 * sizeof(double2));
+    c->dev_res = (double2 *)A.take(8 * sizeof(double2));
+    c->dev_dev = (double *)A.take(((V + 255) / 256) * sizeof(double));
+}
+
+static int hipcheck(hipError_t e, const char *what) {
+    if (e == hipSuccess) return SAPQ_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return SAPQ_EHIP;
+}
+
+static int check_params(const sapq_params *p, std::string &why) {
+    if (!(p->kappa > 0) || !(p->omega > 0 && p->omega < 2)) { why = "kappa must be > 0 and 0 < omega < 2"; return SAPQ_EINVAL; }
+    if (p->n_ssor < 1 || p->n_sap < 1) { why = "n_ssor and n_sap must be >= 1"; return SAPQ_EINVAL; }
+    if (p->prec_inner != SAPQ_FP32 && p->prec_inner != SAPQ_FP16 && p->prec_inner != SAPQ_BF16) {
+        why = "prec_inner must be SAPQ_FP32, SAPQ_FP16 or SAPQ_BF16"; return SAPQ_EINVAL;
+    }
+    if (p->outer != SAPQ_OUTER_FBICGSTAB && p->outer != SAPQ_OUTER_DEFECT) { why = "bad outer kind"; return SAPQ_EINVAL; }
+    if (p->maxit_inner < 1 || p->maxit_outer < 1 || !(p->tol_inner > 0 && p->tol_inner < 1)) {
+        why = "maxit must be >= 1 and 0 < tol_inner < 1"; return SAPQ_EINVAL;
+    }
+    return SAPQ_OK;
+}
+
+static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTables &T, int max_lds) {
+    build_tables(geom, T);
+    c->geom = *geom;
+    c->prm = *prm;
+    c->V = (long)geom->L[0] * geom->L[1] * geom->L[2] * geom->L[3];
+    c->nvec = (size_t)c->V * 12;
+    c->max_plane = T.max_plane;
+    c->ssor_threads = std::min(512, ((T.max_plane + 63) / 64) * 64);
+    c->lds_bytes = (size_t)T.Vb * 12 * sizeof(float2);
+    c->ssor_lds = (long)c->lds_bytes <= (long)max_lds;
+    Arena A{nullptr, 0, 0};
+    carve(c, A, T);
+    return A.used + 256;
+}
+
+}  // namespace sapq
+
+using namespace sapq;
+
+struct sapq_ctx {
+    Ctx c;
+};
+
+extern "C" {
+
+const char *sapq_last_error(void) { return g_err.c_str(); }
+
+static int device_max_lds() {
+    int dev = 0, v = 65536;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    return v;
+}
+
+size_t sapq_arena_bytes(const sapq_geom *geom, const sapq_params *params) {
+    std::string why;
+    if (!geom || !params || check_geom(geom, why) != SAPQ_OK || check_params(params, why) != SAPQ_OK) return 0;
+    Ctx c{};
+    HostTables T;
+    // the LDS decision changes the arena only by the SSOR scratch; plan for the larger case
+    return plan(geom, params, &c, T, 0);
+}
+
+int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, size_t arena_bytes, void *stream,
+                sapq_ctx **out) {
+    std::string why;
+    if (!geom || !params || !out || !arena) { set_error("null argument"); return SAPQ_EINVAL; }
+    int rc = check_geom(geom, why);
+    if (rc == SAPQ_OK) rc = check_params(params, why);
+    if (rc != SAPQ_OK) { set_error(why); return rc; }
+    if (((uintptr_t)arena) & 255) { set_error("arena must be 256-byte aligned"); return SAPQ_EINVAL; }
+    sapq_ctx *h = new sapq_ctx();
+    Ctx *c = &h->c;
+    HostTables T;
+    size_t need = plan(geom, params, c, T, device_max_lds());
+    if (T.max_plane > 4096) { delete h; set_error("hyperplane too large"); return SAPQ_ESHAPE; }
+    if (T.nplanes > MAX_PLANES) { delete h; set_error("too many hyperplanes"); return SAPQ_ESHAPE; }
+    if (arena_bytes < need) {
+        delete h;
+        set_error("arena too small: need " + std::to_string(need) + " bytes");
+        return SAPQ_ENOMEM;
+    }
+    Arena A{(char *)arena, arena_bytes, 0};
+    carve(c, A, T);
+    c->stream = (hipStream_t)stream;
+    c->g.Vb = T.Vb;
+    c->g.NB = T.NB;
+    c->g.NBc = T.NB / 2;
+    c->g.V = c->V;
+    c->g.nplanes = T.nplanes;
+    for (int m = 0; m < 4; ++m) {
+        c->g.bc[m] = (float)geom->bc_sign[m];
+        c->g.B[m] = geom->block[m];
+        c->g.nbk[m] = T.nbk[m];
+    }
+    c->red_blocks = RED_BLOCKS;
+    c->have_U = c->have_F = false;
+    c->n_msap = c->n_d64 = 0;
+    rc = hipcheck(hipHostMalloc((void **)&c->host_res, 8 * sizeof(double2), hipHostMallocDefault), "hipHostMalloc");
+    if (rc) { delete h; return rc; }
+    struct { const void *dst; const std::vector<int> *src; } cp[] = {
+        {c->g.loc_nbr, &T.loc_nbr}, {c->g.blk_nbr, &T.blk_nbr}, {c->g.plane_start, &T.plane_start},
+        {c->g.slot_lex, &T.slot_lex}, {c->g.blk_lex, &T.blk_lex}};
+    for (auto &e : cp) {
+        rc = hipcheck(hipMemcpyAsync((void *)e.dst, e.src->data(), e.src->size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
+                      "hipMemcpyAsync(tables)");
+        if (rc) { hipHostFree(c->host_res); delete h; return rc; }
+    }
+    rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (rc) { hipHostFree(c->host_res); delete h; return rc; }
+    set_sap_lds_limits(c);
+    *out = h;
+    return SAPQ_OK;
+}
+
+int sapq_set_params(sapq_ctx *h, const sapq_params *p) {
+    std::string why;
+    if (!h || !p) { set_error("null argument"); return SAPQ_EINVAL; }
+    int rc = check_params(p, why);
+    if (rc) { set_error(why); return rc; }
+    if (p->prec_inner != h->c.prm.prec_inner) { set_error("prec_inner is fixed at creation"); return SAPQ_EINVAL; }
+    h->c.prm = *p;
+    return SAPQ_OK;
+}
+
+void sapq_destroy(sapq_ctx *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->c.stream);
+    for (hipEvent_t e : h->c.prof.ev) (void)hipEventDestroy(e);
+    (void)hipHostFree(h->c.host_res);
+    delete h;
+}
+
+int sapq_load_gauge(sapq_ctx *h, const double *U, double *max_dev) {
+    if (!h || !U) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    double dev = 0;
+    if (launch_pack_links(c, U, &dev)) return hipcheck(hipGetLastError(), "load_gauge");
+    int rc = hipcheck(hipGetLastError(), "k_pack_links");
+    if (rc) return rc;
+    if (max_dev) *max_dev = dev;
+    if (!(dev <= 1e-10)) {
+        char b[128];
+        snprintf(b, sizeof b, "links are not SU(3): max deviation %.3e", dev);
+        set_error(b);
+        c->have_U = false;
+        return SAPQ_ENOTSU3;
+    }
+    c->have_U = true;
+    return SAPQ_OK;
+}
+
+int sapq_load_clover_inv(sapq_ctx *h, const double *F) {
+    if (!h || !F) { set_error("null argument"); return SAPQ_EINVAL; }
+    launch_pack_clover(&h->c, F);
+    int rc = hipcheck(hipGetLastError(), "k_pack_clover");
+    if (rc) return rc;
+    h->c.have_F = true;
+    return SAPQ_OK;
+}
+
+static int ready(Ctx *c) {
+    if (!c->have_U || !c->have_F) { set_error("gauge field and clover field must be loaded first"); return SAPQ_ESTATE; }
+    return SAPQ_OK;
+}
+
+int sapq_dslash(sapq_ctx *h, double *out, const double *in, int prec) {
+    if (!h || !out || !in) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    if (prec != SAPQ_FP64 && prec != c->prm.prec_inner) { set_error("prec must be SAPQ_FP64 or the context's prec_inner"); return SAPQ_EINVAL; }
+    if (out == in) { set_error("in and out may not alias"); return SAPQ_EINVAL; }
+    int rc = ready(c);
+    if (rc) return rc;
+    void *a = prec == SAPQ_FP64 ? (void *)c->d_tmp : c->i_tmp;
+    void *b = prec == SAPQ_FP64 ? (void *)c->d_v : c->i_v;
+    launch_pack_spinor(c, prec, a, in, 1.0);
+    launch_dslash(c, prec, b, a);
+    launch_unpack_spinor(c, prec, out, b, 1.0);
+    return hipcheck(hipGetLastError(), "sapq_dslash");
+}
+
+int sapq_ssor(sapq_ctx *h, double *x, const double *v, int colour) {
+    if (!h || !x || !v || (colour != 0 && colour != 1)) { set_error("bad argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    int pi = c->prm.prec_inner;
+    launch_pack_spinor(c, pi, c->i_tmp, v, 1.0);
+    blas_zero(c, pi, c->i_v);
+    launch_ssor_only(c, colour, c->i_tmp, c->i_v);
+    launch_unpack_spinor(c, pi, x, c->i_v, 1.0);
+    return hipcheck(hipGetLastError(), "sapq_ssor");
+}
+
+// M_SAP on internal inner-precision vectors: y = M_SAP v; c->sap_r = v - D y
+static void msap(Ctx *c, const void *v, void *y) {
+    for (int j = 0; j < c->prm.n_sap; ++j) {
+        const void *src = j == 0 ? v : c->sap_r;
+        int t = prof_begin(c, SAPQ_K_PHASE_E);
+        launch_sap_phase(c, 0, j == 0, src, c->sap_r, c->sap_x, y);
+        prof_end(c, t);
+        t = prof_begin(c, SAPQ_K_PHASE_O);
+        launch_sap_phase(c, 1, j == 0, src, c->sap_r, c->sap_x, y);
+        prof_end(c, t);
+    }
+    int t = prof_begin(c, SAPQ_K_FACE);
+    launch_sap_face(c, 0, c->sap_r, c->sap_x);
+    prof_end(c, t);
+    c->n_msap++;
+}
+
+int sapq_dk(sapq_ctx *h, double *x, double *w, const double *v) {
+    if (!h || !x || !w || !v) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    int pi = c->prm.prec_inner;
+    launch_pack_spinor(c, pi, c->i_tmp, v, 1.0);
+    launch_sap_phase(c, 0, true, c->i_tmp, c->sap_r, c->sap_x, c->i_ph);
+    launch_sap_phase(c, 1, true, c->i_tmp, c->sap_r, c->sap_x, c->i_ph);
+    launch_sap_face(c, 0, c->sap_r, c->sap_x);
+    blas_xpay(c, pi, c->i_v, c->i_tmp, make_double2(-1, 0), c->sap_r);  // w = v - r
+    launch_unpack_spinor(c, pi, x, c->sap_x, 1.0);
+    launch_unpack_spinor(c, pi, w, c->i_v, 1.0);
+    return hipcheck(hipGetLastError(), "sapq_dk");
+}
+
+int sapq_sap_precondition(sapq_ctx *h, double *out, double *d_out, const double *in) {
+    if (!h || !out || !in) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    int pi = c->prm.prec_inner;
+    launch_pack_spinor(c, pi, c->i_tmp, in, 1.0);
+    msap(c, c->i_tmp, c->i_ph);
+    launch_unpack_spinor(c, pi, out, c->i_ph, 1.0);
+    if (d_out) {
+        blas_xpay(c, pi, c->i_v, c->i_tmp, make_double2(-1, 0), c->sap_r);
+        launch_unpack_spinor(c, pi, d_out, c->i_v, 1.0);
+    }
+    return hipcheck(hipGetLastError(), "sapq_sap_precondition");
+}
+
+}  // extern "C"
+
+namespace sapq {
+
+typedef std::complex<double> zc;
+static inline zc Z(double2 a) { return zc(a.x, a.y); }
+static inline double2 D2(zc a) { return make_double2(a.real(), a.imag()); }
+
+static double2 dot1(Ctx *c, int prec, const void *a, const void *b) {
+    const void *A[1] = {a}, *B[1] = {b};
+    double2 r;
+    blas_dots(c, prec, 1, A, B, &r);
+    return r;
+}
+
+// Inner BiCGStab (right-preconditioned by M_SAP) on inner-precision vectors, e from 0.
+static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
+    const int pi = c->prm.prec_inner;
+    blas_copy(c, pi, c->i_r, rhs);
+    blas_copy(c, pi, c->i_rt, rhs);
+    blas_zero(c, pi, c->i_p);
+    blas_zero(c, pi, c->i_v);
+    blas_zero(c, pi, e);
+    double2 res[3];
+    {
+        const void *A[2] = {c->i_rt, c->i_r}, *B[2] = {c->i_r, c->i_r};
+        blas_dots(c, pi, 2, A, B, res);
+    }
+    zc rho = Z(res[0]), rho_old = 1, alpha = 1, om = 1;
+    const double r0 = std::sqrt(res[1].x), tol = c->prm.tol_inner * r0;
+    int it = 0;
+    if (r0 == 0) { *iters = 0; return SAPQ_OK; }
+    while (it < c->prm.maxit_inner) {
+        if (std::abs(rho) == 0) break;
+        zc beta = (rho / rho_old) * (alpha / om);
+        blas_bicg_p(c, pi, c->i_p, c->i_r, D2(beta), D2(om), c->i_v);
+        msap(c, c->i_p, c->i_ph);                                     // p^ = M p
+        blas_xpay(c, pi, c->i_v, c->i_p, make_double2(-1, 0), c->sap_r);  // v = D p^ = p - r_N
+        zc rv = Z(dot1(c, pi, c->i_rt, c->i_v));
+        if (std::abs(rv) == 0) break;
+        alpha = rho / rv;
+        blas_xpay(c, pi, c->i_s, c->i_r, D2(-alpha), c->i_v);          // s = r - alpha v
+        double ss = dot1(c, pi, c->i_s, c->i_s).x;
+        ++it;
+        if (std::sqrt(ss) <= tol) {
+            blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, make_double2(0, 0), c->i_ph);
+            break;
+        }
+        msap(c, c->i_s, c->i_sh);                                     // s^ = M s
+        blas_xpay(c, pi, c->i_t, c->i_s, make_double2(-1, 0), c->sap_r);  // t = D s^
+        {
+            const void *A[2] = {c->i_t, c->i_t}, *B[2] = {c->i_s, c->i_t};
+            blas_dots(c, pi, 2, A, B, res);
+        }
+        if (res[1].x == 0) {
+            blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, make_double2(0, 0), c->i_ph);
+            break;
+        }
+        om = Z(res[0]) / res[1].x;
+        blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, D2(om), c->i_sh);    // e += alpha p^ + om s^
+        blas_xpay(c, pi, c->i_r, c->i_s, D2(-om), c->i_t);             // r = s - om t
+        {
+            const void *A[2] = {c->i_rt, c->i_r}, *B[2] = {c->i_r, c->i_r};
+            blas_dots(c, pi, 2, A, B, res);
+        }
+        rho_old = rho;
+        rho = Z(res[0]);
+        if (std::sqrt(res[1].x) <= tol) break;
+        if (std::abs(om) == 0) break;
+    }
+    *iters = it;
+    return SAPQ_OK;
+}
+
+// p^ = Inner(p) for an FP64 internal vector: normalise, convert, solve, convert back
+static int apply_inner(Ctx *c, double2 *out, const double2 *in, int *its) {
+    double nrm = std::sqrt(dot1(c, SAPQ_FP64, in, in).x);
+    if (nrm == 0) { blas_zero(c, SAPQ_FP64, out); *its = 0; return SAPQ_OK; }
+    // unit RMS per complex component keeps FP16 storage away from under- and overflow
+    double scale = std::sqrt((double)c->nvec) / nrm;
+    const int pi = c->prm.prec_inner;
+    blas_convert(c, pi, c->i_rin, SAPQ_FP64, in, scale);
+    int rc = inner_bicgstab(c, c->i_e, c->i_rin, its);
+    blas_convert(c, SAPQ_FP64, out, pi, c->i_e, 1.0 / scale);
+    return rc;
+}
+
+static void d64(Ctx *c, double2 *out, const double2 *in) {
+    int t = prof_begin(c, SAPQ_K_DSLASH64);
+    launch_dslash(c, SAPQ_FP64, out, in);
+    prof_end(c, t);
+    c->n_d64++;
+}
+
+static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
+    int outer = 0, inner = 0, restarts = 0, its = 0, conv = 0, nh = 0;
+    double hist[256];
+    const double bn = std::sqrt(dot1(c, SAPQ_FP64, c->d_b, c->d_b).x);
+    d64(c, c->d_tmp, c->d_x);
+    blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
+    double relres = bn > 0 ? std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn : 0.0;
+    if (relres <= tol) conv = 1;
+    const int maxit = c->prm.maxit_outer;
+    if (c->prm.outer == SAPQ_OUTER_DEFECT) {
+        while (!conv && outer < maxit) {
+            apply_inner(c, c->d_ph, c->d_r, &its);
+            inner += its;
+            blas_xpay(c, SAPQ_FP64, c->d_x, c->d_x, make_double2(1, 0), c->d_ph);
+            d64(c, c->d_tmp, c->d_x);
+            blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
+            ++outer;
+            relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
+            if (nh < 256) hist[nh++] = relres;
+            if (relres <= tol) conv = 1;
+        }
+    } else {
+        while (!conv && outer < maxit) {
+            blas_copy(c, SAPQ_FP64, c->d_rt, c->d_r);
+            blas_zero(c, SAPQ_FP64, c->d_p);
+            blas_zero(c, SAPQ_FP64, c->d_v);
+            zc rho_old = 1, alpha = 1, om = 1;
+            bool restart = false;
+            while (!restart && outer < maxit) {
+                zc rho = Z(dot1(c, SAPQ_FP64, c->d_rt, c->d_r));
+                zc beta = (rho / rho_old) * (alpha / om);
+                blas_bicg_p(c, SAPQ_FP64, c->d_p, c->d_r, D2(beta), D2(om), c->d_v);
+                apply_inner(c, c->d_ph, c->d_p, &its);                       // p^ = Inner(p)
+                inner += its;
+                d64(c, c->d_v, c->d_ph);                                     // v = D p^
+                zc rv = Z(dot1(c, SAPQ_FP64, c->d_rt, c->d_v));
+                ++outer;
+                if (std::abs(rv) == 0) { restart = true; }
+                else {
+                    alpha = rho / rv;
+                    blas_xpay(c, SAPQ_FP64, c->d_s, c->d_r, D2(-alpha), c->d_v);  // s = r - alpha v
+                    double sn = std::sqrt(dot1(c, SAPQ_FP64, c->d_s, c->d_s).x);
+                    if (sn <= tol * bn) {
+                        blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, make_double2(0, 0), c->d_ph);
+                        restart = true;
+                    } else {
+                        apply_inner(c, c->d_sh, c->d_s, &its);               // s^ = Inner(s)
+                        inner += its;
+                        d64(c, c->d_t, c->d_sh);                             // t = D s^
+                        double2 res[2];
+                        const void *A[2] = {c->d_t, c->d_t}, *B[2] = {c->d_s, c->d_t};
+                        blas_dots(c, SAPQ_FP64, 2, A, B, res);
+                        om = Z(res[0]) / res[1].x;
+                        blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, D2(om), c->d_sh);
+                        blas_xpay(c, SAPQ_FP64, c->d_r, c->d_s, D2(-om), c->d_t);
+                        rho_old = rho;
+                        double rn = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x);
+                        if (nh < 256) hist[nh++] = rn / bn;
+                        if (rn <= tol * bn || std::abs(om) == 0) restart = true;
+                    }
+                }
+                if (restart) {
+                    d64(c, c->d_tmp, c->d_x);                                // true residual
+                    blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
+                    relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
+                    if (relres <= tol) conv = 1;
+                    else ++restarts;
+                }
+            }
+        }
+        if (!conv) {
+            d64(c, c->d_tmp, c->d_x);
+            blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
+            relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
+        }
+    }
+    if (st) {
+        st->outer_its = outer;
+        st->inner_its = inner;
+        st->restarts = restarts;
+        st->true_relres = relres;
+        st->n_hist = nh;
+        for (int i = 0; i < nh; ++i) st->relres_hist[i] = hist[i];
+    }
+    return conv ? SAPQ_OK : SAPQ_ENOTCONV;
+}
+
+}  // namespace sapq
+
+extern "C" {
+
+int sapq_inner_solve(sapq_ctx *h, double *e, const double *r, int *iters) {
+    if (!h || !e || !r) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    const int pi = c->prm.prec_inner;
+    launch_pack_spinor(c, SAPQ_FP64, c->d_tmp, r, 1.0);
+    int its = 0;
+    rc = apply_inner(c, c->d_ph, c->d_tmp, &its);
+    launch_unpack_spinor(c, SAPQ_FP64, e, c->d_ph, 1.0);
+    (void)pi;
+    if (iters) *iters = its;
+    int hr = hipcheck(hipGetLastError(), "sapq_inner_solve");
+    return hr ? hr : rc;
+}
+
+int sapq_solve(sapq_ctx *h, double *x, const double *b, double tol, sapq_stats *st) {
+    if (!h || !x || !b || !(tol > 0)) { set_error("bad argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    auto t0 = std::chrono::steady_clock::now();
+    c->n_msap = c->n_d64 = 0;
+    c->prof.on = (c->prm.flags & SAPQ_FLAG_PROFILE) != 0;
+    c->prof.used = 0;
+    for (int k = 0; k < 8; ++k) { c->prof.ms[k] = 0; c->prof.n[k] = 0; }
+    launch_pack_spinor(c, SAPQ_FP64, c->d_b, b, 1.0);
+    if (c->prm.flags & SAPQ_FLAG_GUESS)
+        launch_pack_spinor(c, SAPQ_FP64, c->d_x, x, 1.0);
+    else
+        blas_zero(c, SAPQ_FP64, c->d_x);
+    rc = outer_solve(c, tol, st);
+    launch_unpack_spinor(c, SAPQ_FP64, x, c->d_x, 1.0);
+    int hr = hipcheck(hipStreamSynchronize(c->stream), "sapq_solve");
+    if (hr == SAPQ_OK) hr = hipcheck(hipGetLastError(), "sapq_solve");
+    prof_harvest(c);
+    c->prof.on = false;
+    if (st) {
+        for (int k = 0; k < 8; ++k) { st->kern_ms[k] = c->prof.ms[k]; st->kern_n[k] = c->prof.n[k]; }
+        st->n_msap = (int)c->n_msap;
+        st->n_dslash64 = (int)c->n_d64;
+        st->time_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (hr) return hr;
+    if (rc == SAPQ_ENOTCONV) set_error("solver did not reach the tolerance");
+    return rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,562 @@
+// HIP kernels of libsapq for gfx950: layout conversion, the clover-Wilson operator,
+// the SAP phase kernels (gather, SSOR in hyperplane order, block hop) and BLAS-1.
+#include "sapq_impl.h"
+
+namespace sapq {
+
+// ================================================================ site index helpers
+// lexicographic site index of internal site (ib, s)
+__device__ __forceinline__ long lex_site(const GeomDev &g, int ib, int s) {
+    int bl = g.blk_lex[ib], l = g.slot_lex[s];
+    long n = 0, stride = 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        int bc = bl % g.nbk[m];
+        bl /= g.nbk[m];
+        int c = l % g.B[m];
+        l /= g.B[m];
+        n += (long)(bc * g.B[m] + c) * stride;
+        stride *= (long)g.B[m] * g.nbk[m];
+    }
+    return n;
+}
+
+// ================================================================ layout conversion
+template <int P>
+__global__ void k_pack_spinor(GeomDev g, typename Prec<P>::S2 *dst, const double2 *src, double scale) {
+    using C = typename Prec<P>::C;
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    const double2 *p = src + lex_site(g, ib, s) * 12;
+    typename Prec<P>::S2 *q = dst + (size_t)ib * 12 * g.Vb + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        double2 v = p[c];
+        st(q + (size_t)c * g.Vb, cx<C>{C(v.x * scale), C(v.y * scale)});
+    }
+}
+
+template <int P>
+__global__ void k_unpack_spinor(GeomDev g, double2 *dst, const typename Prec<P>::S2 *src, double scale) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    double2 *p = dst + lex_site(g, ib, s) * 12;
+    const typename Prec<P>::S2 *q = src + (size_t)ib * 12 * g.Vb + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        auto v = ld(q + (size_t)c * g.Vb);
+        p[c] = make_double2((double)v.r * scale, (double)v.i * scale);
+    }
+}
+
+// links: keep rows 0 and 1; record max(|U^+U - 1|, |det U - 1|) per workgroup
+template <int P>
+__global__ void k_pack_links(GeomDev g, const double2 *src, double2 *U64, typename Prec<P>::S2 *Uin, double *dev) {
+    using C = typename Prec<P>::C;
+    __shared__ double red[256];
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double worst = 0.0;
+    if (i < g.V) {
+        int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        const double2 *p = src + lex_site(g, ib, s) * 36;
+        for (int mu = 0; mu < 4; ++mu) {
+            cx<double> u[9];
+            for (int e = 0; e < 9; ++e) u[e] = {p[9 * mu + e].x, p[9 * mu + e].y};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    cx<double> t = cmulc(u[a], u[b]) + cmulc(u[3 + a], u[3 + b]) + cmulc(u[6 + a], u[6 + b]);
+                    double re = t.r - (a == b ? 1.0 : 0.0);
+                    worst = fmax(worst, sqrt(re * re + t.i * t.i));
+                }
+            cx<double> det = cmul(u[0], cmul(u[4], u[8]) - cmul(u[5], u[7])) -
+                             cmul(u[1], cmul(u[3], u[8]) - cmul(u[5], u[6])) +
+                             cmul(u[2], cmul(u[3], u[7]) - cmul(u[4], u[6]));
+            worst = fmax(worst, sqrt((det.r - 1) * (det.r - 1) + det.i * det.i));
+            size_t base = ((size_t)ib * 4 + mu) * 6 * g.Vb + s;
+            for (int e = 0; e < 6; ++e) {
+                U64[base + (size_t)e * g.Vb] = make_double2(u[e].r, u[e].i);
+                st(Uin + base + (size_t)e * g.Vb, cx<C>{C(u[e].r), C(u[e].i)});
+            }
+        }
+    }
+    red[threadIdx.x] = worst;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dev[blockIdx.x] = red[0];
+}
+
+// clover: packed hermitian chiral blocks (diagonal pairs, then the strict lower triangle)
+template <int P>
+__global__ void k_pack_clover(GeomDev g, const double2 *src, double2 *F64, typename Prec<P>::S2 *Fin) {
+    using C = typename Prec<P>::C;
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    const double2 *p = src + lex_site(g, ib, s) * 72;
+    for (int k = 0; k < 2; ++k) {
+        const double2 *m = p + 36 * k;
+        size_t base = ((size_t)ib * 2 + k) * 18 * g.Vb + s;
+        cx<double> e[18];
+        for (int d = 0; d < 3; ++d) e[d] = {m[7 * (2 * d)].x, m[7 * (2 * d + 1)].x};
+        int q = 3;
+        for (int r = 1; r < 6; ++r)
+            for (int c = 0; c < r; ++c) e[q++] = {m[6 * r + c].x, m[6 * r + c].y};
+        for (int t = 0; t < 18; ++t) {
+            F64[base + (size_t)t * g.Vb] = make_double2(e[t].r, e[t].i);
+            st(Fin + base + (size_t)t * g.Vb, cx<C>{C(e[t].r), C(e[t].i)});
+        }
+    }
+}
+
+// ================================================================ hopping building block
+// Spinor sources: a field in storage precision, or the float2 SSOR iterate of one block.
+template <typename S2, typename C> struct FieldSrc {
+    const S2 *f;
+    __device__ __forceinline__ void get(cx<C> psi[12], const GeomDev &g, int ib, int s) const { load_spinor(psi, f, g, ib, s); }
+};
+struct BlockSrc {  // [12][Vb] float2 of the current block (LDS or global scratch)
+    const float2 *x;
+    __device__ __forceinline__ void get(cx<float> psi[12], const GeomDev &g, int, int s) const {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            float2 v = x[c * g.Vb + s];
+            psi[c] = {v.x, v.y};
+        }
+    }
+};
+
+// MODE 0: all eight neighbours; 1: neighbours inside the block; 2: neighbours outside it
+template <int MODE, int MU, typename S2, typename C, typename Src>
+__device__ __forceinline__ void hop_dir(cx<C> acc[12], const GeomDev &g, int ib, int s, const S2 *U, const Src &src) {
+    cx<C> psi[12], u[9];
+    Nbr f = neighbour(g, ib, s, 2 * MU);
+    if (MODE == 0 || (MODE == 1) == f.inside) {
+        src.get(psi, g, f.ib, f.s);
+        load_link(u, U, g, ib, s, MU);
+        hop_accum<MU, +1>(acc, psi, u, false, C(f.phase));
+    }
+    Nbr b = neighbour(g, ib, s, 2 * MU + 1);
+    if (MODE == 0 || (MODE == 1) == b.inside) {
+        src.get(psi, g, b.ib, b.s);
+        load_link(u, U, g, b.ib, b.s, MU);
+        hop_accum<MU, -1>(acc, psi, u, true, C(b.phase));
+    }
+}
+
+template <int MODE, typename S2, typename C, typename Src>
+__device__ __forceinline__ void hop_site(cx<C> acc[12], const GeomDev &g, int ib, int s, const S2 *U, const Src &src) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cxz<C>();
+    hop_dir<MODE, 0>(acc, g, ib, s, U, src);
+    hop_dir<MODE, 1>(acc, g, ib, s, U, src);
+    hop_dir<MODE, 2>(acc, g, ib, s, U, src);
+    hop_dir<MODE, 3>(acc, g, ib, s, U, src);
+}
+
+// ================================================================ full operator D
+// out = in - kappa F H in, one thread per site
+template <int P>
+__global__ void __launch_bounds__(256) k_dslash(GeomDev g, typename Prec<P>::S2 *__restrict__ out,
+                                               const typename Prec<P>::S2 *__restrict__ in,
+                                               const typename Prec<P>::S2 *__restrict__ U,
+                                               const typename Prec<P>::S2 *__restrict__ F, double kappa) {
+    using S2 = typename Prec<P>::S2;
+    using C = typename Prec<P>::C;
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    cx<C> h[12], fh[12], psi[12];
+    hop_site<0>(h, g, ib, s, U, FieldSrc<S2, C>{in});
+    clover_mul(fh, h, F, g, ib, s);
+    load_spinor(psi, in, g, ib, s);
+    const C k = C(kappa);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = psi[c] - k * fh[c];
+    store_spinor(out, g, ib, s, psi);
+}
+
+// ================================================================ SAP phase kernel
+// One workgroup per block of colour `colour` (Algorithm 1 fused with the M_SAP update):
+//   v_c  = r_c + kappa F sum_{hops leaving the block} H x_other   (= r_c - D_{c,other} x_other)
+//   x_c  = SSOR block inverse of v_c (n_ssor symmetric sweeps from 0, hyperplane schedule)
+//   y_c  = (first ? 0 : y_c) + x_c,   r_c = v_c - D_cc x_c,   x_c stored for the other colour.
+// mode 1 (ssor only): v_c = rsrc, write x_c and nothing else.
+struct SapArgs {
+    int colour, gather, first, ssor_only, n_ssor;
+    float kappa, omega;
+};
+
+template <int P, bool XLDS>
+__global__ void __launch_bounds__(512) k_sap_phase(GeomDev g, SapArgs a, const typename Prec<P>::S2 *rsrc,
+                                                    typename Prec<P>::S2 *r, typename Prec<P>::S2 *x,
+                                                    typename Prec<P>::S2 *y, const typename Prec<P>::S2 *__restrict__ U,
+                                                    const typename Prec<P>::S2 *__restrict__ F, float2 *scratch) {
+    using S2 = typename Prec<P>::S2;
+    using C = float;
+    extern __shared__ float2 lds[];
+    const int ib = a.colour * g.NBc + blockIdx.x;
+    float2 *xs = XLDS ? lds : scratch + (size_t)ib * 12 * g.Vb;
+    const C kappa = a.kappa, omega = a.omega;
+    // vb: where v_c lives during the sweeps (r, or rsrc in ssor-only mode)
+    const S2 *vb = a.ssor_only ? rsrc : r;
+
+    // 1. gather v_c, zero the iterate
+    for (int s = threadIdx.x; s < g.Vb; s += blockDim.x) {
+        if (!a.ssor_only) {
+            cx<C> v[12];
+            load_spinor(v, rsrc, g, ib, s);
+            if (a.gather) {
+                cx<C> h[12], fh[12];
+                hop_site<2>(h, g, ib, s, U, FieldSrc<S2, C>{x});
+                clover_mul(fh, h, F, g, ib, s);
+#pragma unroll
+                for (int c = 0; c < 12; ++c) v[c] = v[c] + kappa * fh[c];
+            }
+            store_spinor(r, g, ib, s, v);
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) xs[c * g.Vb + s] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+
+    // 2. SSOR sweeps: x_n <- (1-omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m)
+    const BlockSrc bs{xs};
+    for (int sw = 0; sw < a.n_ssor; ++sw) {
+        for (int dir = 0; dir < 2; ++dir) {
+            for (int pi = 0; pi < g.nplanes; ++pi) {
+                const int p = dir == 0 ? pi : g.nplanes - 1 - pi;
+                const int s0 = g.plane_start[p], s1 = g.plane_start[p + 1];
+                for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+                    cx<C> h[12], fh[12], v[12];
+                    hop_site<1>(h, g, ib, s, U, bs);
+                    clover_mul(fh, h, F, g, ib, s);
+                    load_spinor(v, vb, g, ib, s);
+#pragma unroll
+                    for (int c = 0; c < 12; ++c) {
+                        float2 o = xs[c * g.Vb + s];
+                        cx<C> nx = v[c] + kappa * fh[c];
+                        xs[c * g.Vb + s] = make_float2((1.f - omega) * o.x + omega * nx.r, (1.f - omega) * o.y + omega * nx.i);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // 3. outputs
+    for (int s = threadIdx.x; s < g.Vb; s += blockDim.x) {
+        cx<C> xv[12];
+        bs.get(xv, g, ib, s);
+        store_spinor(x, g, ib, s, xv);
+        if (a.ssor_only) continue;
+        cx<C> yv[12];
+        if (a.first) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) yv[c] = xv[c];
+        } else {
+            load_spinor(yv, y, g, ib, s);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) yv[c] = yv[c] + xv[c];
+        }
+        store_spinor(y, g, ib, s, yv);
+        cx<C> h[12], fh[12], v[12];
+        hop_site<1>(h, g, ib, s, U, bs);
+        clover_mul(fh, h, F, g, ib, s);
+        load_spinor(v, r, g, ib, s);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = v[c] - xv[c] + kappa * fh[c];
+        store_spinor(r, g, ib, s, v);
+    }
+}
+
+// r_c += kappa F sum_{hops leaving the block} H x   (r_c -= D_{c,other} x_other), one thread per site
+template <int P>
+__global__ void __launch_bounds__(256) k_sap_face(GeomDev g, int colour, float kappa, typename Prec<P>::S2 *r,
+                                                 const typename Prec<P>::S2 *x, const typename Prec<P>::S2 *__restrict__ U,
+                                                 const typename Prec<P>::S2 *__restrict__ F) {
+    using S2 = typename Prec<P>::S2;
+    using C = float;
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long nc = (long)g.NBc * g.Vb;
+    if (i >= nc) return;
+    int ib = colour * g.NBc + (int)(i / g.Vb), s = (int)(i % g.Vb);
+    cx<C> h[12], fh[12], v[12];
+    hop_site<2>(h, g, ib, s, U, FieldSrc<S2, C>{x});
+    clover_mul(fh, h, F, g, ib, s);
+    load_spinor(v, r, g, ib, s);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = v[c] + kappa * fh[c];
+    store_spinor(r, g, ib, s, v);
+}
+
+// ================================================================ BLAS-1
+constexpr int RED_THREADS = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// partial sums of <a_k, b_k> (k < nd) per workgroup, in double
+template <int P>
+__global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, int nd, const typename Prec<P>::S2 *a0,
+                                                     const typename Prec<P>::S2 *b0, const typename Prec<P>::S2 *a1,
+                                                     const typename Prec<P>::S2 *b1, const typename Prec<P>::S2 *a2,
+                                                     const typename Prec<P>::S2 *b2, double2 *partials) {
+    __shared__ double sm[RED_THREADS / 64][6];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        {
+            auto x = ld(a0 + i), y = ld(b0 + i);
+            acc[0] += (double)x.r * y.r + (double)x.i * y.i;
+            acc[1] += (double)x.r * y.i - (double)x.i * y.r;
+        }
+        if (nd > 1) {
+            auto x = ld(a1 + i), y = ld(b1 + i);
+            acc[2] += (double)x.r * y.r + (double)x.i * y.i;
+            acc[3] += (double)x.r * y.i - (double)x.i * y.r;
+        }
+        if (nd > 2) {
+            auto x = ld(a2 + i), y = ld(b2 + i);
+            acc[4] += (double)x.r * y.r + (double)x.i * y.i;
+            acc[5] += (double)x.r * y.i - (double)x.i * y.r;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) sm[w][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0;
+        for (int j = 0; j < RED_THREADS / 64; ++j) v += sm[j][threadIdx.x];
+        double *pp = reinterpret_cast<double *>(partials + (size_t)blockIdx.x * 3);
+        pp[threadIdx.x] = v;
+    }
+}
+
+// final sum of the partials, fixed order
+__global__ void __launch_bounds__(64) k_dots_final(int nblocks, const double2 *partials, double2 *out) {
+    const int k = threadIdx.x;  // 0..5
+    if (k >= 6) return;
+    double v = 0;
+    const double *pp = reinterpret_cast<const double *>(partials);
+    for (int b = 0; b < nblocks; ++b) v += pp[(size_t)b * 6 + k];
+    reinterpret_cast<double *>(out)[k] = v;
+}
+
+template <int P>
+__global__ void k_xpay(size_t n, typename Prec<P>::S2 *z, const typename Prec<P>::S2 *x, double ar, double ai,
+                       const typename Prec<P>::S2 *y) {
+    using C = typename Prec<P>::C;
+    const cx<C> a{C(ar), C(ai)};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(z + i, ld(x + i) + cmul(a, ld(y + i)));
+}
+
+template <int P>
+__global__ void k_bicg_p(size_t n, typename Prec<P>::S2 *p, const typename Prec<P>::S2 *r, double br, double bi,
+                         double omr, double omi, const typename Prec<P>::S2 *v) {
+    using C = typename Prec<P>::C;
+    const cx<C> beta{C(br), C(bi)}, om{C(omr), C(omi)};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(p + i, ld(r + i) + cmul(beta, ld(p + i) - cmul(om, ld(v + i))));
+}
+
+template <int P>
+__global__ void k_axpbypz(size_t n, typename Prec<P>::S2 *e, double ar, double ai, const typename Prec<P>::S2 *ph,
+                          double br, double bi, const typename Prec<P>::S2 *sh) {
+    using C = typename Prec<P>::C;
+    const cx<C> a{C(ar), C(ai)}, b{C(br), C(bi)};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(e + i, ld(e + i) + cmul(a, ld(ph + i)) + cmul(b, ld(sh + i)));
+}
+
+template <int PD, int PS>
+__global__ void k_convert(size_t n, typename Prec<PD>::S2 *d, const typename Prec<PS>::S2 *s, double scale) {
+    using CD = typename Prec<PD>::C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        auto v = ld(s + i);
+        st(d + i, cx<CD>{CD((double)v.r * scale), CD((double)v.i * scale)});
+    }
+}
+
+template <int P>
+__global__ void k_zero(size_t n, typename Prec<P>::S2 *d) {
+    using C = typename Prec<P>::C;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(d + i, cxz<C>());
+}
+
+// ================================================================ launchers
+#define PREC_SWITCH(prec, BODY)                                   \
+    switch (prec) {                                               \
+    case SAPQ_FP64: { constexpr int P_ = SAPQ_FP64; BODY; } break; \
+    case SAPQ_FP32: { constexpr int P_ = SAPQ_FP32; BODY; } break; \
+    case SAPQ_FP16: { constexpr int P_ = SAPQ_FP16; BODY; } break; \
+    case SAPQ_BF16: { constexpr int P_ = SAPQ_BF16; BODY; } break; \
+    default: break;                                               \
+    }
+
+#define INNER_SWITCH(prec, BODY)                                  \
+    switch (prec) {                                               \
+    case SAPQ_FP32: { constexpr int P_ = SAPQ_FP32; BODY; } break; \
+    case SAPQ_FP16: { constexpr int P_ = SAPQ_FP16; BODY; } break; \
+    case SAPQ_BF16: { constexpr int P_ = SAPQ_BF16; BODY; } break; \
+    default: break;                                               \
+    }
+
+static inline unsigned grid_for(long n, int t) { return (unsigned)((n + t - 1) / t); }
+static constexpr unsigned BLAS_GRID = 1024;
+
+void launch_pack_spinor(Ctx *c, int prec, void *dst, const double *src, double scale) {
+    PREC_SWITCH(prec, (k_pack_spinor<P_><<<grid_for(c->V, 256), 256, 0, c->stream>>>(
+                          c->g, (typename Prec<P_>::S2 *)dst, (const double2 *)src, scale)));
+}
+
+void launch_unpack_spinor(Ctx *c, int prec, double *dst, const void *src, double scale) {
+    PREC_SWITCH(prec, (k_unpack_spinor<P_><<<grid_for(c->V, 256), 256, 0, c->stream>>>(
+                          c->g, (double2 *)dst, (const typename Prec<P_>::S2 *)src, scale)));
+}
+
+int launch_pack_links(Ctx *c, const double *U, double *max_dev) {
+    unsigned nb = grid_for(c->V, 256);
+    INNER_SWITCH(c->prm.prec_inner, (k_pack_links<P_><<<nb, 256, 0, c->stream>>>(
+                                        c->g, (const double2 *)U, c->U64, (typename Prec<P_>::S2 *)c->Uin, c->dev_dev)));
+    double *h = (double *)malloc(sizeof(double) * nb);
+    hipError_t e = hipMemcpyAsync(h, c->dev_dev, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    double w = 0;
+    for (unsigned i = 0; i < nb; ++i) w = fmax(w, h[i]);
+    free(h);
+    *max_dev = w;
+    return e == hipSuccess ? 0 : -1;
+}
+
+void launch_pack_clover(Ctx *c, const double *F) {
+    INNER_SWITCH(c->prm.prec_inner, (k_pack_clover<P_><<<grid_for(c->V, 256), 256, 0, c->stream>>>(
+                                         c->g, (const double2 *)F, c->F64, (typename Prec<P_>::S2 *)c->Fin)));
+}
+
+void launch_dslash(Ctx *c, int prec, void *out, const void *in) {
+    if (prec == SAPQ_FP64) {
+        k_dslash<SAPQ_FP64><<<grid_for(c->V, 256), 256, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in,
+                                                                         c->U64, c->F64, c->prm.kappa);
+        return;
+    }
+    INNER_SWITCH(prec, (k_dslash<P_><<<grid_for(c->V, 256), 256, 0, c->stream>>>(
+                           c->g, (typename Prec<P_>::S2 *)out, (const typename Prec<P_>::S2 *)in,
+                           (const typename Prec<P_>::S2 *)c->Uin, (const typename Prec<P_>::S2 *)c->Fin, c->prm.kappa)));
+}
+
+template <int P>
+static void sap_phase_t(Ctx *c, const SapArgs &a, const void *rsrc, void *r, void *x, void *y) {
+    using S2 = typename Prec<P>::S2;
+    dim3 grid(c->g.NBc), block(c->ssor_threads);
+    if (c->ssor_lds)
+        k_sap_phase<P, true><<<grid, block, c->lds_bytes, c->stream>>>(
+            c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin, c->ssor_scratch);
+    else
+        k_sap_phase<P, false><<<grid, block, 0, c->stream>>>(
+            c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin, c->ssor_scratch);
+}
+
+void set_sap_lds_limits(Ctx *c) {
+    if (!c->ssor_lds || c->lds_bytes <= 65536) return;
+    hipFuncSetAttribute((const void *)k_sap_phase<SAPQ_FP32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
+    hipFuncSetAttribute((const void *)k_sap_phase<SAPQ_FP16, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
+    hipFuncSetAttribute((const void *)k_sap_phase<SAPQ_BF16, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
+}
+
+void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y) {
+    SapArgs a;
+    a.colour = colour;
+    a.gather = (colour == 1 || !first) ? 1 : 0;
+    a.first = first ? 1 : 0;
+    a.ssor_only = 0;
+    a.n_ssor = c->prm.n_ssor;
+    a.kappa = (float)c->prm.kappa;
+    a.omega = (float)c->prm.omega;
+    INNER_SWITCH(c->prm.prec_inner, sap_phase_t<P_>(c, a, rsrc, r, x, y));
+}
+
+void launch_ssor_only(Ctx *c, int colour, const void *v, void *x) {
+    SapArgs a;
+    a.colour = colour;
+    a.gather = 0;
+    a.first = 1;
+    a.ssor_only = 1;
+    a.n_ssor = c->prm.n_ssor;
+    a.kappa = (float)c->prm.kappa;
+    a.omega = (float)c->prm.omega;
+    INNER_SWITCH(c->prm.prec_inner, sap_phase_t<P_>(c, a, v, nullptr, x, nullptr));
+}
+
+void launch_sap_face(Ctx *c, int colour, void *r, const void *x) {
+    long nc = (long)c->g.NBc * c->g.Vb;
+    INNER_SWITCH(c->prm.prec_inner, (k_sap_face<P_><<<grid_for(nc, 256), 256, 0, c->stream>>>(
+                                         c->g, colour, (float)c->prm.kappa, (typename Prec<P_>::S2 *)r,
+                                         (const typename Prec<P_>::S2 *)x, (const typename Prec<P_>::S2 *)c->Uin,
+                                         (const typename Prec<P_>::S2 *)c->Fin)));
+}
+
+void blas_dots(Ctx *c, int prec, int nd, const void *const *a, const void *const *b, double2 *host_out) {
+    PREC_SWITCH(prec, ({
+                    using S2 = typename Prec<P_>::S2;
+                    k_dots<P_><<<c->red_blocks, RED_THREADS, 0, c->stream>>>(
+                        c->nvec, nd, (const S2 *)a[0], (const S2 *)b[0], (const S2 *)(nd > 1 ? a[1] : a[0]),
+                        (const S2 *)(nd > 1 ? b[1] : b[0]), (const S2 *)(nd > 2 ? a[2] : a[0]),
+                        (const S2 *)(nd > 2 ? b[2] : b[0]), c->partials);
+                }));
+    k_dots_final<<<1, 64, 0, c->stream>>>(c->red_blocks, c->partials, c->dev_res);
+    (void)hipMemcpyAsync(c->host_res, c->dev_res, sizeof(double2) * 3, hipMemcpyDeviceToHost, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < nd; ++k) host_out[k] = c->host_res[k];
+    prof_harvest(c);
+}
+
+void blas_copy(Ctx *c, int prec, void *dst, const void *src) {
+    hipMemcpyAsync(dst, src, c->nvec * elem_bytes(prec), hipMemcpyDeviceToDevice, c->stream);
+}
+
+void blas_zero(Ctx *c, int prec, void *dst) {
+    PREC_SWITCH(prec, (k_zero<P_><<<BLAS_GRID, 256, 0, c->stream>>>(c->nvec, (typename Prec<P_>::S2 *)dst)));
+}
+
+void blas_xpay(Ctx *c, int prec, void *z, const void *x, double2 a, const void *y) {
+    PREC_SWITCH(prec, (k_xpay<P_><<<BLAS_GRID, 256, 0, c->stream>>>(c->nvec, (typename Prec<P_>::S2 *)z,
+                                                                      (const typename Prec<P_>::S2 *)x, a.x, a.y,
+                                                                      (const typename Prec<P_>::S2 *)y)));
+}
+
+void blas_bicg_p(Ctx *c, int prec, void *p, const void *r, double2 beta, double2 om, const void *v) {
+    PREC_SWITCH(prec, (k_bicg_p<P_><<<BLAS_GRID, 256, 0, c->stream>>>(c->nvec, (typename Prec<P_>::S2 *)p,
+                                                                        (const typename Prec<P_>::S2 *)r, beta.x, beta.y,
+                                                                        om.x, om.y, (const typename Prec<P_>::S2 *)v)));
+}
+
+void blas_axpbypz(Ctx *c, int prec, void *e, double2 a, const void *ph, double2 b, const void *sh) {
+    PREC_SWITCH(prec, (k_axpbypz<P_><<<BLAS_GRID, 256, 0, c->stream>>>(c->nvec, (typename Prec<P_>::S2 *)e, a.x, a.y,
+                                                                         (const typename Prec<P_>::S2 *)ph, b.x, b.y,
+                                                                         (const typename Prec<P_>::S2 *)sh)));
+}
+
+void blas_convert(Ctx *c, int pd, void *dst, int ps, const void *src, double scale) {
+    if (pd == SAPQ_FP64) {
+        INNER_SWITCH(ps, (k_convert<SAPQ_FP64, P_><<<BLAS_GRID, 256, 0, c->stream>>>(
+                             c->nvec, (double2 *)dst, (const typename Prec<P_>::S2 *)src, scale)));
+    } else if (ps == SAPQ_FP64) {
+        INNER_SWITCH(pd, (k_convert<P_, SAPQ_FP64><<<BLAS_GRID, 256, 0, c->stream>>>(
+                             c->nvec, (typename Prec<P_>::S2 *)dst, (const double2 *)src, scale)));
+    }
+}
+
+}  // namespace sapq

@@ -1,0 +1,285 @@
+// Internal declarations of libsapq: context, device geometry tables, storage
+// types and the per-site device building blocks shared by the kernels.
+//
+// Internal layouts (all structure-of-arrays so that a wavefront touches
+// consecutive addresses):
+//   site      (ib, s): block ib (E blocks first, then O blocks) and slot s inside
+//             the block; slots are sorted by hyperplane h = sum_mu (x_mu mod S_mu),
+//             so every hyperplane is a contiguous slot range.
+//   spinor    [ib][12][Vb]       complex, component 3*alpha + a
+//   links     [ib][4][6][Vb]     rows 0 and 1 of U_mu(n) (row 2 = conj(row0 x row1))
+//   clover    [ib][2][18][Vb]    per chiral block: 3 complex slots holding the 6 real
+//                                diagonal entries pairwise, then the 15 entries below
+//                                the diagonal row by row; F is hermitian
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sapq.h"
+
+namespace sapq {
+
+constexpr int WRAP_BIT = 1 << 30;  // in blk_nbr: the hop crosses the lattice boundary
+constexpr int BLK_MASK = WRAP_BIT - 1;
+constexpr int MAX_PLANES = 64;
+
+// ---------------------------------------------------------------- device geometry
+struct GeomDev {
+    int Vb;           // sites per block
+    int NB;           // blocks
+    int NBc;          // blocks per colour
+    long V;           // sites
+    int nplanes;      // hyperplanes per block
+    float bc[4];      // boundary sign per direction
+    const int *loc_nbr;     // [8][Vb]: >= 0 slot inside the block, else -1 - slot in the next block
+    const int *blk_nbr;     // [8][NB]: neighbouring block id | WRAP_BIT
+    const int *plane_start; // [nplanes + 1]
+    const int *slot_lex;    // [Vb] block-local lexicographic index of each slot
+    const int *blk_lex;     // [NB] lexicographic block index of each internal block id
+    int B[4];
+    int nbk[4];             // blocks per direction
+};
+
+// ---------------------------------------------------------------- storage precisions
+template <int P> struct Prec;
+template <> struct Prec<SAPQ_FP64> { using S2 = double2; using C = double; };
+template <> struct Prec<SAPQ_FP32> { using S2 = float2; using C = float; };
+template <> struct Prec<SAPQ_FP16> { using S2 = __half2; using C = float; };
+template <> struct Prec<SAPQ_BF16> { using S2 = __hip_bfloat162; using C = float; };
+
+template <typename T> struct cx { T r, i; };
+
+template <typename T> __device__ __forceinline__ cx<T> cxz() { return {T(0), T(0)}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
+    return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+template <typename T> __device__ __forceinline__ cx<T> conjx(cx<T> a) { return {a.r, -a.i}; }
+template <typename T> __device__ __forceinline__ cx<T> itimes(cx<T> a) { return {-a.i, a.r}; }
+
+// storage <-> compute
+__device__ __forceinline__ cx<double> ld(const double2 *p) { double2 v = *p; return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> ld(const float2 *p) { float2 v = *p; return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> ld(const __half2 *p) { float2 v = __half22float2(*p); return {v.x, v.y}; }
+__device__ __forceinline__ cx<float> ld(const __hip_bfloat162 *p) {
+    __hip_bfloat162 h = *p;
+    return {__bfloat162float(h.x), __bfloat162float(h.y)};
+}
+__device__ __forceinline__ void st(double2 *p, cx<double> v) { *p = make_double2(v.r, v.i); }
+__device__ __forceinline__ void st(float2 *p, cx<float> v) { *p = make_float2(v.r, v.i); }
+__device__ __forceinline__ void st(__half2 *p, cx<float> v) { *p = __floats2half2_rn(v.r, v.i); }
+__device__ __forceinline__ void st(__hip_bfloat162 *p, cx<float> v) {
+    __hip_bfloat162 h;
+    h.x = __float2bfloat16(v.r);
+    h.y = __float2bfloat16(v.i);
+    *p = h;
+}
+
+// ---------------------------------------------------------------- neighbours
+// Neighbour of (ib, s) in direction d = 2*mu + (0 forward, 1 backward).
+struct Nbr { int ib, s; float phase; bool inside; };
+
+__device__ __forceinline__ Nbr neighbour(const GeomDev &g, int ib, int s, int d) {
+    int t = g.loc_nbr[d * g.Vb + s];
+    Nbr n;
+    if (t >= 0) {
+        n.ib = ib; n.s = t; n.phase = 1.f; n.inside = true;
+    } else {
+        int b = g.blk_nbr[d * g.NB + ib];
+        n.ib = b & BLK_MASK; n.s = -1 - t; n.inside = false;
+        n.phase = (b & WRAP_BIT) ? g.bc[d >> 1] : 1.f;
+    }
+    return n;
+}
+
+// ---------------------------------------------------------------- spinor / link access
+template <typename S2>
+__device__ __forceinline__ const S2 *spin_at(const S2 *f, const GeomDev &g, int ib, int s) {
+    return f + (size_t)ib * 12 * g.Vb + s;
+}
+template <typename S2, typename C>
+__device__ __forceinline__ void load_spinor(cx<C> psi[12], const S2 *f, const GeomDev &g, int ib, int s) {
+    const S2 *p = spin_at(f, g, ib, s);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = ld(p + (size_t)c * g.Vb);
+}
+template <typename S2, typename C>
+__device__ __forceinline__ void store_spinor(S2 *f, const GeomDev &g, int ib, int s, const cx<C> psi[12]) {
+    S2 *p = f + (size_t)ib * 12 * g.Vb + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st(p + (size_t)c * g.Vb, psi[c]);
+}
+
+// link U_mu at (ib, s) rebuilt to 3x3 (row-major u[3*a+b])
+template <typename S2, typename C>
+__device__ __forceinline__ void load_link(cx<C> u[9], const S2 *U, const GeomDev &g, int ib, int s, int mu) {
+    const S2 *p = U + ((size_t)ib * 4 + mu) * 6 * g.Vb + s;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u[e] = ld(p + (size_t)e * g.Vb);
+    // row2 = conj(row0 x row1)
+    u[6] = conjx(cmul(u[1], u[5]) - cmul(u[2], u[4]));
+    u[7] = conjx(cmul(u[2], u[3]) - cmul(u[0], u[5]));
+    u[8] = conjx(cmul(u[0], u[4]) - cmul(u[1], u[3]));
+}
+
+// out = U h (dag = false) or U^+ h (dag = true) for a colour 3-vector
+template <typename C>
+__device__ __forceinline__ void su3_mul(cx<C> out[3], const cx<C> u[9], const cx<C> h[3], bool dag) {
+    if (!dag) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a] = cmul(u[3 * a], h[0]) + cmul(u[3 * a + 1], h[1]) + cmul(u[3 * a + 2], h[2]);
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) out[a] = cmulc(u[a], h[0]) + cmulc(u[3 + a], h[1]) + cmulc(u[6 + a], h[2]);
+    }
+}
+
+// ---------------------------------------------------------------- spin projection
+// Hop term (1 - sgn*gamma_mu) W psi for W = U or U^+ in the chiral basis: project to the
+// two-component half spinor h = (h0, h1), transport it, and rebuild the lower spins.
+template <int MU, int SGN, typename C>
+__device__ __forceinline__ void hop_accum(cx<C> acc[12], const cx<C> psi[12], const cx<C> u[9], bool dag, C phase) {
+    cx<C> h0[3], h1[3];
+    const C s = C(SGN);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<C> p0 = psi[a], p1 = psi[3 + a], p2 = psi[6 + a], p3 = psi[9 + a];
+        if (MU == 0) { h0[a] = p0 + s * itimes(p3); h1[a] = p1 + s * itimes(p2); }
+        if (MU == 1) { h0[a] = p0 + s * p3;         h1[a] = p1 - s * p2; }
+        if (MU == 2) { h0[a] = p0 + s * itimes(p2); h1[a] = p1 - s * itimes(p3); }
+        if (MU == 3) { h0[a] = p0 - s * p2;         h1[a] = p1 - s * p3; }
+    }
+    cx<C> g0[3], g1[3];
+    su3_mul(g0, u, h0, dag);
+    su3_mul(g1, u, h1, dag);
+    const C ps = phase * s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<C> q0 = phase * g0[a], q1 = phase * g1[a];
+        acc[a] = acc[a] + q0;
+        acc[3 + a] = acc[3 + a] + q1;
+        if (MU == 0) { acc[6 + a] = acc[6 + a] - ps * itimes(g1[a]); acc[9 + a] = acc[9 + a] - ps * itimes(g0[a]); }
+        if (MU == 1) { acc[6 + a] = acc[6 + a] - ps * g1[a];         acc[9 + a] = acc[9 + a] + ps * g0[a]; }
+        if (MU == 2) { acc[6 + a] = acc[6 + a] - ps * itimes(g0[a]); acc[9 + a] = acc[9 + a] + ps * itimes(g1[a]); }
+        if (MU == 3) { acc[6 + a] = acc[6 + a] - ps * g0[a];         acc[9 + a] = acc[9 + a] - ps * g1[a]; }
+    }
+}
+
+// ---------------------------------------------------------------- clover
+// y = F(n) x with the packed hermitian chiral blocks of (ib, s)
+template <typename S2, typename C>
+__device__ __forceinline__ void clover_mul(cx<C> y[12], const cx<C> x[12], const S2 *F, const GeomDev &g, int ib, int s) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const S2 *p = F + ((size_t)ib * 2 + k) * 18 * g.Vb + s;
+        cx<C> d01 = ld(p), d23 = ld(p + g.Vb), d45 = ld(p + 2 * (size_t)g.Vb);
+        C d[6] = {d01.r, d01.i, d23.r, d23.i, d45.r, d45.i};
+        const cx<C> *xk = x + 6 * k;
+        cx<C> yk[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) yk[i] = d[i] * xk[i];
+        int e = 3;
+#pragma unroll
+        for (int i = 1; i < 6; ++i) {
+#pragma unroll
+            for (int j = 0; j < i; ++j) {
+                cx<C> f = ld(p + (size_t)e * g.Vb);
+                ++e;
+                yk[i] = yk[i] + cmul(f, xk[j]);
+                yk[j] = yk[j] + cmulc(f, xk[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) y[6 * k + i] = yk[i];
+    }
+}
+
+// ---------------------------------------------------------------- context
+struct Ctx;
+
+// kernel launchers (defined in the .hip files)
+void launch_pack_spinor(Ctx *c, int prec, void *dst, const double *src, double scale);
+void launch_unpack_spinor(Ctx *c, int prec, double *dst, const void *src, double scale);
+int launch_pack_links(Ctx *c, const double *U, double *max_dev);
+void launch_pack_clover(Ctx *c, const double *F);
+void launch_dslash(Ctx *c, int prec, void *out, const void *in);
+void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y);
+void launch_sap_face(Ctx *c, int colour, void *r, const void *x);
+void launch_ssor_only(Ctx *c, int colour, const void *v, void *x);
+
+// BLAS-1 on internal vectors (n = 12 V complex entries)
+void blas_dots(Ctx *c, int prec, int ndot, const void *const *a, const void *const *b, double2 *host_out);
+void blas_copy(Ctx *c, int prec, void *dst, const void *src);
+void blas_zero(Ctx *c, int prec, void *dst);
+// z = x + a*y  (complex a)
+void blas_xpay(Ctx *c, int prec, void *z, const void *x, double2 a, const void *y);
+// p = r + beta*(p - om*v)
+void blas_bicg_p(Ctx *c, int prec, void *p, const void *r, double2 beta, double2 om, const void *v);
+// e += a*ph + b*sh
+void blas_axpbypz(Ctx *c, int prec, void *e, double2 a, const void *ph, double2 b, const void *sh);
+// dst (prec_d) = scale * src (prec_s)
+void blas_convert(Ctx *c, int prec_d, void *dst, int prec_s, const void *src, double scale);
+
+// HIP-event timing of kernel launches, harvested at the host synchronisation points
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> ev;      // pairs
+    std::vector<int> kind;           // kind of each recorded pair
+    int used = 0;
+    double ms[8] = {0};
+    int n[8] = {0};
+};
+
+struct Ctx {
+    sapq_geom geom;
+    sapq_params prm;
+    hipStream_t stream;
+    GeomDev g;
+    int max_plane;
+    int ssor_threads;
+    bool ssor_lds;
+    size_t lds_bytes;
+    long V;
+    size_t nvec;  // 12 V complex entries
+    // fields
+    double2 *U64, *F64;
+    void *Uin, *Fin;  // inner storage precision
+    bool have_U, have_F;
+    // FP64 work vectors (internal layout)
+    double2 *d_b, *d_x, *d_r, *d_rt, *d_p, *d_v, *d_s, *d_t, *d_ph, *d_sh, *d_tmp;
+    // inner-precision work vectors
+    void *i_r, *i_rt, *i_p, *i_v, *i_s, *i_t, *i_e, *i_ph, *i_sh, *i_rin, *i_tmp;
+    // SAP state
+    void *sap_r, *sap_x;
+    float2 *ssor_scratch;  // SSOR iterate when the block does not fit LDS
+    // reductions
+    double2 *partials, *dev_res;
+    double2 *host_res;  // pinned host
+    double *dev_dev;    // unitarity deviation partials
+    int red_blocks;
+    // counters
+    long n_msap, n_d64;
+    Prof prof;
+};
+
+// bracket a launch with HIP events when profiling is on
+int prof_begin(Ctx *c, int kind);
+void prof_end(Ctx *c, int slot);
+void prof_harvest(Ctx *c);
+
+size_t elem_bytes(int prec);  // bytes of one stored complex
+void set_error(const std::string &msg);
+
+}  // namespace sapq

@@ -1,0 +1,199 @@
+"""Thin ctypes binding of libsapq (include/sapq.h).
+
+Argument marshalling only: tensors are checked (device, dtype, contiguity) and
+their data pointers, with torch's current HIP stream, are handed to the C ABI.
+Every step of the solver runs in the library's HIP kernels; there is no
+fallback, and a missing library raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsapq.so")
+_LIB = None
+
+FP64, FP32, FP16, BF16 = 0, 1, 2, 3
+OUTER_FBICGSTAB, OUTER_DEFECT = 0, 1
+PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
+STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOTSU3", -4: "ENOTCONV", -5: "EBREAKDOWN", -6: "EHIP",
+          -7: "ENOMEM", -8: "ESTATE"}
+
+
+class SapqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sapq {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int * 4), ("block", ctypes.c_int * 4), ("subblock", ctypes.c_int * 4),
+                ("bc_sign", ctypes.c_int * 4)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("omega", ctypes.c_double), ("tol_inner", ctypes.c_double),
+                ("n_ssor", ctypes.c_int), ("n_sap", ctypes.c_int), ("maxit_inner", ctypes.c_int),
+                ("maxit_outer", ctypes.c_int), ("prec_inner", ctypes.c_int), ("outer", ctypes.c_int),
+                ("flags", ctypes.c_int)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("outer_its", ctypes.c_int), ("inner_its", ctypes.c_int), ("n_msap", ctypes.c_int),
+                ("n_dslash64", ctypes.c_int), ("restarts", ctypes.c_int), ("n_hist", ctypes.c_int),
+                ("true_relres", ctypes.c_double), ("time_s", ctypes.c_double), ("kern_ms", ctypes.c_double * 8),
+                ("kern_n", ctypes.c_int * 8), ("relres_hist", ctypes.c_double * 256)]
+
+    KINDS = ("phase_E", "phase_O", "face", "dslash64", "blas")
+
+    def as_dict(self):
+        return dict(outer_its=self.outer_its, inner_its=self.inner_its, n_msap=self.n_msap,
+                    n_dslash64=self.n_dslash64, restarts=self.restarts, true_relres=self.true_relres,
+                    time_s=self.time_s, relres_hist=list(self.relres_hist[: self.n_hist]),
+                    kernels={k: dict(ms=self.kern_ms[i], n=self.kern_n[i]) for i, k in enumerate(self.KINDS)
+                             if self.kern_n[i]})
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "sapq_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(Geom), ctypes.POINTER(Params)]),
+    "sapq_create": (ctypes.c_int, [ctypes.POINTER(Geom), ctypes.POINTER(Params), _P, ctypes.c_size_t, _P,
+                                   ctypes.POINTER(_P)]),
+    "sapq_set_params": (ctypes.c_int, [_P, ctypes.POINTER(Params)]),
+    "sapq_load_gauge": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
+    "sapq_load_clover_inv": (ctypes.c_int, [_P, _P]),
+    "sapq_dslash": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "sapq_ssor": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "sapq_dk": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sapq_sap_precondition": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sapq_inner_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int)]),
+    "sapq_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(Stats)]),
+    "sapq_destroy": (None, [_P]),
+    "sapq_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Open libsapq.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(code):
+    if code != 0:
+        raise SapqError(code, lib().sapq_last_error().decode())
+
+
+def _ptr(t, V=None, shape_tail=None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a torch tensor on a GPU device")
+    if t.dtype != torch.complex128 or not t.is_contiguous():
+        raise TypeError("expected a contiguous complex128 tensor")
+    if V is not None and (t.shape[0] != V or tuple(t.shape[1:]) != shape_tail):
+        raise ValueError(f"expected shape {(V,) + shape_tail}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One lattice + parameter set (one sapq context) with its own device arena."""
+
+    def __init__(self, L, block, subblock, kappa, bc=(1, 1, 1, 1), omega=1.0, n_ssor=4, n_sap=4, tol_inner=1e-2,
+                 maxit_inner=50, maxit_outer=100, prec="fp32", outer="fbicgstab", device=None):
+        self.L = tuple(L)
+        self.V = int(L[0] * L[1] * L[2] * L[3])
+        self.geom = Geom((ctypes.c_int * 4)(*L), (ctypes.c_int * 4)(*block), (ctypes.c_int * 4)(*subblock),
+                         (ctypes.c_int * 4)(*bc))
+        self.params = Params(kappa, omega, tol_inner, n_ssor, n_sap, maxit_inner, maxit_outer, PREC[prec],
+                             OUTER_FBICGSTAB if outer == "fbicgstab" else OUTER_DEFECT, 0)
+        self.prec = prec
+        n = lib().sapq_arena_bytes(ctypes.byref(self.geom), ctypes.byref(self.params))
+        if n == 0:
+            # reproduce the validation error message
+            h = _P()
+            dummy = torch.empty(256, dtype=torch.uint8, device=device or "cuda")
+            _check(lib().sapq_create(ctypes.byref(self.geom), ctypes.byref(self.params),
+                                     ctypes.c_void_p(dummy.data_ptr()), 256, None, ctypes.byref(h)))
+        self.device = torch.device(device or "cuda")
+        self.arena = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = _P()
+        _check(lib().sapq_create(ctypes.byref(self.geom), ctypes.byref(self.params),
+                                 ctypes.c_void_p(self.arena.data_ptr()), n, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sapq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, **kw):
+        for k, v in kw.items():
+            if k == "outer":
+                v = OUTER_FBICGSTAB if v == "fbicgstab" else OUTER_DEFECT
+            setattr(self.params, k, v)
+        _check(lib().sapq_set_params(self.h, ctypes.byref(self.params)))
+
+    def _spinor(self):
+        return torch.empty((self.V, 4, 3), dtype=torch.complex128, device=self.device)
+
+    def load_gauge(self, U):
+        dev = ctypes.c_double(0)
+        _check(lib().sapq_load_gauge(self.h, _ptr(U, self.V, (4, 3, 3)), ctypes.byref(dev)))
+        return dev.value
+
+    def load_clover(self, F):
+        _check(lib().sapq_load_clover_inv(self.h, _ptr(F, self.V, (2, 6, 6))))
+
+    def dslash(self, psi, prec="fp64"):
+        out = self._spinor()
+        _check(lib().sapq_dslash(self.h, _ptr(out), _ptr(psi, self.V, (4, 3)), PREC[prec]))
+        return out
+
+    def ssor(self, v, colour):
+        x = self._spinor()
+        _check(lib().sapq_ssor(self.h, _ptr(x), _ptr(v, self.V, (4, 3)), colour))
+        return x
+
+    def dk(self, v):
+        x, w = self._spinor(), self._spinor()
+        _check(lib().sapq_dk(self.h, _ptr(x), _ptr(w), _ptr(v, self.V, (4, 3))))
+        return x, w
+
+    def sap_precondition(self, v, with_d=True):
+        y = self._spinor()
+        dy = self._spinor() if with_d else None
+        _check(lib().sapq_sap_precondition(self.h, _ptr(y), _ptr(dy) if with_d else None, _ptr(v, self.V, (4, 3))))
+        return (y, dy) if with_d else y
+
+    def inner_solve(self, r):
+        e = self._spinor()
+        it = ctypes.c_int(0)
+        _check(lib().sapq_inner_solve(self.h, _ptr(e), _ptr(r, self.V, (4, 3)), ctypes.byref(it)))
+        return e, it.value
+
+    def solve(self, b, tol=1e-10, x0=None, check=True, profile=False):
+        x = self._spinor() if x0 is None else x0.clone()
+        self.params.flags = (0 if x0 is None else 1) | (2 if profile else 0)
+        _check(lib().sapq_set_params(self.h, ctypes.byref(self.params)))
+        st = Stats()
+        rc = lib().sapq_solve(self.h, _ptr(x), _ptr(b, self.V, (4, 3)), tol, ctypes.byref(st))
+        if check:
+            _check(rc)
+        return x, st.as_dict()
