@@ -1,0 +1,300 @@
+"""Benchmark: time-to-solution of the nested SAP/SSOR solver on one MI355X.
+
+A step is one full solve of D x = b to a true relative residual of 1e-10 on the
+24^3x48 workload: synthetic SU(3) links (eps 0.25, seed 2), c_SW 1.0, kappa 0.125,
+SAP blocks 6^3x12 with 16 sub-blocks of 3^3x6, SSOR omega 1.0 x 4 sweeps, N_SAP 4,
+FP32 inner BiCGStab inside an FP64 flexible BiCGStab, one complex Gaussian source.
+Fields and source are resident in HBM before the timed region starts.
+
+Prints ONE JSON line.  The roofline object describes the dominant kernel (the
+fused SAP phase kernel: gather, SSOR sweeps, block hop), timed with HIP events
+on the library's stream during the timed solves.  The cpu_baseline object times
+the FP64 oracle on a bounded sample (one M_SAP application and three operator
+applications at the full lattice) and scales it by the solve's operation counts.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3         # MI355X vector FP32 (published)
+HOP_FLOPS = 168                  # one spin-projected hop: project 12 + 2 SU(3) x half-spinor 132 + rebuild 24
+CLOVER_FLOPS = 552               # two hermitian 6x6 complex mat-vecs
+AXPY_FLOPS = 48                  # x = v + kappa F h on 12 complex entries
+
+WORKLOADS = {
+    "24^3x48": dict(L=(24, 24, 24, 48), B=(6, 6, 6, 12), S=(3, 3, 3, 6), kappa=0.125, csw=1.0, eps=0.25,
+                    seed=2, seed_b=1002),
+    "8^4": dict(L=(8, 8, 8, 8), B=(4, 4, 4, 4), S=(2, 2, 2, 2), kappa=0.120, csw=1.0, eps=0.25, seed=1,
+                seed_b=1001),
+    "32^3x64": dict(L=(32, 32, 32, 64), B=(4, 4, 4, 4), S=(2, 2, 2, 2), kappa=0.125, csw=1.0, eps=0.25, seed=3,
+                    seed_b=1003),
+    "24^3x48/4^4": dict(L=(24, 24, 24, 48), B=(4, 4, 4, 4), S=(2, 2, 2, 2), kappa=0.125, csw=1.0, eps=0.25, seed=2,
+                        seed_b=1002),
+}
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
+    counters of rocprofv3 (run this mode under the profiler)."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"mode": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+                      "launches": reps, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
+
+
+def make_inputs(w):
+    from paper_1210_7398_amd import synth
+
+    t0 = time.time()
+    U = synth.gauge_field(w["L"], w["eps"], w["seed"])
+    F = synth.clover_inverse(w["L"], U, w["csw"], w["kappa"])
+    b = synth.gaussian_spinor(w["L"], w["seed_b"])
+    print(f"# inputs generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    return U, F, b
+
+
+def precision_study(args):
+    """The precision workload: one lattice solved with FP32, FP16 and BF16 storage for the SAP
+    preconditioner and inner solver, FP64 outer iteration, tol 1e-10.  Prints one JSON line
+    with time-to-solution, iteration counts, FP64 true residual and the difference of each
+    solution from the FP32-storage one."""
+    import torch
+
+    from paper_1210_7398_amd import sapq
+
+    wl = "32^3x64" if args.workload == "24^3x48" else args.workload
+    w = WORKLOADS[wl]
+    U, F, b = make_inputs(w)
+    dev = torch.device("cuda:0")
+    Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
+    del U, F
+    res, xref = [], None
+    for prec in ("fp32", "fp16", "bf16"):
+        s = sapq.Solver(w["L"], w["B"], w["S"], w["kappa"], prec=prec, outer=args.outer, maxit_outer=400, device=dev)
+        s.load_gauge(Ud)
+        s.load_clover(Fd)
+        s.solve(bd, tol=1e-10)  # warm-up
+        times, st = [], None
+        for _ in range(max(1, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st = s.solve(bd, tol=1e-10, profile=True)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        if xref is None:
+            xref = x.clone()
+        diff = float(torch.linalg.vector_norm(x - xref) / torch.linalg.vector_norm(xref))
+        ph = st["kernels"].get("phase_E", {}), st["kernels"].get("phase_O", {})
+        n_ph = ph[0].get("n", 0) + ph[1].get("n", 0)
+        res.append(dict(prec=prec, time_s=sorted(times)[len(times) // 2], outer_its=st["outer_its"],
+                        inner_its=st["inner_its"], n_msap=st["n_msap"], true_relres=st["true_relres"],
+                        rel_diff_vs_fp32_storage=diff,
+                        sap_phase_avg_us=(1e3 * (ph[0].get("ms", 0) + ph[1].get("ms", 0)) / n_ph) if n_ph else None))
+        print(f"# {prec}: {res[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "precision", "workload": wl, "outer": args.outer, "tol": 1e-10, "results": res}),
+          flush=True)
+
+
+def phase_model(B, n_ssor, prec_bytes):
+    """Algorithmic bytes and flops per site of one SAP phase kernel launch (a cycle after the
+    first: it gathers the other colour and accumulates y).  Each operand is counted once."""
+    face = sum(2.0 / b for b in B)            # hops per site that leave the block
+    inner = 8.0 - face                         # hops per site that stay inside it
+    S = prec_bytes
+    bytes_ = S * (24 + 24 * face + 48 + 12 * face / 2 + 72 + 24 * 3 + 24)
+    gather = face * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS
+    sweep = inner * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS
+    first = 0.5 * inner * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS   # from x = 0 only lower neighbours count
+    ssor = (2 * n_ssor - 1) * sweep + first
+    final = sweep + 24 + 24
+    return bytes_, gather + ssor + final
+
+
+def dslash_model(prec_bytes):
+    S = prec_bytes
+    return S * (24 + 48 + 72 + 24), 8 * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS
+
+
+def traffic_from_profiles(kernel_name):
+    """HBM bytes per launch measured by rocprofv3 counters, if they were taken on the current
+    kernel source (profiles/counters.json records the source hash)."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_1210_7398_amd", "csrc", "kernels.hip"), "rb").read()
+        if data.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+            return None
+        k = data["kernels"].get(kernel_name)
+        return None if k is None else k.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="24^3x48", choices=list(WORKLOADS))
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision"])
+    ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and is not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "copy":
+        copy_calibration()
+        return
+    if args.mode == "precision":
+        precision_study(args)
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_1210_7398_amd import sapq, synth
+
+    w = WORKLOADS[args.workload]
+    L, B, S = w["L"], w["B"], w["S"]
+    V = int(np.prod(L))
+    U, F, b = make_inputs(w)
+
+    dev = torch.device("cuda:0")
+    solver = sapq.Solver(L, B, S, w["kappa"], prec=args.prec, outer=args.outer, device=dev)
+    solver.load_gauge(torch.from_numpy(U).to(dev))
+    solver.load_clover(torch.from_numpy(F).to(dev))
+    bd = torch.from_numpy(b).to(dev)
+    torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        x, st = solver.solve(bd, tol=1e-10)
+        print(f"# warmup {i}: {st['time_s']:.3f} s outer {st['outer_its']} inner {st['inner_its']} "
+              f"relres {st['true_relres']:.2e}", file=sys.stderr, flush=True)
+
+    torch.cuda.synchronize()
+    stats = []
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        x, st = solver.solve(bd, tol=1e-10, profile=True)
+        stats.append(st)
+        print(f"# step {i}: {st['time_s']:.3f} s outer {st['outer_its']} inner {st['inner_its']} "
+              f"msap {st['n_msap']} relres {st['true_relres']:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    sec_per_solve = elapsed / args.steps
+    assert all(s["true_relres"] <= 1e-10 for s in stats), "a timed solve missed the tolerance"
+
+    prec_bytes = 4 if args.prec == "fp32" else 2
+    sites_per_phase = V // 2
+    ph_bytes, ph_flops = phase_model(B, 4, prec_bytes)
+    k = {}
+    for name in ("phase_E", "phase_O", "face", "dslash64"):
+        ms = sum(s["kernels"].get(name, {}).get("ms", 0.0) for s in stats)
+        n = sum(s["kernels"].get(name, {}).get("n", 0) for s in stats)
+        k[name] = dict(launches=n, avg_us=1e3 * ms / n if n else None, total_ms=ms)
+    n_ph = k["phase_E"]["launches"] + k["phase_O"]["launches"]
+    avg_ph_s = (k["phase_E"]["total_ms"] + k["phase_O"]["total_ms"]) / n_ph / 1e3
+    alg_bytes = ph_bytes * sites_per_phase
+    alg_flops = ph_flops * sites_per_phase
+    t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = alg_flops / (FP32_PEAK_TFLOPS * 1e12)
+    traffic = traffic_from_profiles("k_sap_phase")
+    if t_hbm >= t_alu:
+        roof = dict(bound="hbm", achieved=alg_bytes / avg_ph_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
+    else:
+        roof = dict(bound="alu", achieved=alg_flops / avg_ph_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s")
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = traffic
+    roof["kernel"] = "k_sap_phase"
+    roof["avg_launch_us"] = avg_ph_s * 1e6
+    roof["alg_bytes_per_launch"] = alg_bytes
+    roof["alg_flops_per_launch"] = alg_flops
+
+    d_bytes, d_flops = dslash_model(8)
+    d_avg = k["dslash64"]["avg_us"] * 1e-6 if k["dslash64"]["avg_us"] else None
+    kernels = dict(
+        sap_phase=dict(avg_us=avg_ph_s * 1e6, launches=n_ph, GBps=alg_bytes / avg_ph_s / 1e9,
+                       TFLOPs=alg_flops / avg_ph_s / 1e12),
+        dslash_fp64=dict(avg_us=k["dslash64"]["avg_us"], launches=k["dslash64"]["launches"],
+                         GBps=(d_bytes * V / d_avg / 1e9) if d_avg else None,
+                         frac_hbm=(d_bytes * V / d_avg / 1e9 / HBM_PEAK_GBS) if d_avg else None),
+        face=dict(avg_us=k["face"]["avg_us"], launches=k["face"]["launches"]),
+    )
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        prm = oracle.params(w["kappa"])
+        tc = time.perf_counter()
+        oracle.msap(L, B, S, U, F, prm, b)
+        t_msap = time.perf_counter() - tc
+        tc = time.perf_counter()
+        for _ in range(3):
+            oracle.dslash(L, U, F, w["kappa"], b)
+        t_d = (time.perf_counter() - tc) / 3
+        st0 = stats[0]
+        est = st0["n_msap"] * t_msap + st0["n_dslash64"] * t_d
+        cpu = dict(value=est, unit="s", cores=nthreads, kind="oracle",
+                   sample=(f"oracle (FP64, OpenMP) on the full {args.workload} fields: 1 M_SAP application "
+                           f"({t_msap:.2f} s) and 3 operator applications ({t_d:.2f} s each), scaled by the "
+                           f"solve's {st0['n_msap']} M_SAP and {st0['n_dslash64']} operator applications "
+                           "(vector updates not counted)"))
+
+    st0 = stats[-1]
+    out = {
+        "metric": "time-to-1e-10 residual (s)",
+        "value": sec_per_solve,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec_per_solve * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.prec == "fp32" else f"{args.prec}-storage/f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"clover-Wilson solve {args.workload}, kappa {w['kappa']}, c_SW {w['csw']}, "
+                         f"SAP blocks {'x'.join(map(str, B))}, sub-blocks {'x'.join(map(str, S))}, "
+                         f"SSOR omega 1.0 x4, N_SAP 4, {args.prec} inner BiCGStab, fp64 flexible outer, "
+                         "tol 1e-10, 1 Gaussian source"),
+            "lattice": list(L), "block": list(B), "subblock": list(S), "kappa": w["kappa"],
+            "inner_precision": args.prec, "rhs": 1,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "solver": dict(outer_its=st0["outer_its"], inner_its=st0["inner_its"], n_msap=st0["n_msap"],
+                       n_dslash64=st0["n_dslash64"], true_relres=st0["true_relres"]),
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

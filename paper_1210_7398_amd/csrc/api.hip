@@ -6,6 +6,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -25,7 +26,7 @@ size_t elem_bytes(int prec) {
     }
 }
 
-void set_sap_lds_limits(Ctx *c);
+int set_sap_lds_limits(Ctx *c);
 
 // ---------------------------------------------------------------- kernel timing
 int prof_begin(Ctx *c, int kind) {
@@ -67,6 +68,7 @@ struct HostTables {
     int Vb = 0, NB = 0, nplanes = 0, max_plane = 0;
     int nbk[4];
     std::vector<int> loc_nbr, blk_nbr, plane_start, slot_lex, blk_lex;
+    std::vector<int> nbr16;  // packed forward/backward slots per direction (stored as unsigned)
 };
 
 static int check_geom(const sapq_geom *g, std::string &why) {
@@ -131,6 +133,14 @@ static void build_tables(const sapq_geom *G, HostTables &T) {
                 T.loc_nbr[(2 * mu + dir) * Vb + s] = inside ? t : -1 - t;
             }
     }
+    T.nbr16.resize(4 * Vb);
+    for (int mu = 0; mu < 4; ++mu)
+        for (int s = 0; s < Vb; ++s) {
+            int f = T.loc_nbr[(2 * mu) * Vb + s], b = T.loc_nbr[(2 * mu + 1) * Vb + s];
+            unsigned wf = f >= 0 ? (unsigned)f | 0x8000u : (unsigned)(-1 - f);
+            unsigned wb = b >= 0 ? (unsigned)b | 0x8000u : (unsigned)(-1 - b);
+            T.nbr16[mu * Vb + s] = (int)(wf | (wb << 16));
+        }
     // blocks: E (colour 0) first, then O, each in lexicographic order
     int NB = T.nbk[0] * T.nbk[1] * T.nbk[2] * T.nbk[3];
     T.NB = NB;
@@ -179,6 +189,7 @@ static void carve(Ctx *c, Arena &A, const HostTables &T) {
     size_t eb = elem_bytes(pi);
     auto ints = [&](size_t n) { return (int *)A.take(n * sizeof(int)); };
     c->g.loc_nbr = ints(T.loc_nbr.size());
+    c->g.nbr16 = (const unsigned *)ints(T.nbr16.size());
     c->g.blk_nbr = ints(T.blk_nbr.size());
     c->g.plane_start = ints(T.plane_start.size());
     c->g.slot_lex = ints(T.slot_lex.size());
@@ -223,9 +234,13 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
     c->V = (long)geom->L[0] * geom->L[1] * geom->L[2] * geom->L[3];
     c->nvec = (size_t)c->V * 12;
     c->max_plane = T.max_plane;
-    c->ssor_threads = std::min(512, ((T.max_plane + 63) / 64) * 64);
+    // four lanes per site; at most 512 lanes per workgroup unless SAPQ_SSOR_THREADS asks otherwise
+    int nt_cap = 512;
+    if (const char *e = getenv("SAPQ_SSOR_THREADS")) nt_cap = std::max(64, std::min(1024, atoi(e)));
+    c->ssor_threads = std::min(nt_cap, ((4 * T.max_plane + 63) / 64) * 64);
     c->lds_bytes = (size_t)T.Vb * 12 * sizeof(float2);
-    c->ssor_lds = (long)c->lds_bytes <= (long)max_lds;
+    c->lds_extra = (size_t)T.Vb * 4 * sizeof(unsigned) + (MAX_PLANES + 1) * sizeof(int);
+    c->ssor_lds = (long)(c->lds_bytes + c->lds_extra) <= (long)max_lds;
     Arena A{nullptr, 0, 0};
     carve(c, A, T);
     return A.used + 256;
@@ -270,7 +285,8 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     Ctx *c = &h->c;
     HostTables T;
     size_t need = plan(geom, params, c, T, device_max_lds());
-    if (T.max_plane > 4096) { delete h; set_error("hyperplane too large"); return SAPQ_ESHAPE; }
+    if (T.max_plane > 4096 || T.Vb > 32767) { delete h; set_error("block too large"); return SAPQ_ESHAPE; }
+    if ((long)c->lds_extra > (long)device_max_lds()) { delete h; set_error("block too large for LDS tables"); return SAPQ_ESHAPE; }
     if (T.nplanes > MAX_PLANES) { delete h; set_error("too many hyperplanes"); return SAPQ_ESHAPE; }
     if (arena_bytes < need) {
         delete h;
@@ -296,7 +312,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     rc = hipcheck(hipHostMalloc((void **)&c->host_res, 8 * sizeof(double2), hipHostMallocDefault), "hipHostMalloc");
     if (rc) { delete h; return rc; }
     struct { const void *dst; const std::vector<int> *src; } cp[] = {
-        {c->g.loc_nbr, &T.loc_nbr}, {c->g.blk_nbr, &T.blk_nbr}, {c->g.plane_start, &T.plane_start},
+        {c->g.loc_nbr, &T.loc_nbr}, {c->g.nbr16, &T.nbr16}, {c->g.blk_nbr, &T.blk_nbr}, {c->g.plane_start, &T.plane_start},
         {c->g.slot_lex, &T.slot_lex}, {c->g.blk_lex, &T.blk_lex}};
     for (auto &e : cp) {
         rc = hipcheck(hipMemcpyAsync((void *)e.dst, e.src->data(), e.src->size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
@@ -305,7 +321,12 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     }
     rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (rc) { hipHostFree(c->host_res); delete h; return rc; }
-    set_sap_lds_limits(c);
+    if (set_sap_lds_limits(c)) {
+        hipHostFree(c->host_res);
+        delete h;
+        set_error("hipFuncSetAttribute refused the LDS size of the SAP kernel");
+        return SAPQ_EHIP;
+    }
     *out = h;
     return SAPQ_OK;
 }

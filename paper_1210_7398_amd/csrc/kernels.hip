@@ -90,7 +90,9 @@ __global__ void k_pack_links(GeomDev g, const double2 *src, double2 *U64, typena
     if (threadIdx.x == 0) dev[blockIdx.x] = red[0];
 }
 
-// clover: packed hermitian chiral blocks (diagonal pairs, then the strict lower triangle)
+// clover: each hermitian chiral block [[A, B], [B^+, C]] (A, C hermitian 3x3) is stored as
+// 18 complex slots: the six real diagonal entries pairwise (3 slots), the strict lower
+// triangles of A and of C (3 + 3 slots), and B row by row (9 slots).
 template <int P>
 __global__ void k_pack_clover(GeomDev g, const double2 *src, double2 *F64, typename Prec<P>::S2 *Fin) {
     using C = typename Prec<P>::C;
@@ -103,9 +105,13 @@ __global__ void k_pack_clover(GeomDev g, const double2 *src, double2 *F64, typen
         size_t base = ((size_t)ib * 2 + k) * 18 * g.Vb + s;
         cx<double> e[18];
         for (int d = 0; d < 3; ++d) e[d] = {m[7 * (2 * d)].x, m[7 * (2 * d + 1)].x};
-        int q = 3;
-        for (int r = 1; r < 6; ++r)
-            for (int c = 0; c < r; ++c) e[q++] = {m[6 * r + c].x, m[6 * r + c].y};
+        const int lo[3][2] = {{1, 0}, {2, 0}, {2, 1}};
+        for (int q = 0; q < 3; ++q) {
+            e[3 + q] = {m[6 * lo[q][0] + lo[q][1]].x, m[6 * lo[q][0] + lo[q][1]].y};
+            e[6 + q] = {m[6 * (3 + lo[q][0]) + 3 + lo[q][1]].x, m[6 * (3 + lo[q][0]) + 3 + lo[q][1]].y};
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) e[9 + 3 * a + b] = {m[6 * a + 3 + b].x, m[6 * a + 3 + b].y};
         for (int t = 0; t < 18; ++t) {
             F64[base + (size_t)t * g.Vb] = make_double2(e[t].r, e[t].i);
             st(Fin + base + (size_t)t * g.Vb, cx<C>{C(e[t].r), C(e[t].i)});
@@ -113,13 +119,64 @@ __global__ void k_pack_clover(GeomDev g, const double2 *src, double2 *F64, typen
     }
 }
 
-// ================================================================ hopping building block
-// Spinor sources: a field in storage precision, or the float2 SSOR iterate of one block.
-template <typename S2, typename C> struct FieldSrc {
+// ================================================================ four lanes per site
+// A site is handled by a group of four adjacent lanes; lane j takes direction mu = j
+// (its forward and its backward hop), the four partial hopping sums are added with a
+// quad butterfly, and lane j then owns spin j (components 3j..3j+2) of the result.
+// The spin projection is written with per-lane coefficients so that the four lanes
+// run the same instructions:
+//   (1 - s gamma_mu) W psi:  h0 = p0 + c0 p[a0],  h1 = p1 + c1 p[a1],  g = W h,
+//   spins (0, 1) += (g0, g1),  spin a0 += conj(c0) g0,  spin a1 += conj(c1) g1,
+// with a0 = 3, a1 = 2 for mu = x, y and a0 = 2, a1 = 3 for mu = z, t, and (c0, c1) =
+// (s i, s i), (s, -s), (s i, -s i), (-s, -s) for mu = x, y, z, t.
+template <typename C> struct LaneDir {
+    int mu;
+    bool a0_is3;
+    cx<C> c0, c1;  // forward hop (s = +1); the backward hop uses -c0, -c1
+};
+
+template <typename C> __device__ __forceinline__ LaneDir<C> lane_dir(int j) {
+    LaneDir<C> d;
+    d.mu = j;
+    d.a0_is3 = j < 2;
+    const C one = C(1), zero = C(0);
+    d.c0 = (j == 0 || j == 2) ? cx<C>{zero, one} : (j == 1 ? cx<C>{one, zero} : cx<C>{-one, zero});
+    d.c1 = (j == 0) ? cx<C>{zero, one} : (j == 1 ? cx<C>{-one, zero} : (j == 2 ? cx<C>{zero, -one} : cx<C>{-one, zero}));
+    return d;
+}
+
+template <typename T> __device__ __forceinline__ cx<T> sel(bool p, cx<T> a, cx<T> b) { return {p ? a.r : b.r, p ? a.i : b.i}; }
+
+template <typename C>
+__device__ __forceinline__ void lane_hop(cx<C> acc[12], const cx<C> psi[12], const cx<C> u[9], bool dag, cx<C> c0,
+                                         cx<C> c1, bool a0_is3, C phase) {
+    cx<C> h0[3], h1[3], g0[3], g1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<C> pa0 = sel(a0_is3, psi[9 + a], psi[6 + a]);
+        cx<C> pa1 = sel(a0_is3, psi[6 + a], psi[9 + a]);
+        h0[a] = psi[a] + cmul(c0, pa0);
+        h1[a] = psi[3 + a] + cmul(c1, pa1);
+    }
+    su3_mul(g0, u, h0, dag);
+    su3_mul(g1, u, h1, dag);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<C> q0 = phase * g0[a], q1 = phase * g1[a];
+        acc[a] = acc[a] + q0;
+        acc[3 + a] = acc[3 + a] + q1;
+        cx<C> t0 = cmulc(c0, q0), t1 = cmulc(c1, q1);
+        acc[6 + a] = acc[6 + a] + sel(a0_is3, t1, t0);
+        acc[9 + a] = acc[9 + a] + sel(a0_is3, t0, t1);
+    }
+}
+
+// Spinor sources for the hops.
+template <typename S2, typename C> struct FieldSrc {  // a field in storage precision
     const S2 *f;
     __device__ __forceinline__ void get(cx<C> psi[12], const GeomDev &g, int ib, int s) const { load_spinor(psi, f, g, ib, s); }
 };
-struct BlockSrc {  // [12][Vb] float2 of the current block (LDS or global scratch)
+struct BlockSrc {  // the float2 [12][Vb] SSOR iterate of the current block (LDS or scratch)
     const float2 *x;
     __device__ __forceinline__ void get(cx<float> psi[12], const GeomDev &g, int, int s) const {
 #pragma unroll
@@ -130,36 +187,143 @@ struct BlockSrc {  // [12][Vb] float2 of the current block (LDS or global scratc
     }
 };
 
-// MODE 0: all eight neighbours; 1: neighbours inside the block; 2: neighbours outside it
-template <int MODE, int MU, typename S2, typename C, typename Src>
-__device__ __forceinline__ void hop_dir(cx<C> acc[12], const GeomDev &g, int ib, int s, const S2 *U, const Src &src) {
-    cx<C> psi[12], u[9];
-    Nbr f = neighbour(g, ib, s, 2 * MU);
-    if (MODE == 0 || (MODE == 1) == f.inside) {
-        src.get(psi, g, f.ib, f.s);
-        load_link(u, U, g, ib, s, MU);
-        hop_accum<MU, +1>(acc, psi, u, false, C(f.phase));
+enum { HOP_ALL = 0, HOP_IN = 1, HOP_OUT = 2 };
+
+// value of the lane (lane ^ 1) or (lane ^ 2) of the same quad, by DPP quad permutes
+template <int CTRL> __device__ __forceinline__ float quad_get(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL> __device__ __forceinline__ double quad_get(double v) {
+    long long b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int QUAD_XOR1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int QUAD_XOR2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+
+template <typename C> __device__ __forceinline__ void quad_reduce(cx<C> acc[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        acc[c].r += quad_get<QUAD_XOR1>(acc[c].r);
+        acc[c].i += quad_get<QUAD_XOR1>(acc[c].i);
     }
-    Nbr b = neighbour(g, ib, s, 2 * MU + 1);
-    if (MODE == 0 || (MODE == 1) == b.inside) {
-        src.get(psi, g, b.ib, b.s);
-        load_link(u, U, g, b.ib, b.s, MU);
-        hop_accum<MU, -1>(acc, psi, u, true, C(b.phase));
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        acc[c].r += quad_get<QUAD_XOR2>(acc[c].r);
+        acc[c].i += quad_get<QUAD_XOR2>(acc[c].i);
     }
 }
 
-template <int MODE, typename S2, typename C, typename Src>
-__device__ __forceinline__ void hop_site(cx<C> acc[12], const GeomDev &g, int ib, int s, const S2 *U, const Src &src) {
+// The two neighbours of a lane (direction j, forward and backward) of site (ib, s).
+// nbr16[j][s] packs the forward slot in bits 0..14 and the backward slot in bits 16..30,
+// with bit 15 / bit 31 set when that neighbour lies inside the block; outside
+// neighbours give the slot in the adjacent block.
+struct LaneNbr {
+    int s_f, s_b, ib_f, ib_b;
+    bool in_f, in_b;
+    float ph_f, ph_b;
+};
+
+__device__ __forceinline__ LaneNbr lane_nbr(unsigned w, int ib, int bl_f, int bl_b, float bc) {
+    LaneNbr n;
+    n.s_f = (int)(w & 0x7fffu);
+    n.in_f = (w & 0x8000u) != 0;
+    n.s_b = (int)((w >> 16) & 0x7fffu);
+    n.in_b = (w & 0x80000000u) != 0;
+    n.ib_f = n.in_f ? ib : (bl_f & BLK_MASK);
+    n.ib_b = n.in_b ? ib : (bl_b & BLK_MASK);
+    n.ph_f = (!n.in_f && (bl_f & WRAP_BIT)) ? bc : 1.f;
+    n.ph_b = (!n.in_b && (bl_b & WRAP_BIT)) ? bc : 1.f;
+    return n;
+}
+
+// Lane part of sum_m H_nm psi(m) over the selected neighbours (direction j) of (ib, s),
+// followed by the quad reduction: on return every lane of the group holds the full sum.
+// Excluded neighbours are read from a valid address and their spinor is set to zero.
+template <int MODE, bool LEAN, typename S2, typename C, typename Src>
+__device__ __forceinline__ void quad_hop_sum(cx<C> acc[12], const GeomDev &g, int ib, int s, int j, const LaneNbr &n,
+                                             const S2 *__restrict__ U, const Src &src) {
+    // LEAN: finish the forward hop before the backward hop's loads are issued, which keeps
+    // the register footprint small enough for 1024-lane workgroups
+    const LaneDir<C> d = lane_dir<C>(j);
+    const bool use_f = MODE == HOP_ALL || (MODE == HOP_IN ? n.in_f : !n.in_f);
+    const bool use_b = MODE == HOP_ALL || (MODE == HOP_IN ? n.in_b : !n.in_b);
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = cxz<C>();
-    hop_dir<MODE, 0>(acc, g, ib, s, U, src);
-    hop_dir<MODE, 1>(acc, g, ib, s, U, src);
-    hop_dir<MODE, 2>(acc, g, ib, s, U, src);
-    hop_dir<MODE, 3>(acc, g, ib, s, U, src);
+    {
+        cx<C> pf[12], uf[9];
+        src.get(pf, g, n.ib_f, n.s_f);
+        load_link(uf, U, g, ib, s, j);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) pf[c] = sel(use_f, pf[c], cxz<C>());
+        lane_hop(acc, pf, uf, false, d.c0, d.c1, d.a0_is3, C(n.ph_f));
+    }
+    if (LEAN) __builtin_amdgcn_sched_barrier(0);
+    {
+        cx<C> pb[12], ub[9];
+        src.get(pb, g, n.ib_b, n.s_b);
+        load_link(ub, U, g, n.ib_b, n.s_b, j);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) pb[c] = sel(use_b, pb[c], cxz<C>());
+        lane_hop(acc, pb, ub, true, C(-1) * d.c0, C(-1) * d.c1, d.a0_is3, C(n.ph_b));
+    }
+    if (LEAN) __builtin_amdgcn_sched_barrier(0);
+    quad_reduce(acc);
+}
+
+// Rows of F(n) h owned by lane j (spin j): with k = j >> 1 and hi = j & 1 the lane needs
+// rows 3*hi .. 3*hi+2 of chiral block k = [[A, B], [B^+, C]]:
+//   hi = 0:  A h_u + B h_l        hi = 1:  B^+ h_u + C h_l
+template <typename S2, typename C>
+__device__ __forceinline__ void lane_clover(cx<C> out[3], const cx<C> h[12], const S2 *__restrict__ F, const GeomDev &g,
+                                            int ib, int s, int j) {
+    const int k = j >> 1;
+    const bool hi = (j & 1) != 0;
+    const S2 *p = F + ((size_t)ib * 2 + k) * 18 * g.Vb + s;
+    cx<C> own[3], oth[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cx<C> u = sel(k != 0, h[6 + a], h[a]), l = sel(k != 0, h[9 + a], h[3 + a]);
+        own[a] = sel(hi, l, u);
+        oth[a] = sel(hi, u, l);
+    }
+    const cx<C> d01 = ld(p), d23 = ld(p + g.Vb), d45 = ld(p + 2 * (size_t)g.Vb);
+    const C dg0 = hi ? d23.i : d01.r, dg1 = hi ? d45.r : d01.i, dg2 = hi ? d45.i : d23.r;
+    const S2 *ph = p + (size_t)(hi ? 6 : 3) * g.Vb;
+    const cx<C> h10 = ld(ph), h20 = ld(ph + g.Vb), h21 = ld(ph + 2 * (size_t)g.Vb);
+    cx<C> m[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int slot = hi ? 9 + 3 * b + a : 9 + 3 * a + b;
+            cx<C> v = ld(p + (size_t)slot * g.Vb);
+            m[3 * a + b] = {v.r, hi ? -v.i : v.i};
+        }
+    out[0] = dg0 * own[0] + cmulc(h10, own[1]) + cmulc(h20, own[2]);
+    out[1] = dg1 * own[1] + cmul(h10, own[0]) + cmulc(h21, own[2]);
+    out[2] = dg2 * own[2] + cmul(h20, own[0]) + cmul(h21, own[1]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[a] = out[a] + cmul(m[3 * a], oth[0]) + cmul(m[3 * a + 1], oth[1]) + cmul(m[3 * a + 2], oth[2]);
+}
+
+// spin j (components 3j..3j+2) of a field site
+template <typename S2, typename C>
+__device__ __forceinline__ void load_spin(cx<C> v[3], const S2 *f, const GeomDev &g, int ib, int s, int j) {
+    const S2 *p = f + ((size_t)ib * 12 + 3 * j) * g.Vb + s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[a] = ld(p + (size_t)a * g.Vb);
+}
+template <typename S2, typename C>
+__device__ __forceinline__ void store_spin(S2 *f, const GeomDev &g, int ib, int s, int j, const cx<C> v[3]) {
+    S2 *p = f + ((size_t)ib * 12 + 3 * j) * g.Vb + s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) st(p + (size_t)a * g.Vb, v[a]);
 }
 
 // ================================================================ full operator D
-// out = in - kappa F H in, one thread per site
+// out = in - kappa F H in; four lanes per site
 template <int P>
 __global__ void __launch_bounds__(256) k_dslash(GeomDev g, typename Prec<P>::S2 *__restrict__ out,
                                                const typename Prec<P>::S2 *__restrict__ in,
@@ -167,80 +331,99 @@ __global__ void __launch_bounds__(256) k_dslash(GeomDev g, typename Prec<P>::S2 
                                                const typename Prec<P>::S2 *__restrict__ F, double kappa) {
     using S2 = typename Prec<P>::S2;
     using C = typename Prec<P>::C;
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long i = gt >> 2;
+    const int j = (int)(gt & 3);
     if (i >= g.V) return;
-    int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
-    cx<C> h[12], fh[12], psi[12];
-    hop_site<0>(h, g, ib, s, U, FieldSrc<S2, C>{in});
-    clover_mul(fh, h, F, g, ib, s);
-    load_spinor(psi, in, g, ib, s);
+    const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    const LaneNbr n = lane_nbr(g.nbr16[j * g.Vb + s], ib, g.blk_nbr[(2 * j) * g.NB + ib], g.blk_nbr[(2 * j + 1) * g.NB + ib],
+                               g.bc[j]);
+    cx<C> h[12], fh[3], v[3];
+    quad_hop_sum<HOP_ALL, false>(h, g, ib, s, j, n, U, FieldSrc<S2, C>{in});
+    lane_clover(fh, h, F, g, ib, s, j);
+    load_spin(v, in, g, ib, s, j);
     const C k = C(kappa);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) psi[c] = psi[c] - k * fh[c];
-    store_spinor(out, g, ib, s, psi);
+    for (int a = 0; a < 3; ++a) v[a] = v[a] - k * fh[a];
+    store_spin(out, g, ib, s, j, v);
 }
 
 // ================================================================ SAP phase kernel
 // One workgroup per block of colour `colour` (Algorithm 1 fused with the M_SAP update):
-//   v_c  = r_c + kappa F sum_{hops leaving the block} H x_other   (= r_c - D_{c,other} x_other)
-//   x_c  = SSOR block inverse of v_c (n_ssor symmetric sweeps from 0, hyperplane schedule)
-//   y_c  = (first ? 0 : y_c) + x_c,   r_c = v_c - D_cc x_c,   x_c stored for the other colour.
-// mode 1 (ssor only): v_c = rsrc, write x_c and nothing else.
+//   v_c = r_c + kappa F sum_{hops leaving the block} H x_other   (= r_c - D_{c,other} x_other)
+//   x_c = SSOR block inverse of v_c (n_ssor forward+backward sweeps from 0; the sweeps walk
+//         the hyperplanes of the sub-block-local coordinates, whose sites are independent)
+//   y_c = (first ? 0 : y_c) + x_c,   r_c = v_c - D_cc x_c,   x_c kept for the other colour.
+// ssor_only: v_c = rsrc and only x_c is written.  Four lanes per site throughout.
 struct SapArgs {
     int colour, gather, first, ssor_only, n_ssor;
     float kappa, omega;
 };
 
-template <int P, bool XLDS>
-__global__ void __launch_bounds__(512) k_sap_phase(GeomDev g, SapArgs a, const typename Prec<P>::S2 *rsrc,
-                                                    typename Prec<P>::S2 *r, typename Prec<P>::S2 *x,
-                                                    typename Prec<P>::S2 *y, const typename Prec<P>::S2 *__restrict__ U,
-                                                    const typename Prec<P>::S2 *__restrict__ F, float2 *scratch) {
+template <int P, bool XLDS, int NT>
+__global__ void __launch_bounds__(NT) k_sap_phase(GeomDev g, SapArgs a, const typename Prec<P>::S2 *rsrc,
+                                                  typename Prec<P>::S2 *r, typename Prec<P>::S2 *x,
+                                                  typename Prec<P>::S2 *y, const typename Prec<P>::S2 *__restrict__ U,
+                                                  const typename Prec<P>::S2 *__restrict__ F, float2 *scratch) {
     using S2 = typename Prec<P>::S2;
     using C = float;
+    // LDS: [iterate x (XLDS only): 12 Vb float2][neighbour words: 4 Vb][plane starts: MAX_PLANES + 1]
     extern __shared__ float2 lds[];
     const int ib = a.colour * g.NBc + blockIdx.x;
     float2 *xs = XLDS ? lds : scratch + (size_t)ib * 12 * g.Vb;
+    unsigned *nb_lds = reinterpret_cast<unsigned *>(lds + (XLDS ? 12 * g.Vb : 0));
+    int *ps_lds = reinterpret_cast<int *>(nb_lds + 4 * g.Vb);
     const C kappa = a.kappa, omega = a.omega;
-    // vb: where v_c lives during the sweeps (r, or rsrc in ssor-only mode)
-    const S2 *vb = a.ssor_only ? rsrc : r;
+    const S2 *vb = a.ssor_only ? rsrc : r;  // where v_c lives during the sweeps
+    const int j = threadIdx.x & 3;
+    const int q0 = threadIdx.x >> 2, nq = blockDim.x >> 2;
+    const BlockSrc bs{xs};
+    const int bl_f = g.blk_nbr[(2 * j) * g.NB + ib], bl_b = g.blk_nbr[(2 * j + 1) * g.NB + ib];
+    const float bc = g.bc[j];
 
-    // 1. gather v_c, zero the iterate
-    for (int s = threadIdx.x; s < g.Vb; s += blockDim.x) {
+    for (int t = threadIdx.x; t < 4 * g.Vb; t += blockDim.x) nb_lds[t] = g.nbr16[t];
+    for (int t = threadIdx.x; t <= g.nplanes; t += blockDim.x) ps_lds[t] = g.plane_start[t];
+    __syncthreads();
+
+    // 1. v_c (gathering the other colour), zero the iterate
+    for (int s = q0; s < g.Vb; s += nq) {
         if (!a.ssor_only) {
-            cx<C> v[12];
-            load_spinor(v, rsrc, g, ib, s);
+            cx<C> v[3];
+            load_spin(v, rsrc, g, ib, s, j);
             if (a.gather) {
-                cx<C> h[12], fh[12];
-                hop_site<2>(h, g, ib, s, U, FieldSrc<S2, C>{x});
-                clover_mul(fh, h, F, g, ib, s);
+                const LaneNbr n = lane_nbr(nb_lds[j * g.Vb + s], ib, bl_f, bl_b, bc);
+                cx<C> h[12], fh[3];
+                quad_hop_sum<HOP_OUT, (NT > 512)>(h, g, ib, s, j, n, U, FieldSrc<S2, C>{x});
+                lane_clover(fh, h, F, g, ib, s, j);
 #pragma unroll
-                for (int c = 0; c < 12; ++c) v[c] = v[c] + kappa * fh[c];
+                for (int c = 0; c < 3; ++c) v[c] = v[c] + kappa * fh[c];
             }
-            store_spinor(r, g, ib, s, v);
+            store_spin(r, g, ib, s, j, v);
         }
 #pragma unroll
-        for (int c = 0; c < 12; ++c) xs[c * g.Vb + s] = make_float2(0.f, 0.f);
+        for (int c = 0; c < 3; ++c) xs[(3 * j + c) * g.Vb + s] = make_float2(0.f, 0.f);
     }
     __syncthreads();
 
-    // 2. SSOR sweeps: x_n <- (1-omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m)
-    const BlockSrc bs{xs};
+    // 2. sweeps: x_n <- (1-omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m)
     for (int sw = 0; sw < a.n_ssor; ++sw) {
         for (int dir = 0; dir < 2; ++dir) {
             for (int pi = 0; pi < g.nplanes; ++pi) {
                 const int p = dir == 0 ? pi : g.nplanes - 1 - pi;
-                const int s0 = g.plane_start[p], s1 = g.plane_start[p + 1];
-                for (int s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
-                    cx<C> h[12], fh[12], v[12];
-                    hop_site<1>(h, g, ib, s, U, bs);
-                    clover_mul(fh, h, F, g, ib, s);
-                    load_spinor(v, vb, g, ib, s);
+                const int s0 = ps_lds[p], s1 = ps_lds[p + 1];
+                for (int s = s0 + q0; s < s1; s += nq) {
+                    const LaneNbr n = lane_nbr(nb_lds[j * g.Vb + s], ib, bl_f, bl_b, bc);
+                    cx<C> h[12], fh[3], v[3];
+                    quad_hop_sum<HOP_IN, (NT > 512)>(h, g, ib, s, j, n, U, bs);
+                    if (NT > 512) __builtin_amdgcn_sched_barrier(0);
+                    lane_clover(fh, h, F, g, ib, s, j);
+                    load_spin(v, vb, g, ib, s, j);
 #pragma unroll
-                    for (int c = 0; c < 12; ++c) {
-                        float2 o = xs[c * g.Vb + s];
+                    for (int c = 0; c < 3; ++c) {
+                        float2 *o = &xs[(3 * j + c) * g.Vb + s];
+                        float2 ov = *o;
                         cx<C> nx = v[c] + kappa * fh[c];
-                        xs[c * g.Vb + s] = make_float2((1.f - omega) * o.x + omega * nx.r, (1.f - omega) * o.y + omega * nx.i);
+                        *o = make_float2((1.f - omega) * ov.x + omega * nx.r, (1.f - omega) * ov.y + omega * nx.i);
                     }
                 }
                 __syncthreads();
@@ -249,49 +432,58 @@ __global__ void __launch_bounds__(512) k_sap_phase(GeomDev g, SapArgs a, const t
     }
 
     // 3. outputs
-    for (int s = threadIdx.x; s < g.Vb; s += blockDim.x) {
-        cx<C> xv[12];
-        bs.get(xv, g, ib, s);
-        store_spinor(x, g, ib, s, xv);
+    for (int s = q0; s < g.Vb; s += nq) {
+        cx<C> xv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float2 t = xs[(3 * j + c) * g.Vb + s];
+            xv[c] = {t.x, t.y};
+        }
+        store_spin(x, g, ib, s, j, xv);
         if (a.ssor_only) continue;
-        cx<C> yv[12];
+        cx<C> yv[3];
         if (a.first) {
 #pragma unroll
-            for (int c = 0; c < 12; ++c) yv[c] = xv[c];
+            for (int c = 0; c < 3; ++c) yv[c] = xv[c];
         } else {
-            load_spinor(yv, y, g, ib, s);
+            load_spin(yv, y, g, ib, s, j);
 #pragma unroll
-            for (int c = 0; c < 12; ++c) yv[c] = yv[c] + xv[c];
+            for (int c = 0; c < 3; ++c) yv[c] = yv[c] + xv[c];
         }
-        store_spinor(y, g, ib, s, yv);
-        cx<C> h[12], fh[12], v[12];
-        hop_site<1>(h, g, ib, s, U, bs);
-        clover_mul(fh, h, F, g, ib, s);
-        load_spinor(v, r, g, ib, s);
+        store_spin(y, g, ib, s, j, yv);
+        const LaneNbr n = lane_nbr(nb_lds[j * g.Vb + s], ib, bl_f, bl_b, bc);
+        cx<C> h[12], fh[3], v[3];
+        quad_hop_sum<HOP_IN, (NT > 512)>(h, g, ib, s, j, n, U, bs);
+        lane_clover(fh, h, F, g, ib, s, j);
+        load_spin(v, r, g, ib, s, j);
 #pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = v[c] - xv[c] + kappa * fh[c];
-        store_spinor(r, g, ib, s, v);
+        for (int c = 0; c < 3; ++c) v[c] = v[c] - xv[c] + kappa * fh[c];
+        store_spin(r, g, ib, s, j, v);
     }
 }
 
-// r_c += kappa F sum_{hops leaving the block} H x   (r_c -= D_{c,other} x_other), one thread per site
+// r_c += kappa F sum_{hops leaving the block} H x   (r_c -= D_{c,other} x_other); four lanes per site
 template <int P>
 __global__ void __launch_bounds__(256) k_sap_face(GeomDev g, int colour, float kappa, typename Prec<P>::S2 *r,
                                                  const typename Prec<P>::S2 *x, const typename Prec<P>::S2 *__restrict__ U,
                                                  const typename Prec<P>::S2 *__restrict__ F) {
     using S2 = typename Prec<P>::S2;
     using C = float;
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    long nc = (long)g.NBc * g.Vb;
+    const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long i = gt >> 2;
+    const int j = (int)(gt & 3);
+    const long nc = (long)g.NBc * g.Vb;
     if (i >= nc) return;
-    int ib = colour * g.NBc + (int)(i / g.Vb), s = (int)(i % g.Vb);
-    cx<C> h[12], fh[12], v[12];
-    hop_site<2>(h, g, ib, s, U, FieldSrc<S2, C>{x});
-    clover_mul(fh, h, F, g, ib, s);
-    load_spinor(v, r, g, ib, s);
+    const int ib = colour * g.NBc + (int)(i / g.Vb), s = (int)(i % g.Vb);
+    const LaneNbr n = lane_nbr(g.nbr16[j * g.Vb + s], ib, g.blk_nbr[(2 * j) * g.NB + ib], g.blk_nbr[(2 * j + 1) * g.NB + ib],
+                               g.bc[j]);
+    cx<C> h[12], fh[3], v[3];
+    quad_hop_sum<HOP_OUT, false>(h, g, ib, s, j, n, U, FieldSrc<S2, C>{x});
+    lane_clover(fh, h, F, g, ib, s, j);
+    load_spin(v, r, g, ib, s, j);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) v[c] = v[c] + kappa * fh[c];
-    store_spinor(r, g, ib, s, v);
+    for (int c = 0; c < 3; ++c) v[c] = v[c] + kappa * fh[c];
+    store_spin(r, g, ib, s, j, v);
 }
 
 // ================================================================ BLAS-1
@@ -343,14 +535,24 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, int nd, const ty
     }
 }
 
-// final sum of the partials, fixed order
-__global__ void __launch_bounds__(64) k_dots_final(int nblocks, const double2 *partials, double2 *out) {
-    const int k = threadIdx.x;  // 0..5
-    if (k >= 6) return;
-    double v = 0;
+// final sum of the partials: a fixed pairwise tree (256 threads)
+__global__ void __launch_bounds__(256) k_dots_final(int nblocks, const double2 *partials, double2 *out) {
+    __shared__ double sm[6][256];
     const double *pp = reinterpret_cast<const double *>(partials);
-    for (int b = 0; b < nblocks; ++b) v += pp[(size_t)b * 6 + k];
-    reinterpret_cast<double *>(out)[k] = v;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] += pp[(size_t)b * 6 + k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sm[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) reinterpret_cast<double *>(out)[threadIdx.x] = sm[threadIdx.x][0];
 }
 
 template <int P>
@@ -448,32 +650,56 @@ void launch_pack_clover(Ctx *c, const double *F) {
 
 void launch_dslash(Ctx *c, int prec, void *out, const void *in) {
     if (prec == SAPQ_FP64) {
-        k_dslash<SAPQ_FP64><<<grid_for(c->V, 256), 256, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in,
+        k_dslash<SAPQ_FP64><<<grid_for(4 * c->V, 256), 256, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in,
                                                                          c->U64, c->F64, c->prm.kappa);
         return;
     }
-    INNER_SWITCH(prec, (k_dslash<P_><<<grid_for(c->V, 256), 256, 0, c->stream>>>(
+    INNER_SWITCH(prec, (k_dslash<P_><<<grid_for(4 * c->V, 256), 256, 0, c->stream>>>(
                            c->g, (typename Prec<P_>::S2 *)out, (const typename Prec<P_>::S2 *)in,
                            (const typename Prec<P_>::S2 *)c->Uin, (const typename Prec<P_>::S2 *)c->Fin, c->prm.kappa)));
 }
 
-template <int P>
-static void sap_phase_t(Ctx *c, const SapArgs &a, const void *rsrc, void *r, void *x, void *y) {
+template <int P, int NT>
+static void sap_phase_nt(Ctx *c, const SapArgs &a, const void *rsrc, void *r, void *x, void *y) {
     using S2 = typename Prec<P>::S2;
     dim3 grid(c->g.NBc), block(c->ssor_threads);
     if (c->ssor_lds)
-        k_sap_phase<P, true><<<grid, block, c->lds_bytes, c->stream>>>(
+        k_sap_phase<P, true, NT><<<grid, block, c->lds_bytes + c->lds_extra, c->stream>>>(
             c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin, c->ssor_scratch);
     else
-        k_sap_phase<P, false><<<grid, block, 0, c->stream>>>(
+        k_sap_phase<P, false, NT><<<grid, block, c->lds_extra, c->stream>>>(
             c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin, c->ssor_scratch);
 }
 
-void set_sap_lds_limits(Ctx *c) {
-    if (!c->ssor_lds || c->lds_bytes <= 65536) return;
-    hipFuncSetAttribute((const void *)k_sap_phase<SAPQ_FP32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
-    hipFuncSetAttribute((const void *)k_sap_phase<SAPQ_FP16, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
-    hipFuncSetAttribute((const void *)k_sap_phase<SAPQ_BF16, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->lds_bytes);
+template <int P>
+static void sap_phase_t(Ctx *c, const SapArgs &a, const void *rsrc, void *r, void *x, void *y) {
+    if (c->ssor_threads <= 512)
+        sap_phase_nt<P, 512>(c, a, rsrc, r, x, y);
+    else
+        sap_phase_nt<P, 1024>(c, a, rsrc, r, x, y);
+}
+
+template <int P>
+static void set_lds_limit(Ctx *c) {
+    // only sizes the device can grant are requested; the variant that is not used is left alone
+    if (c->ssor_lds) {
+        const int bytes = (int)(c->lds_bytes + c->lds_extra);
+        (void)hipFuncSetAttribute((const void *)k_sap_phase<P, true, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute((const void *)k_sap_phase<P, true, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    } else {
+        const int bytes = (int)c->lds_extra;
+        (void)hipFuncSetAttribute((const void *)k_sap_phase<P, false, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute((const void *)k_sap_phase<P, false, 1024>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    }
+}
+
+int set_sap_lds_limits(Ctx *c) {
+    const size_t need = c->ssor_lds ? c->lds_bytes + c->lds_extra : c->lds_extra;
+    if (need <= 65536) return 0;
+    set_lds_limit<SAPQ_FP32>(c);
+    set_lds_limit<SAPQ_FP16>(c);
+    set_lds_limit<SAPQ_BF16>(c);
+    return hipGetLastError() == hipSuccess ? 0 : -1;  // also clears the runtime's last-error slot
 }
 
 void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y) {
@@ -502,7 +728,7 @@ void launch_ssor_only(Ctx *c, int colour, const void *v, void *x) {
 
 void launch_sap_face(Ctx *c, int colour, void *r, const void *x) {
     long nc = (long)c->g.NBc * c->g.Vb;
-    INNER_SWITCH(c->prm.prec_inner, (k_sap_face<P_><<<grid_for(nc, 256), 256, 0, c->stream>>>(
+    INNER_SWITCH(c->prm.prec_inner, (k_sap_face<P_><<<grid_for(4 * nc, 256), 256, 0, c->stream>>>(
                                          c->g, colour, (float)c->prm.kappa, (typename Prec<P_>::S2 *)r,
                                          (const typename Prec<P_>::S2 *)x, (const typename Prec<P_>::S2 *)c->Uin,
                                          (const typename Prec<P_>::S2 *)c->Fin)));
@@ -516,7 +742,7 @@ void blas_dots(Ctx *c, int prec, int nd, const void *const *a, const void *const
                         (const S2 *)(nd > 1 ? b[1] : b[0]), (const S2 *)(nd > 2 ? a[2] : a[0]),
                         (const S2 *)(nd > 2 ? b[2] : b[0]), c->partials);
                 }));
-    k_dots_final<<<1, 64, 0, c->stream>>>(c->red_blocks, c->partials, c->dev_res);
+    k_dots_final<<<1, 256, 0, c->stream>>>(c->red_blocks, c->partials, c->dev_res);
     (void)hipMemcpyAsync(c->host_res, c->dev_res, sizeof(double2) * 3, hipMemcpyDeviceToHost, c->stream);
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < nd; ++k) host_out[k] = c->host_res[k];

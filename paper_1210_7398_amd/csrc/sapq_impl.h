@@ -39,6 +39,7 @@ struct GeomDev {
     int nplanes;      // hyperplanes per block
     float bc[4];      // boundary sign per direction
     const int *loc_nbr;     // [8][Vb]: >= 0 slot inside the block, else -1 - slot in the next block
+    const unsigned *nbr16;  // [4][Vb]: forward | backward << 16 slots of direction mu, bit 15/31 = inside
     const int *blk_nbr;     // [8][NB]: neighbouring block id | WRAP_BIT
     const int *plane_start; // [nplanes + 1]
     const int *slot_lex;    // [Vb] block-local lexicographic index of each slot
@@ -250,7 +251,8 @@ struct Ctx {
     int max_plane;
     int ssor_threads;
     bool ssor_lds;
-    size_t lds_bytes;
+    size_t lds_bytes;   // SSOR iterate in LDS
+    size_t lds_extra;   // neighbour words and plane starts in LDS
     long V;
     size_t nvec;  // 12 V complex entries
     // fields

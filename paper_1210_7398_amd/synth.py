@@ -95,26 +95,33 @@ def gamma_matrices():
 
 
 def _shift(f, L, mu, step):
-    """Field at n + step*mu (periodic), for f of shape [V, ...]."""
+    """Field at n + step*mu (periodic), for a torch tensor f of shape [V, ...]."""
+    import torch
+
     Lx, Ly, Lz, Lt = L
-    axis = 3 - mu
-    g = f.reshape((Lt, Lz, Ly, Lx) + f.shape[1:])
-    return np.roll(g, -step, axis=axis).reshape(f.shape)
+    g = f.reshape((Lt, Lz, Ly, Lx) + tuple(f.shape[1:]))
+    return torch.roll(g, -step, dims=3 - mu).reshape(f.shape)
 
 
 def clover_inverse(L, U, csw, kappa):
     """Inverse clover field F(n) = (1 - c_SW kappa sum_{mu<nu} sigma_mu_nu F_mu_nu(n))^-1 as two
     chiral 6x6 blocks [V, 2, 6, 6]; F_mu_nu is the four-leaf clover (Q - Q^+)/(8i), traceless,
-    sigma_mu_nu = (i/2)[gamma_mu, gamma_nu].  Periodic gauge field (no fermion phases)."""
+    sigma_mu_nu = (i/2)[gamma_mu, gamma_nu].  Periodic gauge field (no fermion phases).
+    Computed with torch on the host (batched 3x3 products), returned as numpy."""
+    import torch
+
     V = volume(L)
     g = gamma_matrices()
-    dag = lambda m: np.swapaxes(m.conj(), -1, -2)
-    A = np.zeros((V, 12, 12), np.complex128)
-    A[:] = np.eye(12)
+    Ut = torch.from_numpy(np.ascontiguousarray(U))
+    dag = lambda m: m.conj().transpose(-1, -2)
+    # A is block diagonal in the chiral basis: build its two 6x6 blocks directly
+    A = torch.zeros((V, 2, 6, 6), dtype=torch.complex128)
+    A[:] = torch.eye(6, dtype=torch.complex128)
+    eye3 = torch.eye(3, dtype=torch.complex128)
     for mu in range(4):
         for nu in range(mu + 1, 4):
-            Umu = U[:, mu]
-            Unu = U[:, nu]
+            Umu = Ut[:, mu].contiguous()
+            Unu = Ut[:, nu].contiguous()
             Umu_pnu = _shift(Umu, L, nu, 1)
             Unu_pmu = _shift(Unu, L, mu, 1)
             Umu_mmu = _shift(Umu, L, mu, -1)
@@ -130,12 +137,14 @@ def clover_inverse(L, U, csw, kappa):
             Q += dag(Umu_mmu) @ dag(Unu_mmu_mnu) @ Umu_mmu_mnu @ Unu_mnu
             Q += dag(Unu_mnu) @ Umu_mnu @ Unu_pmu_mnu @ dag(Umu)
             Fmn = (Q - dag(Q)) / 8j
-            tr = np.trace(Fmn, axis1=1, axis2=2) / 3.0
-            Fmn -= tr[:, None, None] * np.eye(3)
-            sig = 0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu])
-            A -= csw * kappa * np.einsum("ab,nij->naibj", sig, Fmn).reshape(V, 12, 12)
-    blocks = np.stack([A[:, 0:6, 0:6], A[:, 6:12, 6:12]], axis=1)
-    return np.linalg.inv(blocks)
+            tr = Fmn.diagonal(dim1=1, dim2=2).sum(-1) / 3.0
+            Fmn -= tr[:, None, None] * eye3
+            sig = torch.from_numpy(0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu]))
+            for k in range(2):
+                sk = sig[2 * k : 2 * k + 2, 2 * k : 2 * k + 2]
+                blk = sk[None, :, None, :, None] * Fmn[:, None, :, None, :]
+                A[:, k] -= csw * kappa * blk.reshape(V, 6, 6)
+    return np.ascontiguousarray(torch.linalg.inv(A).numpy())
 
 
 def unit_clover(L):

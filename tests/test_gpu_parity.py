@@ -114,3 +114,50 @@ def test_solve_true_residual(torch_cuda, orc, name, outer):
     xo, sto, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
     assert ok
     assert relerr(x, xo) < 1e-8
+
+
+# ---------------------------------------------------------------- storage precisions
+# FP16 has a 2^-11 unit roundoff and BF16 2^-8; one operator application inherits a few of
+# them from the rounded fields and input, the SAP chain a few more per stored vector.
+PREC_TOL = {
+    "fp16": dict(dslash=2e-3, ssor=5e-3, msap=1e-2),
+    "bf16": dict(dslash=2e-2, ssor=4e-2, msap=8e-2),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("name", ["8^4/4^4/2^4", "12^3x24/6^3x12/3^3x6"])
+def test_low_precision_storage(torch_cuda, orc, name, prec):
+    L, B, S, kappa, eps, bc = GEOMS[name]
+    U, F = fields(name)
+    tol = PREC_TOL[prec]
+    s = make_solver(name, prec=prec)
+    psi = synth.gaussian_spinor(L, 111)
+    want = orc.dslash(L, U, F, kappa, psi, bc=bc)
+    assert relerr(to_host(s.dslash(to_dev(psi), prec)), want) < tol["dslash"]
+    assert relerr(to_host(s.dslash(to_dev(psi), "fp64")), want) < 1e-14  # FP64 copy untouched
+    prm = orc.params(kappa)
+    x_w = orc.ssor(L, B, S, U, F, prm, 0, psi, bc=bc)
+    assert relerr(to_host(s.ssor(to_dev(psi), 0)), x_w) < tol["ssor"]
+    y_w, dy_w = orc.msap(L, B, S, U, F, prm, psi, bc=bc)
+    y, dy = (to_host(t) for t in s.sap_precondition(to_dev(psi)))
+    assert relerr(y, y_w) < tol["msap"]
+    assert relerr(dy, dy_w) < tol["msap"]
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("outer", ["defect", "fbicgstab"])
+def test_low_precision_solve(torch_cuda, orc, prec, outer):
+    """FP16/BF16 storage inside, FP64 outside: the FP64 true residual still reaches 1e-10 and
+    the solution agrees with the oracle's to the accuracy the residual implies."""
+    name = "8^4/4^4/2^4"
+    L, B, S, kappa, eps, bc = GEOMS[name]
+    U, F = fields(name)
+    s = make_solver(name, prec=prec, outer=outer, maxit_outer=200)
+    b = synth.gaussian_spinor(L, 112)
+    x, st = s.solve(to_dev(b), tol=1e-10)
+    x = to_host(x)
+    rr = relerr(orc.dslash(L, U, F, kappa, x, bc=bc), b)
+    assert rr <= 1e-10, (rr, st)
+    xo, _, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
+    assert ok and relerr(x, xo) < 1e-8
