@@ -93,6 +93,8 @@ typedef struct {
 
 #define SAPQ_FLAG_GUESS 1   /* sapq_solve starts from the x passed in */
 #define SAPQ_FLAG_PROFILE 2 /* sapq_solve times its kernels with HIP events (see sapq_stats) */
+#define SAPQ_FLAG_NN 4      /* reserve the learned stage (at sapq_create) and use it in the inner
+                               solver once weights are set (see sapq_nn_*) */
 
 /* Per-solve statistics (host struct). */
 typedef struct {
@@ -178,6 +180,50 @@ int sapq_inner_solve(sapq_ctx *ctx, double *e, const double *r, int *iters);
  * solution on return.  stats (host, nullable).  SAPQ_ENOTCONV leaves the best iterate.
  */
 int sapq_solve(sapq_ctx *ctx, double *x, const double *b, double tol, sapq_stats *stats);
+
+/*
+ * Learned gauge-covariant preconditioner stage (not in the paper; an extension of its
+ * inner preconditioner).  N is three linear parallel-transport convolution layers with
+ * channels 1 -> SAPQ_NN_CHANNELS -> SAPQ_NN_CHANNELS -> 1; a layer maps c_in spinor
+ * channels to c_out as
+ *     out[c'](n) = sum_{d=0..8} sum_c W[d][c'][c] (T_d in[c])(n)
+ * with W[d][c'][c] a 4x4 complex spin matrix, T_0 = 1, T_{1+2mu} psi(n) = U_mu(n) psi(n+mu),
+ * T_{2+2mu} psi(n) = U_mu(n-mu)^+ psi(n-mu) (boundary signs as in D).  With the stage on, the
+ * inner solver's preconditioner becomes z = N r + M_SAP (r - D N r), which is linear in r,
+ * so the inner BiCGStab still sees a fixed operator, and plain SAP is the fallback.
+ * Weight blob: sapq_nn_param_count() floats, layer after layer, W[9][c_out][c_in][4][4]
+ * complex as (re, im) pairs.  The layers compute in FP32 with the weights rounded to BF16;
+ * Adam keeps FP32 master weights.  All sapq_nn_* calls need a context created with
+ * params.flags & SAPQ_FLAG_NN (else SAPQ_ESTATE); training needs prec_inner = SAPQ_FP32.
+ */
+#define SAPQ_NN_CHANNELS 8
+size_t sapq_nn_param_count(void);
+
+/* Set the weights (device float array) and reset the Adam moments; enables the stage. */
+int sapq_nn_set_weights(sapq_ctx *ctx, const float *w);
+
+/* Copy the FP32 master weights out (device float array). */
+int sapq_nn_get_weights(sapq_ctx *ctx, float *w);
+
+/* out = N in (spinor layout, FP64 at the boundary, FP32 inside). */
+int sapq_nn_forward(sapq_ctx *ctx, double *out, const double *in);
+
+/*
+ * Gradients of a real loss L(N in) given grad_out = dL/dRe z + i dL/dIm z at z = N in:
+ * grad_w (device float, sapq_nn_param_count()) = dL/dRe W + i dL/dIm W in the blob layout,
+ * grad_in (nullable) = N^+ grad_out.
+ */
+int sapq_nn_backward(sapq_ctx *ctx, float *grad_w, double *grad_in, const double *grad_out, const double *in);
+
+/*
+ * One Adam step (lr, step count t >= 1) on the mean over a batch of the loss
+ * |N(D e) - e|^2 / |e|^2.  e: device float array of n_vec error vectors, each in the spinor
+ * layout as (re, im) float pairs ([n_vec][V][4][3][2]); idx (host): the batch's batch indices
+ * into it.  The residual r = D e is formed on the device in FP32.  *loss (host, nullable):
+ * the batch mean before the step.
+ */
+int sapq_nn_train_step(sapq_ctx *ctx, const float *e, long n_vec, const int *idx, int batch, float lr, int t,
+                       double *loss);
 
 /* Release the context (host memory only; the arena stays the caller's). */
 void sapq_destroy(sapq_ctx *ctx);

@@ -188,3 +188,104 @@ def solve(L, B, S, U, F, prm, b, tol=1e-10, x0=None, bc=(1, 1, 1, 1)):
     )
     stats = dict(outer=int(st[0]), inner=int(st[1]), relres=float(st[2]), restarts=int(st[3]))
     return x, stats, rc == 0
+
+
+# ----------------------------------------------------------------------------- learned stage
+# Three linear parallel-transport convolution layers, channels 1 -> 8 -> 8 -> 1.  Weight blob
+# (the library's layout): float32, layer by layer, W[9][c_out][c_in][4][4] complex as (re, im).
+NN_CHANNELS = 8
+NN_SHAPES = [(1, NN_CHANNELS), (NN_CHANNELS, NN_CHANNELS), (NN_CHANNELS, 1)]  # (c_in, c_out)
+
+
+def nn_param_count():
+    return sum(2 * 16 * 9 * ci * co for ci, co in NN_SHAPES)
+
+
+def nn_unflatten(w):
+    """Flat float blob -> list of complex128 arrays W[9][c_out][c_in][4][4]."""
+    w = np.asarray(w, np.float64)
+    out, off = [], 0
+    for ci, co in NN_SHAPES:
+        n = 2 * 16 * 9 * ci * co
+        a = w[off : off + n].reshape(9, co, ci, 4, 4, 2)
+        out.append(np.ascontiguousarray(a[..., 0] + 1j * a[..., 1]))
+        off += n
+    return out
+
+
+def nn_flatten(Ws):
+    return np.concatenate([np.stack([W.real, W.imag], -1).reshape(-1) for W in Ws]).astype(np.float64)
+
+
+def _gbc(L, bc):
+    return _geom(L, None, None, bc)
+
+
+def nn_layer(L, U, W, x, bc=(1, 1, 1, 1)):
+    """out[c'] = sum_d sum_c W[d][c'][c] T_d x[c] for x [c_in, V, 4, 3]."""
+    cout, cin = W.shape[1], W.shape[2]
+    x = np.ascontiguousarray(x, np.complex128)
+    out = np.zeros((cout,) + x.shape[1:], np.complex128)
+    lib().orc_nn_layer(_gbc(L, bc), _p(U), _p(np.ascontiguousarray(W)), ctypes.c_int(cin), ctypes.c_int(cout),
+                       _p(x), _p(out))
+    return out
+
+
+def nn_layer_adjoint(L, U, W, gout, bc=(1, 1, 1, 1)):
+    cout, cin = W.shape[1], W.shape[2]
+    gout = np.ascontiguousarray(gout, np.complex128)
+    gin = np.zeros((cin,) + gout.shape[1:], np.complex128)
+    lib().orc_nn_layer_adjoint(_gbc(L, bc), _p(U), _p(np.ascontiguousarray(W)), ctypes.c_int(cin), ctypes.c_int(cout),
+                               _p(gout), _p(gin))
+    return gin
+
+
+def nn_layer_wgrad(L, U, cin, cout, gout, x, bc=(1, 1, 1, 1)):
+    G = np.zeros((9, cout, cin, 4, 4), np.complex128)
+    lib().orc_nn_layer_wgrad(_gbc(L, bc), _p(U), ctypes.c_int(cin), ctypes.c_int(cout),
+                             _p(np.ascontiguousarray(gout, np.complex128)), _p(np.ascontiguousarray(x, np.complex128)),
+                             _p(G))
+    return G
+
+
+def nn_forward(L, U, Ws, r, bc=(1, 1, 1, 1)):
+    """z = N r for a spinor r [V, 4, 3]; returns (z, activations of every layer input)."""
+    acts = [r[None]]
+    for W in Ws:
+        acts.append(nn_layer(L, U, W, acts[-1], bc))
+    return acts[-1][0], acts[:-1]
+
+
+def nn_backward(L, U, Ws, r, gz, bc=(1, 1, 1, 1)):
+    """Weight gradients dL/dRe W + i dL/dIm W and N^+ gz for dL/dz = gz at z = N r, by the chain
+    rule through the layers (each layer's input gradient is its adjoint applied to its output
+    gradient)."""
+    _, acts = nn_forward(L, U, Ws, r, bc)
+    g = np.asarray(gz, np.complex128)[None]
+    grads = [None] * len(Ws)
+    for k in range(len(Ws) - 1, -1, -1):
+        W = Ws[k]
+        grads[k] = nn_layer_wgrad(L, U, W.shape[2], W.shape[1], g, acts[k], bc)
+        g = nn_layer_adjoint(L, U, W, g, bc)
+    return grads, g[0]
+
+
+def nn_loss_grad(L, U, Ws, r, e, bc=(1, 1, 1, 1)):
+    """loss = |N r - e|^2 / |e|^2 and its gradients dL/dRe W + i dL/dIm W."""
+    z, _ = nn_forward(L, U, Ws, r, bc)
+    ee = float(np.vdot(e, e).real)
+    loss = float(np.vdot(z - e, z - e).real) / ee
+    grads, _ = nn_backward(L, U, Ws, r, (2.0 / ee) * (z - e), bc)
+    return loss, grads
+
+
+def adam_step(p, grad, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba) of real arrays, in place; t counts from 1."""
+    m *= b1
+    m += (1 - b1) * grad
+    v *= b2
+    v += (1 - b2) * grad * grad
+    mh = m / (1 - b1**t)
+    vh = v / (1 - b2**t)
+    p -= lr * mh / (np.sqrt(vh) + eps)
+    return p

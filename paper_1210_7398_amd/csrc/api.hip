@@ -203,6 +203,18 @@ static void carve(Ctx *c, Arena &A, const HostTables &T) {
     void **din[] = {&c->i_r, &c->i_rt, &c->i_p, &c->i_v, &c->i_s, &c->i_t, &c->i_e, &c->i_ph, &c->i_sh, &c->i_rin, &c->i_tmp, &c->sap_r, &c->sap_x};
     for (auto p : din) *p = A.take(nv * eb);
     c->ssor_scratch = c->ssor_lds ? nullptr : (float2 *)A.take(nv * 8);
+    if (c->prm.flags & SAPQ_FLAG_NN) {
+        c->nn_alloc = true;
+        float **w[] = {&c->nn_w, &c->nn_wq, &c->nn_G, &c->nn_m, &c->nn_v};
+        for (auto p : w) *p = (float *)A.take(NN_PARAMS * sizeof(float));
+        c->nn_wt = (float2 *)A.take(9 * NN_C * NN_C * 16 * sizeof(float2));
+        struct { float2 **p; int ch; } f[] = {{&c->nn_a0, 1}, {&c->nn_a1, NN_C}, {&c->nn_a2, NN_C}, {&c->nn_z, 1},
+                                               {&c->nn_gz, 1}, {&c->nn_g2, NN_C}, {&c->nn_g1, NN_C}, {&c->nn_gin, 1},
+                                               {&c->nn_e, 1}};
+        for (auto &e : f) *e.p = (float2 *)A.take(nv * e.ch * sizeof(float2));
+        c->i_z = A.take(nv * eb);
+        c->i_rp = A.take(nv * eb);
+    }
     c->partials = (double2 *)A.take(RED_BLOCKS * 3 * sizeof(double2));
     c->dev_res = (double2 *)A.take(8 * sizeof(double2));
     c->dev_dev = (double *)A.take(((V + 255) / 256) * sizeof(double));
@@ -294,6 +306,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
         return SAPQ_ENOMEM;
     }
     Arena A{(char *)arena, arena_bytes, 0};
+    c->nn_alloc = false;
     carve(c, A, T);
     c->stream = (hipStream_t)stream;
     c->g.Vb = T.Vb;
@@ -427,6 +440,37 @@ static void msap(Ctx *c, const void *v, void *y) {
     c->n_msap++;
 }
 
+}  // extern "C"
+
+namespace sapq {
+
+// z = N r on FP32 internal fields (nn_a0 holds r; activations stay for a backward pass)
+static void nn_forward(Ctx *c) {
+    const float2 *W = (const float2 *)c->nn_wq;
+    launch_nn_layer(c, NN_CIN[0], NN_COUT[0], c->nn_a0, c->nn_a1, W + NN_OFF[0] / 2);
+    launch_nn_layer(c, NN_CIN[1], NN_COUT[1], c->nn_a1, c->nn_a2, W + NN_OFF[1] / 2);
+    launch_nn_layer(c, NN_CIN[2], NN_COUT[2], c->nn_a2, c->nn_z, W + NN_OFF[2] / 2);
+}
+
+// nn_G += dL/dW and nn_gin = N^+ nn_gz, for the activations of the last nn_forward
+static void nn_backward(Ctx *c) {
+    const float2 *W = (const float2 *)c->nn_wq;
+    float2 *G = (float2 *)c->nn_G;
+    const float2 *acts[3] = {c->nn_a0, c->nn_a1, c->nn_a2};
+    float2 *gin[3] = {c->nn_gin, c->nn_g1, c->nn_g2};
+    const float2 *gout = c->nn_gz;
+    for (int k = 2; k >= 0; --k) {
+        launch_nn_wgrad(c, NN_CIN[k], NN_COUT[k], gout, acts[k], G + NN_OFF[k] / 2);
+        launch_nn_adjoint_weights(c, NN_CIN[k], NN_COUT[k], W + NN_OFF[k] / 2, c->nn_wt);
+        launch_nn_layer(c, NN_COUT[k], NN_CIN[k], gout, gin[k], c->nn_wt);
+        gout = gin[k];
+    }
+}
+
+}  // namespace sapq
+
+extern "C" {
+
 int sapq_dk(sapq_ctx *h, double *x, double *w, const double *v) {
     if (!h || !x || !w || !v) { set_error("null argument"); return SAPQ_EINVAL; }
     Ctx *c = &h->c;
@@ -474,6 +518,24 @@ static double2 dot1(Ctx *c, int prec, const void *a, const void *b) {
     return r;
 }
 
+// The inner preconditioner: ph = M_SAP p, or with the learned stage ph = z + M_SAP (p - D z),
+// z = N p.  Either way D ph = p - r_N comes out of the SAP recurrence: v = p - sap_r.
+static void precondition(Ctx *c, const void *p, void *ph) {
+    const int pi = c->prm.prec_inner;
+    if (!(c->have_nn && (c->prm.flags & SAPQ_FLAG_NN))) {
+        msap(c, p, ph);
+        return;
+    }
+    blas_convert(c, SAPQ_FP32, c->nn_a0, pi, p, 1.0);
+    nn_forward(c);
+    blas_convert(c, pi, c->i_z, SAPQ_FP32, c->nn_z, 1.0);
+    launch_dslash(c, pi, c->i_rp, c->i_z);
+    blas_xpay(c, pi, c->i_rp, p, make_double2(-1, 0), c->i_rp);  // r' = p - D z
+    msap(c, c->i_rp, ph);
+    blas_xpay(c, pi, ph, ph, make_double2(1, 0), c->i_z);         // ph = M r' + z
+    // the SAP recurrence left sap_r = r' - D M r', so p - sap_r = D z + D M r' = D ph
+}
+
 // Inner BiCGStab (right-preconditioned by M_SAP) on inner-precision vectors, e from 0.
 static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
     const int pi = c->prm.prec_inner;
@@ -495,7 +557,7 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
         if (std::abs(rho) == 0) break;
         zc beta = (rho / rho_old) * (alpha / om);
         blas_bicg_p(c, pi, c->i_p, c->i_r, D2(beta), D2(om), c->i_v);
-        msap(c, c->i_p, c->i_ph);                                     // p^ = M p
+        precondition(c, c->i_p, c->i_ph);                             // p^ = M p
         blas_xpay(c, pi, c->i_v, c->i_p, make_double2(-1, 0), c->sap_r);  // v = D p^ = p - r_N
         zc rv = Z(dot1(c, pi, c->i_rt, c->i_v));
         if (std::abs(rv) == 0) break;
@@ -507,7 +569,7 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
             blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, make_double2(0, 0), c->i_ph);
             break;
         }
-        msap(c, c->i_s, c->i_sh);                                     // s^ = M s
+        precondition(c, c->i_s, c->i_sh);                             // s^ = M s
         blas_xpay(c, pi, c->i_t, c->i_s, make_double2(-1, 0), c->sap_r);  // t = D s^
         {
             const void *A[2] = {c->i_t, c->i_t}, *B[2] = {c->i_s, c->i_t};
@@ -643,6 +705,92 @@ static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
 }  // namespace sapq
 
 extern "C" {
+
+size_t sapq_nn_param_count(void) { return (size_t)NN_PARAMS; }
+
+static int nn_ready(Ctx *c, bool need_weights) {
+    if (!c->nn_alloc) { set_error("context was created without SAPQ_FLAG_NN"); return SAPQ_ESTATE; }
+    if (!c->have_U) { set_error("gauge field must be loaded first"); return SAPQ_ESTATE; }
+    if (need_weights && !c->have_nn) { set_error("network weights are not set"); return SAPQ_ESTATE; }
+    return SAPQ_OK;
+}
+
+int sapq_nn_set_weights(sapq_ctx *h, const float *w) {
+    if (!h || !w) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = nn_ready(c, false);
+    if (rc) return rc;
+    (void)hipMemcpyAsync(c->nn_w, w, NN_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemsetAsync(c->nn_m, 0, NN_PARAMS * sizeof(float), c->stream);
+    (void)hipMemsetAsync(c->nn_v, 0, NN_PARAMS * sizeof(float), c->stream);
+    launch_nn_round(c, NN_PARAMS, c->nn_w, c->nn_wq);
+    rc = hipcheck(hipGetLastError(), "sapq_nn_set_weights");
+    if (rc == SAPQ_OK) c->have_nn = true;
+    return rc;
+}
+
+int sapq_nn_get_weights(sapq_ctx *h, float *w) {
+    if (!h || !w) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = nn_ready(c, true);
+    if (rc) return rc;
+    (void)hipMemcpyAsync(w, c->nn_w, NN_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    return hipcheck(hipGetLastError(), "sapq_nn_get_weights");
+}
+
+int sapq_nn_forward(sapq_ctx *h, double *out, const double *in) {
+    if (!h || !out || !in) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = nn_ready(c, true);
+    if (rc) return rc;
+    launch_pack_spinor(c, SAPQ_FP32, c->nn_a0, in, 1.0);
+    nn_forward(c);
+    launch_unpack_spinor(c, SAPQ_FP32, out, c->nn_z, 1.0);
+    return hipcheck(hipGetLastError(), "sapq_nn_forward");
+}
+
+int sapq_nn_backward(sapq_ctx *h, float *grad_w, double *grad_in, const double *grad_out, const double *in) {
+    if (!h || !grad_w || !grad_out || !in) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = nn_ready(c, true);
+    if (rc) return rc;
+    launch_pack_spinor(c, SAPQ_FP32, c->nn_a0, in, 1.0);
+    nn_forward(c);
+    launch_pack_spinor(c, SAPQ_FP32, c->nn_gz, grad_out, 1.0);
+    (void)hipMemsetAsync(c->nn_G, 0, NN_PARAMS * sizeof(float), c->stream);
+    nn_backward(c);
+    (void)hipMemcpyAsync(grad_w, c->nn_G, NN_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    if (grad_in) launch_unpack_spinor(c, SAPQ_FP32, grad_in, c->nn_gin, 1.0);
+    return hipcheck(hipGetLastError(), "sapq_nn_backward");
+}
+
+int sapq_nn_train_step(sapq_ctx *h, const float *e, long n_vec, const int *idx, int batch, float lr, int t,
+                       double *loss) {
+    if (!h || !e || !idx || batch < 1 || n_vec < 1 || t < 1 || !(lr > 0)) { set_error("bad argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = nn_ready(c, true);
+    if (rc) return rc;
+    if (!c->have_F) { set_error("clover field must be loaded first"); return SAPQ_ESTATE; }
+    if (c->prm.prec_inner != SAPQ_FP32) { set_error("training needs prec_inner = SAPQ_FP32"); return SAPQ_EINVAL; }
+    for (int k = 0; k < batch; ++k)
+        if (idx[k] < 0 || idx[k] >= n_vec) { set_error("batch index out of range"); return SAPQ_EINVAL; }
+    (void)hipMemsetAsync(c->nn_G, 0, NN_PARAMS * sizeof(float), c->stream);
+    double total = 0;
+    for (int k = 0; k < batch; ++k) {
+        launch_pack_spinor_f32(c, c->nn_e, e + (size_t)idx[k] * c->V * 24);
+        launch_dslash(c, SAPQ_FP32, c->nn_a0, c->nn_e);                       // r = D e
+        nn_forward(c);                                                        // z = N r
+        double2 ee = dot1(c, SAPQ_FP32, c->nn_e, c->nn_e);
+        blas_xpay(c, SAPQ_FP32, c->nn_gz, c->nn_z, make_double2(-1, 0), c->nn_e);  // z - e
+        double2 dd = dot1(c, SAPQ_FP32, c->nn_gz, c->nn_gz);
+        total += dd.x / ee.x;
+        blas_convert(c, SAPQ_FP32, c->nn_gz, SAPQ_FP32, c->nn_gz, 2.0 / ee.x);  // dL/dz = 2 (z - e) / |e|^2
+        nn_backward(c);
+    }
+    launch_nn_adam(c, NN_PARAMS, c->nn_w, c->nn_G, 1.f / batch, c->nn_m, c->nn_v, lr, t, c->nn_wq);
+    if (loss) *loss = total / batch;
+    return hipcheck(hipGetLastError(), "sapq_nn_train_step");
+}
 
 int sapq_inner_solve(sapq_ctx *h, double *e, const double *r, int *iters) {
     if (!h || !e || !r) { set_error("null argument"); return SAPQ_EINVAL; }

@@ -37,6 +37,17 @@ __global__ void k_pack_spinor(GeomDev g, typename Prec<P>::S2 *dst, const double
     }
 }
 
+// FP32 (re, im) pairs in the interchange layout -> FP32 internal layout
+__global__ void k_pack_spinor_f32(GeomDev g, float2 *dst, const float2 *src) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    const float2 *p = src + lex_site(g, ib, s) * 12;
+    float2 *q = dst + (size_t)ib * 12 * g.Vb + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) q[(size_t)c * g.Vb] = p[c];
+}
+
 template <int P>
 __global__ void k_unpack_spinor(GeomDev g, double2 *dst, const typename Prec<P>::S2 *src, double scale) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -624,6 +635,10 @@ void launch_pack_spinor(Ctx *c, int prec, void *dst, const double *src, double s
                           c->g, (typename Prec<P_>::S2 *)dst, (const double2 *)src, scale)));
 }
 
+void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src) {
+    k_pack_spinor_f32<<<grid_for(c->V, 256), 256, 0, c->stream>>>(c->g, (float2 *)dst, (const float2 *)src);
+}
+
 void launch_unpack_spinor(Ctx *c, int prec, double *dst, const void *src, double scale) {
     PREC_SWITCH(prec, (k_unpack_spinor<P_><<<grid_for(c->V, 256), 256, 0, c->stream>>>(
                           c->g, (double2 *)dst, (const typename Prec<P_>::S2 *)src, scale)));
@@ -776,7 +791,13 @@ void blas_axpbypz(Ctx *c, int prec, void *e, double2 a, const void *ph, double2 
 }
 
 void blas_convert(Ctx *c, int pd, void *dst, int ps, const void *src, double scale) {
-    if (pd == SAPQ_FP64) {
+    if (pd == SAPQ_FP32 && ps != SAPQ_FP64) {
+        INNER_SWITCH(ps, (k_convert<SAPQ_FP32, P_><<<BLAS_GRID, 256, 0, c->stream>>>(
+                             c->nvec, (float2 *)dst, (const typename Prec<P_>::S2 *)src, scale)));
+    } else if (ps == SAPQ_FP32 && pd != SAPQ_FP64) {
+        INNER_SWITCH(pd, (k_convert<P_, SAPQ_FP32><<<BLAS_GRID, 256, 0, c->stream>>>(
+                             c->nvec, (typename Prec<P_>::S2 *)dst, (const float2 *)src, scale)));
+    } else if (pd == SAPQ_FP64) {
         INNER_SWITCH(ps, (k_convert<SAPQ_FP64, P_><<<BLAS_GRID, 256, 0, c->stream>>>(
                              c->nvec, (double2 *)dst, (const typename Prec<P_>::S2 *)src, scale)));
     } else if (ps == SAPQ_FP64) {

@@ -1,0 +1,218 @@
+// Learned gauge-covariant preconditioner stage: linear parallel-transport convolution
+// layers, their adjoints and weight gradients, and the Adam update.
+//
+// A layer maps c_in spinor channels to c_out:
+//   out[c'](n) = sum_{d=0..8} sum_c W[d][c'][c] (T_d in[c])(n),  W[d][c'][c] a 4x4 complex spin matrix,
+//   T_0 = 1, T_{1+2mu} psi(n) = U_mu(n) psi(n+mu), T_{2+2mu} psi(n) = U_mu(n-mu)^+ psi(n-mu),
+// with the fermion boundary sign on hops that wrap.  Activations are FP32 fields in the
+// internal layout, one [NB][12][Vb] spinor field per channel.  The forward pass uses the
+// weights rounded to BF16 (FP32 arithmetic); Adam keeps an FP32 master copy.
+#include "sapq_impl.h"
+
+namespace sapq {
+
+// (T_d psi)(ib, s) for one FP32 channel field; links in storage precision P
+template <int P>
+__device__ __forceinline__ void nn_transport(cx<float> t[12], const float2 *__restrict__ psi, const GeomDev &g,
+                                             const typename Prec<P>::S2 *__restrict__ U, int ib, int s, int d) {
+    if (d == 0) {
+        load_spinor(t, psi, g, ib, s);
+        return;
+    }
+    const int mu = (d - 1) >> 1;
+    const bool fwd = ((d - 1) & 1) == 0;
+    const unsigned w = g.nbr16[mu * g.Vb + s];
+    const unsigned half = fwd ? (w & 0xffffu) : (w >> 16);
+    const int ns = (int)(half & 0x7fffu);
+    const bool inside = (half & 0x8000u) != 0;
+    int nb = ib;
+    float ph = 1.f;
+    if (!inside) {
+        const int bl = g.blk_nbr[(2 * mu + (fwd ? 0 : 1)) * g.NB + ib];
+        nb = bl & BLK_MASK;
+        ph = (bl & WRAP_BIT) ? g.bc[mu] : 1.f;
+    }
+    cx<float> p[12], u[9];
+    load_spinor(p, psi, g, nb, ns);
+    if (fwd)
+        load_link(u, U, g, ib, s, mu);
+    else
+        load_link(u, U, g, nb, ns, mu);
+#pragma unroll
+    for (int be = 0; be < 4; ++be) {
+        cx<float> h[3] = {p[3 * be], p[3 * be + 1], p[3 * be + 2]}, o[3];
+        su3_mul(o, u, h, !fwd);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t[3 * be + a] = ph * o[a];
+    }
+}
+
+// out[c'] for one output channel c' = blockIdx.y; weights W[9][COUT][CIN][16] complex (float2)
+template <int P, int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_nn_layer(GeomDev g, const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                 const float2 *__restrict__ W,
+                                                 const typename Prec<P>::S2 *__restrict__ U) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int co = blockIdx.y;
+    if (i >= g.V) return;
+    const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    const size_t chan = (size_t)g.V * 12;
+    cx<float> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
+    for (int d = 0; d < 9; ++d) {
+#pragma unroll 1
+        for (int ci = 0; ci < CIN; ++ci) {
+            cx<float> t[12];
+            nn_transport<P>(t, in + ci * chan, g, U, ib, s, d);
+            const float2 *w = W + (((size_t)d * COUT + co) * CIN + ci) * 16;
+#pragma unroll
+            for (int al = 0; al < 4; ++al)
+#pragma unroll
+                for (int be = 0; be < 4; ++be) {
+                    const float2 wv = w[4 * al + be];
+                    const cx<float> wc{wv.x, wv.y};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) acc[3 * al + a] = acc[3 * al + a] + cmul(wc, t[3 * be + a]);
+                }
+        }
+    }
+    store_spinor(out + co * chan, g, ib, s, acc);
+}
+
+// G[d][c'][c] (16 complex) = sum_n sum_a gout[c'](n)[al][a] conj((T_d in[c])(n)[be][a]), added to G.
+// One workgroup per (d, c', c); a fixed-order tree finishes the sum.
+template <int P>
+__global__ void __launch_bounds__(256) k_nn_wgrad(GeomDev g, int cin, int cout, const float2 *__restrict__ gout,
+                                                 const float2 *__restrict__ in, const typename Prec<P>::S2 *__restrict__ U,
+                                                 float2 *__restrict__ G) {
+    __shared__ float sm[32][257];
+    const int d = blockIdx.x, co = blockIdx.y, ci = blockIdx.z;
+    const size_t chan = (size_t)g.V * 12;
+    float acc[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) acc[k] = 0.f;
+    for (long i = threadIdx.x; i < g.V; i += blockDim.x) {
+        const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        cx<float> t[12], go[12];
+        nn_transport<P>(t, in + ci * chan, g, U, ib, s, d);
+        load_spinor(go, gout + co * chan, g, ib, s);
+#pragma unroll
+        for (int al = 0; al < 4; ++al)
+#pragma unroll
+            for (int be = 0; be < 4; ++be) {
+                cx<float> v = cxz<float>();
+#pragma unroll
+                for (int a = 0; a < 3; ++a) v = v + cmulc(t[3 * be + a], go[3 * al + a]);
+                acc[2 * (4 * al + be)] += v.r;
+                acc[2 * (4 * al + be) + 1] += v.i;
+            }
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) sm[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < 32; ++k) sm[k][threadIdx.x] += sm[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 16) {
+        float2 *p = G + (((size_t)d * cout + co) * cin + ci) * 16 + threadIdx.x;
+        float2 o = *p;
+        *p = make_float2(o.x + sm[2 * threadIdx.x][0], o.y + sm[2 * threadIdx.x + 1][0]);
+    }
+}
+
+// weights of the adjoint layer (it maps cout channels to cin):
+//   Wt[d][c][c'][a][b] = conj(W[rev(d)][c'][c][b][a]),  rev swaps +mu and -mu
+__global__ void k_nn_adjoint_weights(int cin, int cout, const float2 *__restrict__ W, float2 *__restrict__ Wt) {
+    const int n = 9 * cin * cout * 16;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int r = t;
+    const int b = r % 4; r /= 4;
+    const int a = r % 4; r /= 4;
+    const int cc = r % cout; r /= cout;  // input channel of the adjoint = output channel c' of W
+    const int ci = r % cin; r /= cin;    // output channel of the adjoint = input channel c of W
+    const int d = r;
+    const int rd = d == 0 ? 0 : (((d - 1) & 1) == 0 ? d + 1 : d - 1);
+    const float2 w = W[(((size_t)rd * cout + cc) * cin + ci) * 16 + 4 * b + a];
+    Wt[t] = make_float2(w.x, -w.y);
+}
+
+// Adam (Kingma and Ba) on the FP32 master weights; writes the BF16-rounded copy used by the layers
+__global__ void k_nn_adam(int n, float *__restrict__ w, const float *__restrict__ grad, float gscale,
+                          float *__restrict__ m, float *__restrict__ v, float lr, float b1, float b2, float eps, float c1,
+                          float c2, float *__restrict__ wq) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float gr = grad[t] * gscale;
+    const float mt = b1 * m[t] + (1.f - b1) * gr;
+    const float vt = b2 * v[t] + (1.f - b2) * gr * gr;
+    m[t] = mt;
+    v[t] = vt;
+    const float p = w[t] - lr * (mt / c1) / (sqrtf(vt / c2) + eps);
+    w[t] = p;
+    wq[t] = __bfloat162float(__float2bfloat16(p));
+}
+
+__global__ void k_nn_round(int n, const float *__restrict__ w, float *__restrict__ wq) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) wq[t] = __bfloat162float(__float2bfloat16(w[t]));
+}
+
+// ---------------------------------------------------------------- launchers
+template <int P>
+static void nn_layer_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {
+    using S2 = typename Prec<P>::S2;
+    dim3 grid((unsigned)((c->V + 255) / 256), (unsigned)cout);
+    const S2 *U = (const S2 *)c->Uin;
+    if (cin == 1 && cout == 8)
+        k_nn_layer<P, 1, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
+    else if (cin == 8 && cout == 8)
+        k_nn_layer<P, 8, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
+    else if (cin == 8 && cout == 1)
+        k_nn_layer<P, 8, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
+}
+
+void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {
+    switch (c->prm.prec_inner) {
+    case SAPQ_FP32: nn_layer_p<SAPQ_FP32>(c, cin, cout, in, out, W); break;
+    case SAPQ_FP16: nn_layer_p<SAPQ_FP16>(c, cin, cout, in, out, W); break;
+    case SAPQ_BF16: nn_layer_p<SAPQ_BF16>(c, cin, cout, in, out, W); break;
+    }
+}
+
+void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2 *in, float2 *G) {
+    dim3 grid(9, (unsigned)cout, (unsigned)cin);
+    switch (c->prm.prec_inner) {
+    case SAPQ_FP32:
+        k_nn_wgrad<SAPQ_FP32><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, (const float2 *)c->Uin, G);
+        break;
+    case SAPQ_FP16:
+        k_nn_wgrad<SAPQ_FP16><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, (const __half2 *)c->Uin, G);
+        break;
+    case SAPQ_BF16:
+        k_nn_wgrad<SAPQ_BF16><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, (const __hip_bfloat162 *)c->Uin, G);
+        break;
+    }
+}
+
+void launch_nn_adjoint_weights(Ctx *c, int cin, int cout, const float2 *W, float2 *Wt) {
+    const int n = 9 * cin * cout * 16;
+    k_nn_adjoint_weights<<<(n + 255) / 256, 256, 0, c->stream>>>(cin, cout, W, Wt);
+}
+
+void launch_nn_adam(Ctx *c, int n, float *w, const float *grad, float gscale, float *m, float *v, float lr, int t,
+                    float *wq) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    k_nn_adam<<<(n + 255) / 256, 256, 0, c->stream>>>(n, w, grad, gscale, m, v, lr, b1, b2, eps, c1, c2, wq);
+}
+
+void launch_nn_round(Ctx *c, int n, const float *w, float *wq) {
+    k_nn_round<<<(n + 255) / 256, 256, 0, c->stream>>>(n, w, wq);
+}
+
+}  // namespace sapq

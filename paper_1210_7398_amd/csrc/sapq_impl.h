@@ -274,7 +274,27 @@ struct Ctx {
     // counters
     long n_msap, n_d64;
     Prof prof;
+    // learned stage (allocated when params.flags & SAPQ_FLAG_NN)
+    bool nn_alloc = false, have_nn = false;
+    float *nn_w, *nn_wq, *nn_G, *nn_m, *nn_v;
+    float2 *nn_wt;                       // adjoint weights of one layer
+    float2 *nn_a0, *nn_a1, *nn_a2, *nn_z; // layer inputs (1, 8, 8 channels) and output
+    float2 *nn_gz, *nn_g2, *nn_g1, *nn_gin, *nn_e;
+    void *i_z, *i_rp;                    // N r and r - D N r in inner storage
 };
+
+constexpr int NN_C = SAPQ_NN_CHANNELS;
+constexpr int NN_PARAMS = 2 * 16 * 9 * (NN_C + NN_C * NN_C + NN_C);
+constexpr int NN_OFF[3] = {0, 2 * 16 * 9 * NN_C, 2 * 16 * 9 * (NN_C + NN_C * NN_C)};  // floats
+constexpr int NN_CIN[3] = {1, NN_C, NN_C};
+constexpr int NN_COUT[3] = {NN_C, NN_C, 1};
+
+void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W);
+void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2 *in, float2 *G);
+void launch_nn_adjoint_weights(Ctx *c, int cin, int cout, const float2 *W, float2 *Wt);
+void launch_nn_adam(Ctx *c, int n, float *w, const float *grad, float gscale, float *m, float *v, float lr, int t, float *wq);
+void launch_nn_round(Ctx *c, int n, const float *w, float *wq);
+void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src);
 
 // bracket a launch with HIP events when profiling is on
 int prof_begin(Ctx *c, int kind);

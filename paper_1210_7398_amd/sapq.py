@@ -16,6 +16,7 @@ _LIB = None
 
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 OUTER_FBICGSTAB, OUTER_DEFECT = 0, 1
+FLAG_GUESS, FLAG_PROFILE, FLAG_NN = 1, 2, 4
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOTSU3", -4: "ENOTCONV", -5: "EBREAKDOWN", -6: "EHIP",
           -7: "ENOMEM", -8: "ESTATE"}
@@ -69,6 +70,13 @@ _SIGS = {
     "sapq_sap_precondition": (ctypes.c_int, [_P, _P, _P, _P]),
     "sapq_inner_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "sapq_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(Stats)]),
+    "sapq_nn_param_count": (ctypes.c_size_t, []),
+    "sapq_nn_set_weights": (ctypes.c_int, [_P, _P]),
+    "sapq_nn_get_weights": (ctypes.c_int, [_P, _P]),
+    "sapq_nn_forward": (ctypes.c_int, [_P, _P, _P]),
+    "sapq_nn_backward": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "sapq_nn_train_step": (ctypes.c_int, [_P, _P, ctypes.c_long, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                          ctypes.c_float, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "sapq_destroy": (None, [_P]),
     "sapq_last_error": (ctypes.c_char_p, []),
 }
@@ -108,13 +116,14 @@ class Solver:
     """One lattice + parameter set (one sapq context) with its own device arena."""
 
     def __init__(self, L, block, subblock, kappa, bc=(1, 1, 1, 1), omega=1.0, n_ssor=4, n_sap=4, tol_inner=1e-2,
-                 maxit_inner=50, maxit_outer=100, prec="fp32", outer="fbicgstab", device=None):
+                 maxit_inner=50, maxit_outer=100, prec="fp32", outer="fbicgstab", device=None, nn=False):
         self.L = tuple(L)
         self.V = int(L[0] * L[1] * L[2] * L[3])
         self.geom = Geom((ctypes.c_int * 4)(*L), (ctypes.c_int * 4)(*block), (ctypes.c_int * 4)(*subblock),
                          (ctypes.c_int * 4)(*bc))
+        self.base_flags = FLAG_NN if nn else 0
         self.params = Params(kappa, omega, tol_inner, n_ssor, n_sap, maxit_inner, maxit_outer, PREC[prec],
-                             OUTER_FBICGSTAB if outer == "fbicgstab" else OUTER_DEFECT, 0)
+                             OUTER_FBICGSTAB if outer == "fbicgstab" else OUTER_DEFECT, self.base_flags)
         self.prec = prec
         n = lib().sapq_arena_bytes(ctypes.byref(self.geom), ctypes.byref(self.params))
         if n == 0:
@@ -190,10 +199,53 @@ class Solver:
 
     def solve(self, b, tol=1e-10, x0=None, check=True, profile=False):
         x = self._spinor() if x0 is None else x0.clone()
-        self.params.flags = (0 if x0 is None else 1) | (2 if profile else 0)
+        self.params.flags = self.base_flags | (0 if x0 is None else FLAG_GUESS) | (FLAG_PROFILE if profile else 0)
         _check(lib().sapq_set_params(self.h, ctypes.byref(self.params)))
         st = Stats()
         rc = lib().sapq_solve(self.h, _ptr(x), _ptr(b, self.V, (4, 3)), tol, ctypes.byref(st))
         if check:
             _check(rc)
         return x, st.as_dict()
+
+    # ------------------------------------------------------------------ learned stage
+    def use_nn(self, on=True):
+        """Switch the learned stage of the inner preconditioner on or off (needs nn=True at creation)."""
+        self.base_flags = (self.base_flags | FLAG_NN) if on else (self.base_flags & ~FLAG_NN)
+        self.params.flags = self.base_flags
+        _check(lib().sapq_set_params(self.h, ctypes.byref(self.params)))
+
+    def nn_set_weights(self, w):
+        if w.dtype != torch.float32 or not w.is_contiguous() or w.numel() != nn_param_count() or w.device.type != "cuda":
+            raise TypeError("expected a contiguous float32 GPU tensor with nn_param_count() entries")
+        _check(lib().sapq_nn_set_weights(self.h, ctypes.c_void_p(w.data_ptr())))
+
+    def nn_get_weights(self):
+        w = torch.empty(nn_param_count(), dtype=torch.float32, device=self.device)
+        _check(lib().sapq_nn_get_weights(self.h, ctypes.c_void_p(w.data_ptr())))
+        return w
+
+    def nn_forward(self, psi):
+        out = self._spinor()
+        _check(lib().sapq_nn_forward(self.h, _ptr(out), _ptr(psi, self.V, (4, 3))))
+        return out
+
+    def nn_backward(self, grad_out, inp):
+        gw = torch.empty(nn_param_count(), dtype=torch.float32, device=self.device)
+        gin = self._spinor()
+        _check(lib().sapq_nn_backward(self.h, ctypes.c_void_p(gw.data_ptr()), _ptr(gin), _ptr(grad_out, self.V, (4, 3)),
+                                      _ptr(inp, self.V, (4, 3))))
+        return gw, gin
+
+    def nn_train_step(self, e, idx, lr, t):
+        """e: float32 GPU tensor [n, V, 4, 3, 2] of error vectors; idx: batch indices."""
+        if e.dtype != torch.float32 or not e.is_contiguous() or tuple(e.shape[1:]) != (self.V, 4, 3, 2):
+            raise TypeError("expected a contiguous float32 tensor [n, V, 4, 3, 2]")
+        ib = (ctypes.c_int * len(idx))(*[int(i) for i in idx])
+        loss = ctypes.c_double(0)
+        _check(lib().sapq_nn_train_step(self.h, ctypes.c_void_p(e.data_ptr()), e.shape[0], ib, len(idx), lr, t,
+                                        ctypes.byref(loss)))
+        return loss.value
+
+
+def nn_param_count():
+    return int(lib().sapq_nn_param_count())

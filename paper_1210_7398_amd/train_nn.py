@@ -1,0 +1,79 @@
+"""Training of the learned preconditioner stage on the GPU, through the C ABI.
+
+Training pairs come from the plain SAP solver: for a Gaussian source b the nested
+solve gives x* (to 1e-12), and defect-correction iterates x_0 = 0,
+x_{k+1} = x_k + Inner(b - D x_k) give the pairs (r_k, e_k) = (b - D x_k, x* - x_k).
+Only e_k is stored (float32, interchange layout); the library forms r_k = D e_k in
+FP32 inside sapq_nn_train_step.  The loss is the batch mean of |N r - e|^2 / |e|^2
+and the update is Adam; forward, backward and the update run in the library's kernels.
+"""
+import numpy as np
+import torch
+
+from . import sapq, synth
+
+
+def init_weights(seed, scale=0.02, device="cuda"):
+    """Small random weights, except the local term of every layer, which starts near a
+    multiple of the identity so that N starts close to a scaled identity map."""
+    rng = np.random.default_rng(seed)
+    n = sapq.nn_param_count()
+    w = scale * rng.normal(size=n)
+    C = 8
+    shapes = [(1, C), (C, C), (C, 1)]
+    off = 0
+    for ci, co in shapes:
+        blk = w[off : off + 2 * 16 * 9 * ci * co].reshape(9, co, ci, 4, 4, 2)
+        for c in range(min(ci, co)):
+            blk[0, c, c, :, :, 0] += np.eye(4) * (1.0 / np.sqrt(max(ci, co)) if ci != co else 1.0)
+        off += blk.size
+    return torch.tensor(w, dtype=torch.float32, device=device)
+
+
+def make_pairs(solver, sources, n_iter=5, tol=1e-12):
+    """Error vectors e_k = x* - x_k of defect-correction iterates of the plain SAP solver,
+    k = 0 .. n_iter-1, for each source; returns a float32 tensor [n, V, 4, 3, 2]."""
+    out = []
+    for b in sources:
+        xs, st = solver.solve(b, tol=tol, check=False)
+        x = torch.zeros_like(b)
+        for _ in range(n_iter):
+            e = xs - x
+            out.append(torch.view_as_real(e.to(torch.complex64)).contiguous())
+            r = b - solver.dslash(x, "fp64")
+            dx, _ = solver.inner_solve(r)
+            x = x + dx
+    return torch.stack(out)
+
+
+def train(solvers_and_pairs, steps, batch=8, lr=1e-3, seed=0, log=None):
+    """Adam on mini-batches drawn in turn from each (solver, e) entry; the solvers share one
+    set of weights, carried from one to the next.  Returns the per-step losses."""
+    rng = np.random.default_rng(seed)
+    losses = []
+    w = None
+    for t in range(1, steps + 1):
+        solver, e = solvers_and_pairs[(t - 1) % len(solvers_and_pairs)]
+        if w is not None and len(solvers_and_pairs) > 1:
+            solver.nn_set_weights(w)  # only one solver per field; moments restart per field
+        idx = rng.integers(0, e.shape[0], size=batch)
+        losses.append(solver.nn_train_step(e, idx, lr, t))
+        if len(solvers_and_pairs) > 1:
+            w = solver.nn_get_weights()
+        if log and (t % log == 0 or t == 1):
+            print(f"# nn step {t}: loss {np.mean(losses[-log:]):.4f}", flush=True)
+    return losses
+
+
+def preconditioned_residual(solver, r, use_nn):
+    """|(1 - D P) r| / |r| for P the inner preconditioner (M_SAP, or the stage + M_SAP)."""
+    solver.use_nn(use_nn)
+    if use_nn:
+        z = solver.nn_forward(r)
+        rp = r - solver.dslash(z, "fp64")
+        _, dy = solver.sap_precondition(rp)
+        res = rp - dy
+    else:
+        _, dy = solver.sap_precondition(r)
+        res = r - dy
+    return float(torch.linalg.vector_norm(res) / torch.linalg.vector_norm(r))
