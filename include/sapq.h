@@ -182,6 +182,33 @@ int sapq_inner_solve(sapq_ctx *ctx, double *e, const double *r, int *iters);
 int sapq_solve(sapq_ctx *ctx, double *x, const double *b, double tol, sapq_stats *stats);
 
 /*
+ * Batched solve: nctx contexts (one gauge field each; any lattice sizes, but one SAP block and
+ * sub-block shape and one prec_inner), with nrhs[i] right-hand sides for context i.  b[i] and x[i]
+ * are device arrays of nrhs[i] spinors in the spinor layout ([nrhs[i]][V_i][4][3]).  All fields and
+ * right-hand sides advance together: the outer iteration is FP64 defect correction
+ * (x += Inner(b - D x), true residual per right-hand side), each inner BiCGStab iteration is one
+ * hipGraph replay, and each SAP phase is one kernel launch over all fields, blocks and groups of
+ * right-hand sides, the links and clover rows of a site being loaded once per group.  Krylov
+ * scalars are per right-hand side; converged ones are masked.  Parameters (kappa, n_ssor, n_sap,
+ * tol_inner, maxit_*) are each context's; the stream is ctxs[0]'s.  arena: device memory of at
+ * least sapq_batch_arena_bytes() bytes, 256-byte aligned.  stats (host, nullable): one entry per
+ * right-hand side, contexts in order.  Returns SAPQ_ENOTCONV if any right-hand side missed tol.
+ */
+size_t sapq_batch_arena_bytes(sapq_ctx *const *ctxs, int nctx, const int *nrhs);
+int sapq_solve_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *const *x, const double *const *b,
+                     double tol, void *arena, size_t arena_bytes, sapq_stats *stats);
+
+/*
+ * Autotune the sub-block shape of a context: every sub-block shape whose extents are 2 or more
+ * and divide the block is timed on a solve of the point source at the origin (spin 0, colour 0)
+ * to 1e-10, and the fastest is kept (the ll ordering, hence the preconditioner, changes with it).
+ * cache_json_path (host, nullable): a JSON file of earlier choices, keyed by lattice, block,
+ * kappa and prec_inner; a hit skips the timing, a miss appends the result.  *subblock_out
+ * (host, nullable, 4 ints) receives the choice.
+ */
+int sapq_autotune(sapq_ctx *ctx, const char *cache_json_path, int *subblock_out);
+
+/*
  * Learned gauge-covariant preconditioner stage (not in the paper; an extension of its
  * inner preconditioner).  N is three linear parallel-transport convolution layers with
  * channels 1 -> SAPQ_NN_CHANNELS -> SAPQ_NN_CHANNELS -> 1; a layer maps c_in spinor

@@ -191,7 +191,7 @@ static void carve(Ctx *c, Arena &A, const HostTables &T) {
     c->g.loc_nbr = ints(T.loc_nbr.size());
     c->g.nbr16 = (const unsigned *)ints(T.nbr16.size());
     c->g.blk_nbr = ints(T.blk_nbr.size());
-    c->g.plane_start = ints(T.plane_start.size());
+    c->g.plane_start = ints(MAX_PLANES + 1);  // room for any sub-block shape of this block
     c->g.slot_lex = ints(T.slot_lex.size());
     c->g.blk_lex = ints(T.blk_lex.size());
     c->U64 = (double2 *)A.take((size_t)V * 24 * 16);
@@ -262,10 +262,6 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
 
 using namespace sapq;
 
-struct sapq_ctx {
-    Ctx c;
-};
-
 extern "C" {
 
 const char *sapq_last_error(void) { return g_err.c_str(); }
@@ -300,6 +296,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     if (T.max_plane > 4096 || T.Vb > 32767) { delete h; set_error("block too large"); return SAPQ_ESHAPE; }
     if ((long)c->lds_extra > (long)device_max_lds()) { delete h; set_error("block too large for LDS tables"); return SAPQ_ESHAPE; }
     if (T.nplanes > MAX_PLANES) { delete h; set_error("too many hyperplanes"); return SAPQ_ESHAPE; }
+    if (c->ssor_threads > 512 && !getenv("SAPQ_SSOR_THREADS")) { delete h; set_error("hyperplane too large"); return SAPQ_ESHAPE; }
     if (arena_bytes < need) {
         delete h;
         set_error("arena too small: need " + std::to_string(need) + " bytes");
@@ -790,6 +787,111 @@ int sapq_nn_train_step(sapq_ctx *h, const float *e, long n_vec, const int *idx, 
     launch_nn_adam(c, NN_PARAMS, c->nn_w, c->nn_G, 1.f / batch, c->nn_m, c->nn_v, lr, t, c->nn_wq);
     if (loss) *loss = total / batch;
     return hipcheck(hipGetLastError(), "sapq_nn_train_step");
+}
+
+// Rebuild the sub-block dependent tables (ll order, hyperplanes, neighbours) for shape S.
+static int apply_subblock(Ctx *c, const int S[4]) {
+    sapq_geom G = c->geom;
+    for (int m = 0; m < 4; ++m) G.subblock[m] = S[m];
+    std::string why;
+    int rc = check_geom(&G, why);
+    if (rc) { set_error(why); return rc; }
+    HostTables T;
+    build_tables(&G, T);
+    if (T.nplanes > MAX_PLANES || T.max_plane * 4 > 512) { set_error("sub-block shape gives too large a hyperplane"); return SAPQ_ESHAPE; }
+    struct { const void *dst; const std::vector<int> *src; } cp[] = {
+        {c->g.loc_nbr, &T.loc_nbr}, {c->g.nbr16, &T.nbr16}, {c->g.plane_start, &T.plane_start}, {c->g.slot_lex, &T.slot_lex}};
+    for (auto &e : cp) {
+        rc = hipcheck(hipMemcpyAsync((void *)e.dst, e.src->data(), e.src->size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
+                      "hipMemcpyAsync(tables)");
+        if (rc) return rc;
+    }
+    rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    c->geom.subblock[0] = S[0]; c->geom.subblock[1] = S[1]; c->geom.subblock[2] = S[2]; c->geom.subblock[3] = S[3];
+    c->g.nplanes = T.nplanes;
+    c->max_plane = T.max_plane;
+    c->ssor_threads = std::min(512, ((4 * T.max_plane + 63) / 64) * 64);
+    return SAPQ_OK;
+}
+
+static std::string tune_key(const Ctx *c) {
+    char b[256];
+    snprintf(b, sizeof b, "L=%dx%dx%dx%d;B=%dx%dx%dx%d;kappa=%.6f;nssor=%d;nsap=%d;prec=%d", c->geom.L[0], c->geom.L[1],
+             c->geom.L[2], c->geom.L[3], c->geom.block[0], c->geom.block[1], c->geom.block[2], c->geom.block[3],
+             c->prm.kappa, c->prm.n_ssor, c->prm.n_sap, c->prm.prec_inner);
+    return b;
+}
+
+int sapq_autotune(sapq_ctx *h, const char *cache_json_path, int *subblock_out) {
+    if (!h) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    const std::string key = tune_key(c);
+    // cache: one JSON object per line, {"key": "...", "subblock": [a, b, c, d], "time_s": t}
+    if (cache_json_path) {
+        if (FILE *f = fopen(cache_json_path, "r")) {
+            char line[1024];
+            int S[4];
+            bool hit = false;
+            while (fgets(line, sizeof line, f)) {
+                const char *k = strstr(line, "\"key\": \"");
+                if (!k || strncmp(k + 8, key.c_str(), key.size()) != 0 || k[8 + key.size()] != '"') continue;
+                const char *sb = strstr(line, "\"subblock\": [");
+                if (sb && sscanf(sb + 13, "%d, %d, %d, %d", &S[0], &S[1], &S[2], &S[3]) == 4) hit = true;
+            }
+            fclose(f);
+            if (hit) {
+                rc = apply_subblock(c, S);
+                if (rc == SAPQ_OK && subblock_out) memcpy(subblock_out, S, sizeof S);
+                return rc;
+            }
+        }
+    }
+    // point source at the origin, spin 0, colour 0, staged through an FP64 work vector
+    std::vector<double> src((size_t)c->V * 24, 0.0);
+    src[0] = 1.0;
+    double best_t = 1e300;
+    int best[4] = {c->geom.subblock[0], c->geom.subblock[1], c->geom.subblock[2], c->geom.subblock[3]};
+    std::vector<int> ext[4];
+    for (int m = 0; m < 4; ++m)
+        for (int s = 2; s <= c->geom.block[m]; ++s)
+            if (c->geom.block[m] % s == 0) ext[m].push_back(s);
+    const int saved_flags = c->prm.flags;
+    c->prm.flags &= ~SAPQ_FLAG_PROFILE;
+    for (int a : ext[0])
+        for (int b : ext[1])
+            for (int d : ext[2])
+                for (int e : ext[3]) {
+                    const int S[4] = {a, b, d, e};
+                    if (apply_subblock(c, S) != SAPQ_OK) continue;
+                    (void)hipMemcpyAsync(c->d_ph, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+                    launch_pack_spinor(c, SAPQ_FP64, c->d_b, (const double *)c->d_ph, 1.0);
+                    blas_zero(c, SAPQ_FP64, c->d_x);
+                    (void)hipStreamSynchronize(c->stream);
+                    auto t0 = std::chrono::steady_clock::now();
+                    sapq_stats st;
+                    int r2 = outer_solve(c, 1e-10, &st);
+                    (void)hipStreamSynchronize(c->stream);
+                    double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                    if (r2 == SAPQ_OK && t < best_t) {
+                        best_t = t;
+                        memcpy(best, S, sizeof best);
+                    }
+                }
+    c->prm.flags = saved_flags;
+    rc = apply_subblock(c, best);
+    if (rc) return rc;
+    if (subblock_out) memcpy(subblock_out, best, sizeof best);
+    if (cache_json_path && best_t < 1e300) {
+        if (FILE *f = fopen(cache_json_path, "a")) {
+            fprintf(f, "{\"key\": \"%s\", \"subblock\": [%d, %d, %d, %d], \"time_s\": %.6f}\n", key.c_str(), best[0],
+                    best[1], best[2], best[3], best_t);
+            fclose(f);
+        }
+    }
+    return hipcheck(hipGetLastError(), "sapq_autotune");
 }
 
 int sapq_inner_solve(sapq_ctx *h, double *e, const double *r, int *iters) {

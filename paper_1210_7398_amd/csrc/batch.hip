@@ -1,0 +1,899 @@
+// Batched solver: several gauge fields (lattices of any size, one SAP block and sub-block
+// shape) with several right-hand sides each, solved together.  Every inner BiCGStab
+// iteration of all fields and right-hand sides is one hipGraph replay; each SAP phase is one
+// kernel launch over a work list of (field, block, group of right-hand sides), whose
+// workgroup loads the links and clover rows of a site once and applies them to every
+// right-hand side of the group.  Krylov scalars live on the device, one set per right-hand
+// side; converged right-hand sides are masked.  The outer iteration is FP64 defect
+// correction.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sitecore.h"
+
+namespace sapq {
+
+// inner vector slots (storage precision), rhs-major: slot base + k * nvec
+enum { IV_R, IV_RT, IV_P, IV_V, IV_S, IV_T, IV_E, IV_PH, IV_SH, IV_SAPR, IV_SAPX, IV_RIN, NIV };
+// outer vector slots (FP64)
+enum { DV_B, DV_X, DV_R, DV_T, NDV };
+
+constexpr int MAX_FIELDS = 16;
+
+struct BField {
+    GeomDev g;
+    const void *Uin, *Fin;
+    const double2 *U64, *F64;
+    float kappa, omega;
+    int n_ssor;
+    int nrhs, rhs0;       // right-hand sides of this field and the index of its first one
+    int ngroups;          // groups of NR right-hand sides
+    size_t nvec;
+    void *iv[NIV];
+    double2 *dv[NDV];
+};
+
+struct BatchDev {
+    int nf, total_rhs;
+    int work0[MAX_FIELDS + 1];  // prefix sums of NBc * ngroups over fields
+    BField f[MAX_FIELDS];
+};
+
+// per right-hand-side Krylov state on the device
+struct BState {
+    double2 rho, rho_old, alpha, omega, beta;
+    double r0, rr;
+    int done, its;
+};
+
+// ---------------------------------------------------------------- work list decode
+__device__ __forceinline__ int field_of_work(const BatchDev &B, int w) {
+    int f = 0;
+    while (f + 1 < B.nf && w >= B.work0[f + 1]) ++f;
+    return f;
+}
+
+// ---------------------------------------------------------------- multi-RHS SAP phase
+// As the single-source phase kernel, for NR right-hand sides at once (iterates in LDS).
+template <int P, int NR>
+__global__ void __launch_bounds__(512) k_bsap_phase(const BatchDev *__restrict__ Bd, int colour, int first, int s_src,
+                                                    int s_r, int s_x, int s_y, const BState *__restrict__ bst) {
+    using S2 = typename Prec<P>::S2;
+    using C = float;
+    extern __shared__ float2 lds[];
+    const BatchDev &B = *Bd;
+    const int w = blockIdx.x;
+    const int fi = field_of_work(B, w);
+    const BField &F = B.f[fi];
+    const GeomDev &g = F.g;
+    const int local = w - B.work0[fi];
+    const int ib = colour * g.NBc + local / F.ngroups;
+    const int k0 = (local % F.ngroups) * NR;
+    // skip groups whose right-hand sides are all finished (uniform over the workgroup)
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        if (k0 + k < F.nrhs && !bst[F.rhs0 + k0 + k].done) any = true;
+    if (!any) return;
+    float2 *xs = lds;  // [NR][12][Vb]
+    unsigned *nb_lds = reinterpret_cast<unsigned *>(lds + NR * 12 * g.Vb);
+    int *ps_lds = reinterpret_cast<int *>(nb_lds + 4 * g.Vb);
+    const S2 *U = (const S2 *)F.Uin;
+    const S2 *Fc = (const S2 *)F.Fin;
+    const C kappa = F.kappa, omega = F.omega;
+    const int j = threadIdx.x & 3;
+    const int q0 = threadIdx.x >> 2, nq = blockDim.x >> 2;
+    const int bl_f = g.blk_nbr[(2 * j) * g.NB + ib], bl_b = g.blk_nbr[(2 * j + 1) * g.NB + ib];
+    const float bc = g.bc[j];
+    const S2 *src = (const S2 *)F.iv[s_src];
+    S2 *r = (S2 *)F.iv[s_r];
+    S2 *x = (S2 *)F.iv[s_x];
+    S2 *y = (S2 *)F.iv[s_y];
+    const size_t nv = F.nvec;
+    const int nk = min(NR, F.nrhs - k0);
+
+    for (int t = threadIdx.x; t < 4 * g.Vb; t += blockDim.x) nb_lds[t] = g.nbr16[t];
+    for (int t = threadIdx.x; t <= g.nplanes; t += blockDim.x) ps_lds[t] = g.plane_start[t];
+    __syncthreads();
+
+    const bool gather = colour == 1 || !first;
+    for (int s = q0; s < g.Vb; s += nq) {
+        const LaneNbr n = lane_nbr(nb_lds[j * g.Vb + s], ib, bl_f, bl_b, bc);
+        LaneLinks<C> lk;
+        LaneClover<C> lc;
+        if (gather) {
+            lane_links(lk, g, ib, s, j, n, U);
+            lane_clover_load(lc, Fc, g, ib, s, j);
+        }
+        for (int k = 0; k < nk; ++k) {
+            const size_t ko = (size_t)(k0 + k) * nv;
+            cx<C> v[3];
+            load_spin(v, src + ko, g, ib, s, j);
+            if (gather) {
+                cx<C> h[12], fh[3];
+                quad_hop_apply<HOP_OUT>(h, g, j, n, lk, FieldSrc<S2, C>{x + ko});
+                lane_clover_apply(fh, h, lc, j);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = v[c] + kappa * fh[c];
+            }
+            store_spin(r + ko, g, ib, s, j, v);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xs[(k * 12 + 3 * j + c) * g.Vb + s] = make_float2(0.f, 0.f);
+        }
+    }
+    __syncthreads();
+
+    for (int sw = 0; sw < F.n_ssor; ++sw) {
+        for (int dir = 0; dir < 2; ++dir) {
+            for (int pi = 0; pi < g.nplanes; ++pi) {
+                const int p = dir == 0 ? pi : g.nplanes - 1 - pi;
+                const int s0 = ps_lds[p], s1 = ps_lds[p + 1];
+                for (int s = s0 + q0; s < s1; s += nq) {
+                    const LaneNbr n = lane_nbr(nb_lds[j * g.Vb + s], ib, bl_f, bl_b, bc);
+                    LaneLinks<C> lk;
+                    LaneClover<C> lc;
+                    lane_links(lk, g, ib, s, j, n, U);
+                    lane_clover_load(lc, Fc, g, ib, s, j);
+                    for (int k = 0; k < nk; ++k) {
+                        const BlockSrc bs{xs + (size_t)k * 12 * g.Vb};
+                        cx<C> h[12], fh[3], v[3];
+                        quad_hop_apply<HOP_IN>(h, g, j, n, lk, bs);
+                        lane_clover_apply(fh, h, lc, j);
+                        load_spin(v, r + (size_t)(k0 + k) * nv, g, ib, s, j);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) {
+                            float2 *o = &xs[(k * 12 + 3 * j + c) * g.Vb + s];
+                            float2 ov = *o;
+                            cx<C> nx = v[c] + kappa * fh[c];
+                            *o = make_float2((1.f - omega) * ov.x + omega * nx.r, (1.f - omega) * ov.y + omega * nx.i);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    for (int s = q0; s < g.Vb; s += nq) {
+        const LaneNbr n = lane_nbr(nb_lds[j * g.Vb + s], ib, bl_f, bl_b, bc);
+        LaneLinks<C> lk;
+        LaneClover<C> lc;
+        lane_links(lk, g, ib, s, j, n, U);
+        lane_clover_load(lc, Fc, g, ib, s, j);
+        for (int k = 0; k < nk; ++k) {
+            const size_t ko = (size_t)(k0 + k) * nv;
+            const float2 *xk = xs + (size_t)k * 12 * g.Vb;
+            cx<C> xv[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float2 t = xk[(3 * j + c) * g.Vb + s];
+                xv[c] = {t.x, t.y};
+            }
+            store_spin(x + ko, g, ib, s, j, xv);
+            cx<C> yv[3];
+            if (first) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) yv[c] = xv[c];
+            } else {
+                load_spin(yv, y + ko, g, ib, s, j);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) yv[c] = yv[c] + xv[c];
+            }
+            store_spin(y + ko, g, ib, s, j, yv);
+            cx<C> h[12], fh[3], v[3];
+            quad_hop_apply<HOP_IN>(h, g, j, n, lk, BlockSrc{xk});
+            lane_clover_apply(fh, h, lc, j);
+            load_spin(v, r + ko, g, ib, s, j);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] = v[c] - xv[c] + kappa * fh[c];
+            store_spin(r + ko, g, ib, s, j, v);
+        }
+    }
+}
+
+// allow the batched phase kernels the dynamic LDS they are launched with
+static void batch_lds_attr(int bytes) {
+    const void *fns[] = {(const void *)k_bsap_phase<SAPQ_FP32, 1>, (const void *)k_bsap_phase<SAPQ_FP32, 2>,
+                         (const void *)k_bsap_phase<SAPQ_FP32, 4>, (const void *)k_bsap_phase<SAPQ_FP16, 1>,
+                         (const void *)k_bsap_phase<SAPQ_FP16, 2>, (const void *)k_bsap_phase<SAPQ_FP16, 4>,
+                         (const void *)k_bsap_phase<SAPQ_BF16, 1>, (const void *)k_bsap_phase<SAPQ_BF16, 2>,
+                         (const void *)k_bsap_phase<SAPQ_BF16, 4>};
+    for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// r_c += kappa F sum_{hops leaving the block} H x for every field and right-hand side
+template <int P>
+__global__ void __launch_bounds__(256) k_bsap_face(const BatchDev *__restrict__ Bd, int colour, int s_r, int s_x,
+                                                  const BState *__restrict__ bst) {
+    using S2 = typename Prec<P>::S2;
+    using C = float;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs || bst[F.rhs0 + k].done) return;
+    const GeomDev &g = F.g;
+    const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long i = gt >> 2;
+    const int j = (int)(gt & 3);
+    if (i >= (long)g.NBc * g.Vb) return;
+    const int ib = colour * g.NBc + (int)(i / g.Vb), s = (int)(i % g.Vb);
+    const size_t ko = (size_t)k * F.nvec;
+    S2 *r = (S2 *)F.iv[s_r] + ko;
+    const S2 *x = (const S2 *)F.iv[s_x] + ko;
+    const LaneNbr n = lane_nbr(g.nbr16[j * g.Vb + s], ib, g.blk_nbr[(2 * j) * g.NB + ib],
+                               g.blk_nbr[(2 * j + 1) * g.NB + ib], g.bc[j]);
+    cx<C> h[12], fh[3], v[3];
+    quad_hop_sum<HOP_OUT, false>(h, g, ib, s, j, n, (const S2 *)F.Uin, FieldSrc<S2, C>{x});
+    lane_clover(fh, h, (const S2 *)F.Fin, g, ib, s, j);
+    load_spin(v, r, g, ib, s, j);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = v[c] + F.kappa * fh[c];
+    store_spin(r, g, ib, s, j, v);
+}
+
+// out = D in in FP64 for every field and right-hand side (outer slots)
+__global__ void __launch_bounds__(256) k_bdslash64(const BatchDev *__restrict__ Bd, int s_out, int s_in) {
+    using C = double;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const GeomDev &g = F.g;
+    const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long i = gt >> 2;
+    const int j = (int)(gt & 3);
+    if (i >= g.V) return;
+    const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    const size_t ko = (size_t)k * F.nvec;
+    const double2 *in = F.dv[s_in] + ko;
+    double2 *out = F.dv[s_out] + ko;
+    const LaneNbr n = lane_nbr(g.nbr16[j * g.Vb + s], ib, g.blk_nbr[(2 * j) * g.NB + ib],
+                               g.blk_nbr[(2 * j + 1) * g.NB + ib], g.bc[j]);
+    cx<C> h[12], fh[3], v[3];
+    quad_hop_sum<HOP_ALL, false>(h, g, ib, s, j, n, F.U64, FieldSrc<double2, C>{in});
+    lane_clover(fh, h, F.F64, g, ib, s, j);
+    load_spin(v, in, g, ib, s, j);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = v[c] - (double)F.kappa * fh[c];
+    store_spin(out, g, ib, s, j, v);
+}
+
+// ---------------------------------------------------------------- batched vector updates
+// Coefficients are per right-hand side: a table index selects which BState entry (or 1, -1).
+enum { CF_ONE, CF_MONE, CF_MALPHA, CF_MOMEGA, CF_ALPHA, CF_OMEGA };
+
+__device__ __forceinline__ cx<double> coef(const BState &s, int which) {
+    switch (which) {
+    case CF_ONE: return {1.0, 0.0};
+    case CF_MONE: return {-1.0, 0.0};
+    case CF_MALPHA: return {-s.alpha.x, -s.alpha.y};
+    case CF_MOMEGA: return {-s.omega.x, -s.omega.y};
+    case CF_ALPHA: return {s.alpha.x, s.alpha.y};
+    default: return {s.omega.x, s.omega.y};
+    }
+}
+
+// z = x + c y, skipped for finished right-hand sides when masked
+template <int P>
+__global__ void k_bxpay(const BatchDev *__restrict__ Bd, int s_z, int s_x, int which, int s_y,
+                        const BState *__restrict__ bst, int masked) {
+    using C = typename Prec<P>::C;
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const BState &S = bst[F.rhs0 + k];
+    if (masked && S.done) return;
+    const cx<double> cd = coef(S, which);
+    const cx<C> c{C(cd.r), C(cd.i)};
+    const size_t ko = (size_t)k * F.nvec;
+    S2 *z = (S2 *)F.iv[s_z] + ko;
+    const S2 *x = (const S2 *)F.iv[s_x] + ko;
+    const S2 *y = (const S2 *)F.iv[s_y] + ko;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.nvec; i += (size_t)gridDim.x * blockDim.x)
+        st(z + i, ld(x + i) + cmul(c, ld(y + i)));
+}
+
+// p = r + beta (p - omega v)
+template <int P>
+__global__ void k_bbicg_p(const BatchDev *__restrict__ Bd, const BState *__restrict__ bst) {
+    using C = typename Prec<P>::C;
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const BState &S = bst[F.rhs0 + k];
+    if (S.done) return;
+    const cx<C> beta{C(S.beta.x), C(S.beta.y)}, om{C(S.omega.x), C(S.omega.y)};
+    const size_t ko = (size_t)k * F.nvec;
+    S2 *p = (S2 *)F.iv[IV_P] + ko;
+    const S2 *r = (const S2 *)F.iv[IV_R] + ko;
+    const S2 *v = (const S2 *)F.iv[IV_V] + ko;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.nvec; i += (size_t)gridDim.x * blockDim.x)
+        st(p + i, ld(r + i) + cmul(beta, ld(p + i) - cmul(om, ld(v + i))));
+}
+
+// e += alpha ph + omega sh
+template <int P>
+__global__ void k_bupdate_e(const BatchDev *__restrict__ Bd, const BState *__restrict__ bst) {
+    using C = typename Prec<P>::C;
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const BState &S = bst[F.rhs0 + k];
+    if (S.done) return;
+    const cx<C> a{C(S.alpha.x), C(S.alpha.y)}, o{C(S.omega.x), C(S.omega.y)};
+    const size_t ko = (size_t)k * F.nvec;
+    S2 *e = (S2 *)F.iv[IV_E] + ko;
+    const S2 *ph = (const S2 *)F.iv[IV_PH] + ko;
+    const S2 *sh = (const S2 *)F.iv[IV_SH] + ko;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.nvec; i += (size_t)gridDim.x * blockDim.x)
+        st(e + i, ld(e + i) + cmul(a, ld(ph + i)) + cmul(o, ld(sh + i)));
+}
+
+template <int P>
+__global__ void k_bzero(const BatchDev *__restrict__ Bd, int slot) {
+    using C = typename Prec<P>::C;
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    S2 *z = (S2 *)F.iv[slot];
+    const size_t n = F.nvec * F.nrhs;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        st(z + i, cxz<C>());
+}
+
+// dot products <a_q, b_q> (q < nd) per right-hand side: partial sums per workgroup
+constexpr int BDOT_BLOCKS = 64;
+template <int P, bool OUTER>
+__global__ void __launch_bounds__(256) k_bdots(const BatchDev *__restrict__ Bd, int nd, int a0, int b0, int a1, int b1,
+                                               double *__restrict__ partials /* [rhs][BDOT_BLOCKS][4] */) {
+    using S2 = typename Prec<P>::S2;
+    __shared__ double sm[4][4];
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const size_t ko = (size_t)k * F.nvec;
+    const S2 *A0 = (const S2 *)(OUTER ? (const void *)F.dv[a0] : F.iv[a0]) + ko;
+    const S2 *B0 = (const S2 *)(OUTER ? (const void *)F.dv[b0] : F.iv[b0]) + ko;
+    const S2 *A1 = (const S2 *)(OUTER ? (const void *)F.dv[a1] : F.iv[a1]) + ko;
+    const S2 *B1 = (const S2 *)(OUTER ? (const void *)F.dv[b1] : F.iv[b1]) + ko;
+    double acc[4] = {0, 0, 0, 0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.nvec; i += (size_t)gridDim.x * blockDim.x) {
+        auto x = ld(A0 + i), y = ld(B0 + i);
+        acc[0] += (double)x.r * y.r + (double)x.i * y.i;
+        acc[1] += (double)x.r * y.i - (double)x.i * y.r;
+        if (nd > 1) {
+            auto u = ld(A1 + i), w = ld(B1 + i);
+            acc[2] += (double)u.r * w.r + (double)u.i * w.i;
+            acc[3] += (double)u.r * w.i - (double)u.i * w.r;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) sm[wv][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double v = sm[0][threadIdx.x] + sm[1][threadIdx.x] + sm[2][threadIdx.x] + sm[3][threadIdx.x];
+        partials[((size_t)(F.rhs0 + k) * BDOT_BLOCKS + blockIdx.x) * 4 + threadIdx.x] = v;
+    }
+}
+
+// scalar steps of BiCGStab, one thread per right-hand side (partials summed in fixed order)
+enum { SC_INIT, SC_BETA, SC_ALPHA, SC_OMEGA, SC_UPDATE, SC_OUTER };
+
+__device__ __forceinline__ double2 sum_part(const double *partials, int rhs, int q) {
+    double re = 0, im = 0;
+    for (int b = 0; b < BDOT_BLOCKS; ++b) {
+        re += partials[((size_t)rhs * BDOT_BLOCKS + b) * 4 + 2 * q];
+        im += partials[((size_t)rhs * BDOT_BLOCKS + b) * 4 + 2 * q + 1];
+    }
+    return make_double2(re, im);
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ void k_bscalar(int step, int total, const double *__restrict__ partials, BState *__restrict__ st, double tol,
+                          int maxit, int *__restrict__ active) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < total) {
+        BState &S = st[k];
+        if (step == SC_INIT) {
+            // partials hold <rt, r> and <r, r>; S.done was set by the caller for converged systems
+            S.rho = sum_part(partials, k, 0);
+            S.rr = sum_part(partials, k, 1).x;
+            S.r0 = sqrt(S.rr);
+            S.rho_old = make_double2(1, 0);
+            S.alpha = make_double2(1, 0);
+            S.omega = make_double2(1, 0);
+            S.its = 0;
+            if (S.r0 == 0) S.done = 1;
+        } else if (!S.done) {
+            if (step == SC_BETA) {
+                S.beta = cmul2(cdiv(S.rho, S.rho_old), cdiv(S.alpha, S.omega));
+            } else if (step == SC_ALPHA) {
+                const double2 rv = sum_part(partials, k, 0);
+                if (rv.x == 0 && rv.y == 0) { S.done = 1; S.alpha = make_double2(0, 0); }
+                else S.alpha = cdiv(S.rho, rv);
+            } else if (step == SC_OMEGA) {
+                const double2 ts = sum_part(partials, k, 0);
+                const double tt = sum_part(partials, k, 1).x;
+                S.omega = tt > 0 ? make_double2(ts.x / tt, ts.y / tt) : make_double2(0, 0);
+            } else if (step == SC_UPDATE) {
+                S.rho_old = S.rho;
+                S.rho = sum_part(partials, k, 0);
+                S.rr = sum_part(partials, k, 1).x;
+                S.its += 1;
+                if (sqrt(S.rr) <= tol * S.r0 || S.its >= maxit || (S.omega.x == 0 && S.omega.y == 0) ||
+                    (S.rho.x == 0 && S.rho.y == 0))
+                    S.done = 1;
+            }
+        }
+    }
+    if (step == SC_UPDATE && blockIdx.x == 0 && threadIdx.x == 0) {
+        int n = 0;
+        for (int q = 0; q < total; ++q) n += st[q].done ? 0 : 1;
+        *active = n;
+    }
+}
+
+// inner storage <-> FP64 outer, with a per-right-hand-side scale from the outer norms
+template <int P>
+__global__ void k_bconvert_in(const BatchDev *__restrict__ Bd, const double *__restrict__ scale) {
+    using C = typename Prec<P>::C;
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const double sc = scale[F.rhs0 + k];
+    const size_t ko = (size_t)k * F.nvec;
+    S2 *d = (S2 *)F.iv[IV_RIN] + ko;
+    const double2 *s = F.dv[DV_R] + ko;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.nvec; i += (size_t)gridDim.x * blockDim.x) {
+        double2 v = s[i];
+        st(d + i, cx<C>{C(v.x * sc), C(v.y * sc)});
+    }
+}
+
+template <int P>
+__global__ void k_bconvert_out(const BatchDev *__restrict__ Bd, const double *__restrict__ scale) {
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const double sc = scale[F.rhs0 + k];
+    if (sc == 0) return;
+    const size_t ko = (size_t)k * F.nvec;
+    double2 *x = F.dv[DV_X] + ko;
+    const S2 *e = (const S2 *)F.iv[IV_E] + ko;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.nvec; i += (size_t)gridDim.x * blockDim.x) {
+        auto v = ld(e + i);
+        double2 o = x[i];
+        x[i] = make_double2(o.x + (double)v.r / sc, o.y + (double)v.i / sc);
+    }
+}
+
+// r = b - t (FP64)
+__global__ void k_bresid(const BatchDev *__restrict__ Bd) {
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs) return;
+    const size_t ko = (size_t)k * F.nvec;
+    const double2 *b = F.dv[DV_B] + ko, *t = F.dv[DV_T] + ko;
+    double2 *r = F.dv[DV_R] + ko;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < F.nvec; i += (size_t)gridDim.x * blockDim.x)
+        r[i] = make_double2(b[i].x - t[i].x, b[i].y - t[i].y);
+}
+
+template <int P>
+__global__ void k_bcopy(const BatchDev *__restrict__ Bd, int s_d, int s_s) {
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    S2 *d = (S2 *)F.iv[s_d];
+    const S2 *s = (const S2 *)F.iv[s_s];
+    const size_t n = F.nvec * F.nrhs;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) d[i] = s[i];
+}
+
+// ---------------------------------------------------------------- host driver
+struct Batch {
+    std::vector<Ctx *> ctx;
+    int nf = 0, total = 0, max_rhs = 0;
+    long max_V = 0;
+    int prec = SAPQ_FP32, NR = 1;
+    size_t lds = 0;
+    hipStream_t stream = nullptr;
+    BatchDev host;
+    BatchDev *dev = nullptr;
+    BState *st = nullptr;
+    double *partials = nullptr, *scale = nullptr;
+    int *active = nullptr, *host_active = nullptr;
+    double *host_scalars = nullptr;
+};
+
+static size_t rhs_bytes(Ctx *c, int prec) { return c->nvec * elem_bytes(prec); }
+
+static size_t layout_batch(Batch &B, char *base) {
+    size_t used = 0;
+    auto take = [&](size_t n) -> void * {
+        size_t off = (used + 255) & ~(size_t)255;
+        used = off + n;
+        return base ? (void *)(base + off) : nullptr;
+    };
+    B.dev = (BatchDev *)take(sizeof(BatchDev));
+    B.st = (BState *)take(sizeof(BState) * B.total);
+    B.partials = (double *)take(sizeof(double) * 4 * BDOT_BLOCKS * B.total);
+    B.scale = (double *)take(sizeof(double) * B.total);
+    B.active = (int *)take(sizeof(int) * 4);
+    for (int f = 0; f < B.nf; ++f) {
+        BField &F = B.host.f[f];
+        for (int s = 0; s < NIV; ++s) F.iv[s] = take(rhs_bytes(B.ctx[f], B.prec) * F.nrhs);
+        for (int s = 0; s < NDV; ++s) F.dv[s] = (double2 *)take(B.ctx[f]->nvec * 16 * F.nrhs);
+    }
+    return used + 256;
+}
+
+
+static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrhs, std::string &why) {
+    if (nctx < 1 || nctx > MAX_FIELDS) { why = "between 1 and 16 contexts"; return SAPQ_EINVAL; }
+    B.nf = nctx;
+    B.total = 0;
+    int work = 0;
+    for (int f = 0; f < nctx; ++f) {
+        if (!ctxs[f] || nrhs[f] < 1) { why = "null context or nrhs < 1"; return SAPQ_EINVAL; }
+        Ctx *c = &ctxs[f]->c;
+        B.ctx.push_back(c);
+        if (f > 0) {
+            Ctx *c0 = B.ctx[0];
+            for (int m = 0; m < 4; ++m)
+                if (c->geom.block[m] != c0->geom.block[m] || c->geom.subblock[m] != c0->geom.subblock[m]) {
+                    why = "all contexts need the same block and sub-block shape";
+                    return SAPQ_EINVAL;
+                }
+            if (c->prm.prec_inner != c0->prm.prec_inner) { why = "all contexts need the same prec_inner"; return SAPQ_EINVAL; }
+        }
+        if (!c->have_U || !c->have_F) { why = "fields must be loaded in every context"; return SAPQ_ESTATE; }
+        B.max_rhs = std::max(B.max_rhs, nrhs[f]);
+        B.max_V = std::max(B.max_V, c->V);
+    }
+    Ctx *c0 = B.ctx[0];
+    B.prec = c0->prm.prec_inner;
+    B.stream = c0->stream;
+    // right-hand sides per workgroup: as many as the LDS holds (1, 2 or 4)
+    int max_lds = 65536, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    const size_t per = (size_t)c0->g.Vb * 12 * sizeof(float2);
+    B.NR = 0;
+    for (int nr : {4, 2, 1})
+        if (B.NR == 0 && nr <= std::max(1, B.max_rhs) && per * nr + c0->lds_extra <= (size_t)max_lds) B.NR = nr;
+    if (B.NR == 0) { why = "the SAP block is too large for the batched kernel's LDS"; return SAPQ_ESHAPE; }
+    B.lds = per * B.NR + c0->lds_extra;
+    if (B.lds > 65536) {
+        batch_lds_attr((int)B.lds);
+        (void)hipGetLastError();  // clears the runtime's last-error slot
+    }
+    if (c0->ssor_threads > 512) { why = "hyperplanes too large for the batched kernel"; return SAPQ_ESHAPE; }
+    memset(&B.host, 0, sizeof(B.host));
+    B.host.nf = nctx;
+    for (int f = 0; f < nctx; ++f) {
+        Ctx *c = B.ctx[f];
+        BField &F = B.host.f[f];
+        F.g = c->g;
+        F.Uin = c->Uin;
+        F.Fin = c->Fin;
+        F.U64 = c->U64;
+        F.F64 = c->F64;
+        F.kappa = (float)c->prm.kappa;
+        F.omega = (float)c->prm.omega;
+        F.n_ssor = c->prm.n_ssor;
+        F.nrhs = nrhs[f];
+        F.rhs0 = B.total;
+        F.ngroups = (nrhs[f] + B.NR - 1) / B.NR;
+        F.nvec = c->nvec;
+        B.host.work0[f] = work;
+        work += c->g.NBc * F.ngroups;
+        B.total += nrhs[f];
+    }
+    B.host.work0[nctx] = work;
+    B.host.total_rhs = B.total;
+    return SAPQ_OK;
+}
+
+#define BPREC(prec, BODY)                                          \
+    switch (prec) {                                                \
+    case SAPQ_FP32: { constexpr int P_ = SAPQ_FP32; BODY; } break; \
+    case SAPQ_FP16: { constexpr int P_ = SAPQ_FP16; BODY; } break; \
+    case SAPQ_BF16: { constexpr int P_ = SAPQ_BF16; BODY; } break; \
+    default: break;                                                \
+    }
+
+static dim3 vgrid(const Batch &B) { return dim3(256, (unsigned)B.nf, (unsigned)B.max_rhs); }
+
+template <int P, int NR>
+static void bphase(Batch &B, int colour, int first, int src, int r, int x, int y) {
+    k_bsap_phase<P, NR><<<(unsigned)B.host.work0[B.nf], B.ctx[0]->ssor_threads, B.lds, B.stream>>>(B.dev, colour, first, src,
+                                                                                                  r, x, y, B.st);
+}
+
+static void bmsap(Batch &B, int src, int y) {
+    Ctx *c0 = B.ctx[0];
+    for (int j = 0; j < c0->prm.n_sap; ++j) {
+        const int s = j == 0 ? src : IV_SAPR;
+        for (int colour = 0; colour < 2; ++colour) {
+            BPREC(B.prec, ({
+                      if (B.NR == 4) bphase<P_, 4>(B, colour, j == 0, s, IV_SAPR, IV_SAPX, y);
+                      else if (B.NR == 2) bphase<P_, 2>(B, colour, j == 0, s, IV_SAPR, IV_SAPX, y);
+                      else bphase<P_, 1>(B, colour, j == 0, s, IV_SAPR, IV_SAPX, y);
+                  }));
+        }
+    }
+    long maxc = 0;
+    for (Ctx *c : B.ctx) maxc = std::max(maxc, (long)c->g.NBc * c->g.Vb);
+    dim3 g((unsigned)((4 * maxc + 255) / 256), (unsigned)B.nf, (unsigned)B.max_rhs);
+    BPREC(B.prec, (k_bsap_face<P_><<<g, 256, 0, B.stream>>>(B.dev, 0, IV_SAPR, IV_SAPX, B.st)));
+}
+
+static void bdots(Batch &B, int nd, int a0, int b0, int a1, int b1) {
+    dim3 g(BDOT_BLOCKS, (unsigned)B.nf, (unsigned)B.max_rhs);
+    BPREC(B.prec, (k_bdots<P_, false><<<g, 256, 0, B.stream>>>(B.dev, nd, a0, b0, a1, b1, B.partials)));
+}
+
+static void bscalar(Batch &B, int step, double tol, int maxit) {
+    k_bscalar<<<(B.total + 63) / 64, 64, 0, B.stream>>>(step, B.total, B.partials, B.st, tol, maxit, B.active);
+}
+
+static void bxpay(Batch &B, int z, int x, int which, int y, int masked) {
+    BPREC(B.prec, (k_bxpay<P_><<<vgrid(B), 256, 0, B.stream>>>(B.dev, z, x, which, y, B.st, masked)));
+}
+
+// one inner BiCGStab iteration for every active right-hand side (captured in a graph)
+static void inner_iteration(Batch &B, double tol, int maxit) {
+    bscalar(B, SC_BETA, tol, maxit);
+    BPREC(B.prec, (k_bbicg_p<P_><<<vgrid(B), 256, 0, B.stream>>>(B.dev, B.st)));
+    bmsap(B, IV_P, IV_PH);
+    bxpay(B, IV_V, IV_P, CF_MONE, IV_SAPR, 1);       // v = D p^ = p - r_N
+    bdots(B, 1, IV_RT, IV_V, IV_RT, IV_V);
+    bscalar(B, SC_ALPHA, tol, maxit);
+    bxpay(B, IV_S, IV_R, CF_MALPHA, IV_V, 1);        // s = r - alpha v
+    bmsap(B, IV_S, IV_SH);
+    bxpay(B, IV_T, IV_S, CF_MONE, IV_SAPR, 1);       // t = D s^
+    bdots(B, 2, IV_T, IV_S, IV_T, IV_T);
+    bscalar(B, SC_OMEGA, tol, maxit);
+    BPREC(B.prec, (k_bupdate_e<P_><<<vgrid(B), 256, 0, B.stream>>>(B.dev, B.st)));
+    bxpay(B, IV_R, IV_S, CF_MOMEGA, IV_T, 1);        // r = s - omega t
+    bdots(B, 2, IV_RT, IV_R, IV_R, IV_R);
+    bscalar(B, SC_UPDATE, tol, maxit);
+}
+
+static int hipok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return SAPQ_OK;
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return SAPQ_EHIP;
+}
+
+}  // namespace sapq
+
+using namespace sapq;
+
+extern "C" {
+
+size_t sapq_batch_arena_bytes(sapq_ctx *const *ctxs, int nctx, const int *nrhs) {
+    if (!ctxs || !nrhs) return 0;
+    Batch B;
+    std::string why;
+    if (setup_batch(B, ctxs, nctx, nrhs, why) != SAPQ_OK) return 0;
+    return layout_batch(B, nullptr);
+}
+
+int sapq_solve_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *const *x, const double *const *b,
+                     double tol, void *arena, size_t arena_bytes, sapq_stats *stats) {
+    if (!ctxs || !nrhs || !x || !b || !arena || !(tol > 0)) { set_error("null argument"); return SAPQ_EINVAL; }
+    Batch B;
+    std::string why;
+    int rc = setup_batch(B, ctxs, nctx, nrhs, why);
+    if (rc) { set_error(why); return rc; }
+    if (((uintptr_t)arena) & 255) { set_error("arena must be 256-byte aligned"); return SAPQ_EINVAL; }
+    size_t need = layout_batch(B, nullptr);
+    if (arena_bytes < need) { set_error("batch arena too small: need " + std::to_string(need)); return SAPQ_ENOMEM; }
+    layout_batch(B, (char *)arena);
+    auto t0 = std::chrono::steady_clock::now();
+    // graphs cannot be captured on the legacy default stream: run the batch on a stream of its
+    // own (default priority), ordered after the work already queued on the caller's stream
+    hipStream_t caller = B.stream, s = nullptr;
+    if ((rc = hipok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
+    {
+        hipEvent_t ev;
+        if ((rc = hipok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate"))) {
+            (void)hipStreamDestroy(s);
+            return rc;
+        }
+        (void)hipEventRecord(ev, caller);
+        (void)hipStreamWaitEvent(s, ev, 0);
+        (void)hipStreamSynchronize(s);
+        (void)hipEventDestroy(ev);
+    }
+    B.stream = s;
+    // the context launchers below (pack / unpack) use the context's stream: point it at ours
+    std::vector<hipStream_t> saved;
+    for (Ctx *c : B.ctx) {
+        saved.push_back(c->stream);
+        c->stream = s;
+    }
+    Ctx *c0 = B.ctx[0];
+    rc = hipok(hipMemcpyAsync(B.dev, &B.host, sizeof(BatchDev), hipMemcpyHostToDevice, s), "copy batch descriptor");
+    if (rc == SAPQ_OK) rc = hipok(hipHostMalloc((void **)&B.host_active, 4 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        for (size_t f = 0; f < B.ctx.size(); ++f) B.ctx[f]->stream = saved[f];
+        (void)hipStreamDestroy(s);
+        return rc;
+    }
+    std::vector<BState> hst(B.total);
+    std::vector<double> hscale(B.total), bnorm(B.total), relres(B.total, 1.0);
+    std::vector<int> outer_its(B.total, 0), inner_its(B.total, 0), conv(B.total, 0);
+    std::vector<double2> dres(B.total * 2);
+    // pack sources, zero solutions
+    for (int f = 0; f < B.nf; ++f) {
+        Ctx *c = B.ctx[f];
+        BField &F = B.host.f[f];
+        for (int k = 0; k < F.nrhs; ++k) {
+            launch_pack_spinor(c, SAPQ_FP64, F.dv[DV_B] + (size_t)k * c->nvec, b[f] + (size_t)k * c->V * 24, 1.0);
+            (void)hipMemsetAsync(F.dv[DV_X] + (size_t)k * c->nvec, 0, c->nvec * 16, s);
+        }
+    }
+    auto outer_norms = [&](int a, int bslot, int cslot, int dslot) {
+        dim3 g(BDOT_BLOCKS, (unsigned)B.nf, (unsigned)B.max_rhs);
+        k_bdots<SAPQ_FP64, true><<<g, 256, 0, s>>>(B.dev, 2, a, bslot, cslot, dslot, B.partials);
+        std::vector<double> hp((size_t)B.total * BDOT_BLOCKS * 4);
+        (void)hipMemcpyAsync(hp.data(), B.partials, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        (void)hipStreamSynchronize(s);
+        for (int q = 0; q < B.total; ++q) {
+            double v0 = 0, v1 = 0;
+            for (int bb = 0; bb < BDOT_BLOCKS; ++bb) {
+                v0 += hp[((size_t)q * BDOT_BLOCKS + bb) * 4 + 0];
+                v1 += hp[((size_t)q * BDOT_BLOCKS + bb) * 4 + 2];
+            }
+            dres[2 * q] = make_double2(v0, 0);
+            dres[2 * q + 1] = make_double2(v1, 0);
+        }
+    };
+    outer_norms(DV_B, DV_B, DV_B, DV_B);
+    for (int q = 0; q < B.total; ++q) bnorm[q] = std::sqrt(dres[2 * q].x);
+    dim3 vg(256, (unsigned)B.nf, (unsigned)B.max_rhs);
+    dim3 dg((unsigned)((4 * B.max_V + 255) / 256), (unsigned)B.nf, (unsigned)B.max_rhs);
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const double tol_in = c0->prm.tol_inner;
+    const int maxit_in = c0->prm.maxit_inner;
+    int outer = 0;
+    rc = SAPQ_OK;
+    while (outer < c0->prm.maxit_outer) {
+        // true residual r = b - D x and convergence per right-hand side
+        k_bdslash64<<<dg, 256, 0, s>>>(B.dev, DV_T, DV_X);
+        k_bresid<<<vg, 256, 0, s>>>(B.dev);
+        outer_norms(DV_R, DV_R, DV_R, DV_R);
+        int left = 0;
+        for (int q = 0; q < B.total; ++q) {
+            relres[q] = bnorm[q] > 0 ? std::sqrt(dres[2 * q].x) / bnorm[q] : 0.0;
+            conv[q] = relres[q] <= tol;
+            hscale[q] = conv[q] ? 0.0 : std::sqrt((double)B.ctx[0]->nvec) / std::max(1e-300, std::sqrt(dres[2 * q].x));
+            left += !conv[q];
+        }
+        // per-field scale: unit RMS per complex component of that field
+        for (int f = 0; f < B.nf; ++f)
+            for (int k = 0; k < B.host.f[f].nrhs; ++k) {
+                int q = B.host.f[f].rhs0 + k;
+                if (!conv[q]) hscale[q] = std::sqrt((double)B.ctx[f]->nvec) / std::sqrt(dres[2 * q].x);
+            }
+        if (!left) break;
+        ++outer;
+        // inner solve of D e = r (scaled) for the unconverged right-hand sides
+        for (int q = 0; q < B.total; ++q) {
+            memset(&hst[q], 0, sizeof(BState));
+            hst[q].done = conv[q];
+            if (!conv[q]) outer_its[q]++;
+        }
+        (void)hipMemcpyAsync(B.st, hst.data(), sizeof(BState) * B.total, hipMemcpyHostToDevice, s);
+        (void)hipMemcpyAsync(B.scale, hscale.data(), sizeof(double) * B.total, hipMemcpyHostToDevice, s);
+        BPREC(B.prec, (k_bconvert_in<P_><<<vg, 256, 0, s>>>(B.dev, B.scale)));
+        BPREC(B.prec, (k_bcopy<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_R, IV_RIN)));
+        BPREC(B.prec, (k_bcopy<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_RT, IV_RIN)));
+        BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_P)));
+        BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_V)));
+        BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_E)));
+        bdots(B, 2, IV_RT, IV_R, IV_R, IV_R);
+        bscalar(B, SC_INIT, tol_in, maxit_in);
+        if (!gexec) {
+            if ((rc = hipok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))) break;
+            inner_iteration(B, tol_in, maxit_in);
+            if ((rc = hipok(hipStreamEndCapture(s, &graph), "hipStreamEndCapture"))) break;
+            if ((rc = hipok(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate"))) break;
+        }
+        for (int it = 0; it < maxit_in; ++it) {
+            if ((rc = hipok(hipGraphLaunch(gexec, s), "hipGraphLaunch"))) break;
+            (void)hipMemcpyAsync(B.host_active, B.active, sizeof(int), hipMemcpyDeviceToHost, s);
+            if ((rc = hipok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
+            if (*B.host_active == 0) break;
+        }
+        if (rc) break;
+        (void)hipMemcpyAsync(hst.data(), B.st, sizeof(BState) * B.total, hipMemcpyDeviceToHost, s);
+        BPREC(B.prec, (k_bconvert_out<P_><<<vg, 256, 0, s>>>(B.dev, B.scale)));
+        (void)hipStreamSynchronize(s);
+        for (int q = 0; q < B.total; ++q)
+            if (!conv[q]) inner_its[q] += hst[q].its;
+    }
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc == SAPQ_OK) {
+        // final true residuals, unpack
+        k_bdslash64<<<dg, 256, 0, s>>>(B.dev, DV_T, DV_X);
+        k_bresid<<<vg, 256, 0, s>>>(B.dev);
+        outer_norms(DV_R, DV_R, DV_R, DV_R);
+        for (int f = 0; f < B.nf; ++f) {
+            Ctx *c = B.ctx[f];
+            BField &F = B.host.f[f];
+            for (int k = 0; k < F.nrhs; ++k)
+                launch_unpack_spinor(c, SAPQ_FP64, x[f] + (size_t)k * c->V * 24, F.dv[DV_X] + (size_t)k * c->nvec, 1.0);
+        }
+        rc = hipok(hipStreamSynchronize(s), "sapq_solve_batch");
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    bool all = true;
+    for (int q = 0; q < B.total; ++q) {
+        relres[q] = bnorm[q] > 0 ? std::sqrt(dres[2 * q].x) / bnorm[q] : 0.0;
+        all = all && relres[q] <= tol;
+        if (stats) {
+            memset(&stats[q], 0, sizeof(sapq_stats));
+            stats[q].outer_its = outer_its[q];
+            stats[q].inner_its = inner_its[q];
+            stats[q].true_relres = relres[q];
+            stats[q].time_s = secs;
+        }
+    }
+    (void)hipHostFree(B.host_active);
+    (void)hipStreamSynchronize(s);
+    for (size_t f = 0; f < B.ctx.size(); ++f) B.ctx[f]->stream = saved[f];
+    (void)hipStreamDestroy(s);
+    if (rc) return rc;
+    if (!all) { set_error("some right-hand sides did not reach the tolerance"); return SAPQ_ENOTCONV; }
+    return SAPQ_OK;
+}
+
+}  // extern "C"

@@ -305,3 +305,7 @@ size_t elem_bytes(int prec);  // bytes of one stored complex
 void set_error(const std::string &msg);
 
 }  // namespace sapq
+
+struct sapq_ctx {
+    sapq::Ctx c;
+};

@@ -77,6 +77,10 @@ _SIGS = {
     "sapq_nn_backward": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sapq_nn_train_step": (ctypes.c_int, [_P, _P, ctypes.c_long, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                           ctypes.c_float, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "sapq_batch_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "sapq_solve_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_P),
+                                        ctypes.POINTER(_P), ctypes.c_double, _P, ctypes.c_size_t, ctypes.POINTER(Stats)]),
+    "sapq_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
     "sapq_destroy": (None, [_P]),
     "sapq_last_error": (ctypes.c_char_p, []),
 }
@@ -207,6 +211,12 @@ class Solver:
             _check(rc)
         return x, st.as_dict()
 
+    def autotune(self, cache_path=None):
+        """Pick the fastest sub-block shape (sapq_autotune); returns it."""
+        out = (ctypes.c_int * 4)()
+        _check(lib().sapq_autotune(self.h, cache_path.encode() if cache_path else None, out))
+        return tuple(out)
+
     # ------------------------------------------------------------------ learned stage
     def use_nn(self, on=True):
         """Switch the learned stage of the inner preconditioner on or off (needs nn=True at creation)."""
@@ -245,6 +255,30 @@ class Solver:
         _check(lib().sapq_nn_train_step(self.h, ctypes.c_void_p(e.data_ptr()), e.shape[0], ib, len(idx), lr, t,
                                         ctypes.byref(loss)))
         return loss.value
+
+
+def solve_batch(solvers, sources, tol=1e-10, check=True):
+    """Solve every source of every solver's field together (sapq_solve_batch).  sources[i]:
+    complex128 GPU tensor [nrhs_i, V_i, 4, 3].  Returns (solutions, per-source stats dicts)."""
+    n = len(solvers)
+    ctxs = (_P * n)(*[s.h for s in solvers])
+    nrhs = (ctypes.c_int * n)(*[int(b.shape[0]) for b in sources])
+    for s, b in zip(solvers, sources):
+        if b.dtype != torch.complex128 or not b.is_contiguous() or tuple(b.shape[1:]) != (s.V, 4, 3):
+            raise TypeError("expected contiguous complex128 sources [nrhs, V, 4, 3]")
+    xs = [torch.empty_like(b) for b in sources]
+    xp = (_P * n)(*[x.data_ptr() for x in xs])
+    bp = (_P * n)(*[b.data_ptr() for b in sources])
+    nbytes = lib().sapq_batch_arena_bytes(ctxs, n, nrhs)
+    if nbytes == 0:
+        raise SapqError(-1, "batch not allowed (shapes, precisions or block size)")
+    arena = torch.empty(nbytes, dtype=torch.uint8, device=solvers[0].device)
+    total = sum(int(b.shape[0]) for b in sources)
+    st = (Stats * total)()
+    rc = lib().sapq_solve_batch(ctxs, n, nrhs, xp, bp, tol, ctypes.c_void_p(arena.data_ptr()), nbytes, st)
+    if check:
+        _check(rc)
+    return xs, [st[i].as_dict() for i in range(total)]
 
 
 def nn_param_count():
