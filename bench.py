@@ -113,6 +113,89 @@ def precision_study(args):
           flush=True)
 
 
+BATCH_FIELDS = [((16, 16, 16, 32), 0.2, 11), ((24, 24, 24, 48), 0.25, 12), ((24, 24, 24, 48), 0.3, 13),
+                ((32, 32, 32, 64), 0.25, 14)]
+
+
+def batch_study(args):
+    """The batched workload: 12 spin-colour point sources on each of four gauge fields of mixed
+    sizes (16^3x32 eps 0.2, 24^3x48 eps 0.25 and 0.3, 32^3x64 eps 0.25), kappa 0.125, 4^4 SAP
+    blocks with the sub-block shape chosen by the autotuner, solved together by one
+    sapq_solve_batch call (graph-captured inner iterations); compared with solving the same
+    48 sources one at a time.  Prints one JSON line."""
+    import tempfile
+
+    import torch
+
+    from paper_1210_7398_amd import sapq, synth
+
+    kappa, B = 0.125, (4, 4, 4, 4)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    flds = []
+    for L, eps, seed in BATCH_FIELDS:
+        U = synth.gauge_field(L, eps, seed, device=dev)
+        F = synth.clover_inverse(L, U, 1.0, kappa, device=dev)
+        flds.append((L, U, F))
+        torch.cuda.synchronize()
+        print(f"# field {L} ready after {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    print(f"# fields generated on the GPU in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    cache = os.path.join(tempfile.mkdtemp(), "tune.jsonl")
+    L0, U0, F0 = flds[0]
+    tuner = sapq.Solver(L0, B, (2, 2, 2, 2), kappa, prec=args.prec, outer="defect", device=dev)
+    tuner.load_gauge(U0)
+    tuner.load_clover(F0)
+    t0 = time.time()
+    S = tuner.autotune(cache)
+    tune_s = time.time() - t0
+    tuner.close()
+    print(f"# autotuned sub-block {S} in {tune_s:.1f} s", file=sys.stderr, flush=True)
+    solvers, srcs = [], []
+    for L, U, F in flds:
+        s = sapq.Solver(L, B, S, kappa, prec=args.prec, outer="defect", device=dev)
+        s.load_gauge(U)
+        s.load_clover(F)
+        V = synth.volume(L)
+        b = torch.zeros((12, V, 4, 3), dtype=torch.complex128, device=dev)
+        for k in range(12):
+            b[k, 0, k % 4, k // 4] = 1.0
+        solvers.append(s)
+        srcs.append(b)
+    del flds
+    xs, st = sapq.solve_batch(solvers, srcs, tol=1e-10)  # warm-up
+    times = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xs, st = sapq.solve_batch(solvers, srcs, tol=1e-10)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+    t_batch = sorted(times)[len(times) // 2]
+    print(f"# batched: {t_batch:.3f} s for 48 sources", file=sys.stderr, flush=True)
+    # the same 48 sources one at a time with the one-source solver
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    seq_stats = []
+    for s, b in zip(solvers, srcs):
+        for k in range(b.shape[0]):
+            _, sk = s.solve(b[k].contiguous(), tol=1e-10)
+            seq_stats.append(sk)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t1
+    print(f"# one at a time: {t_seq:.3f} s", file=sys.stderr, flush=True)
+    out = {
+        "mode": "batch", "metric": "time-to-1e-10 residual (s), 48 sources on 4 fields", "prec": args.prec,
+        "fields": [dict(lattice=list(L), eps=eps, seed=seed, sources=12) for L, eps, seed in BATCH_FIELDS],
+        "kappa": kappa, "block": list(B), "subblock": list(S), "autotune_s": tune_s,
+        "batched_s": t_batch, "one_at_a_time_s": t_seq, "speedup": t_seq / t_batch,
+        "batched_max_true_relres": max(x["true_relres"] for x in st),
+        "batched_outer_its_max": max(x["outer_its"] for x in st),
+        "batched_inner_its_total": sum(x["inner_its"] for x in st),
+        "one_at_a_time_max_true_relres": max(x["true_relres"] for x in seq_stats),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def phase_model(B, n_ssor, prec_bytes):
     """Algorithmic bytes and flops per site of one SAP phase kernel launch (a cycle after the
     first: it gathers the other colour and accumulates y).  Each operand is counted once."""
@@ -158,7 +241,7 @@ def main():
     ap.add_argument("--workload", default="24^3x48", choices=list(WORKLOADS))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision", "batch", "nn"])
     ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -170,6 +253,9 @@ def main():
         return
     if args.mode == "precision":
         precision_study(args)
+        return
+    if args.mode == "batch":
+        batch_study(args)
         return
 
     import numpy as np

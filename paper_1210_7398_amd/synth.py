@@ -41,18 +41,70 @@ def su3_from_normals(h, eps):
     return np.einsum("...ij,...j,...kj->...ik", vec, ph, vec.conj())
 
 
-def gauge_field(L, eps, seed):
+def gauge_field(L, eps, seed, device=None):
     """U_mu(n) = exp(i eps H), H Gaussian traceless hermitian, drawn as normals of shape
-    (Lt, Lz, Ly, Lx, 4, 8) from numpy's default_rng(seed); returns [V, 4, 3, 3]."""
+    (Lt, Lz, Ly, Lx, 4, 8) from numpy's default_rng(seed); returns [V, 4, 3, 3] (numpy).
+    With a torch device the exponential is taken there and a torch tensor is returned (same
+    draws; the eigendecomposition rounds differently)."""
     Lx, Ly, Lz, Lt = L
     rng = np.random.default_rng(seed)
     V = volume(L)
-    U = np.empty((V, 4, 3, 3), np.complex128)
     h = rng.normal(size=(Lt, Lz, Ly, Lx, 4, 8)).reshape(V, 4, 8)
+    if device is not None:
+        import torch
+
+        U = torch.empty((V, 4, 3, 3), dtype=torch.complex128, device=device)
+        gm = torch.from_numpy(_GM).to(device)
+        chunk = 1 << 20
+        for s in range(0, V, chunk):
+            hc = torch.from_numpy(h[s : s + chunk]).to(device).to(torch.complex128)
+            X = (1j * eps * 0.5) * torch.einsum("...a,aij->...ij", hc, gm)
+            U[s : s + chunk] = _su3_exp_torch(X)
+        return U
+    U = np.empty((V, 4, 3, 3), np.complex128)
     chunk = 1 << 18
     for s in range(0, V, chunk):
         U[s : s + chunk] = su3_from_normals(h[s : s + chunk], eps)
     return U
+
+
+def _su3_exp_torch(X, squarings=6, order=10):
+    """exp(X) for traceless anti-hermitian 3x3 X by scaling and squaring of a Taylor series
+    (|X| / 2^6 < 0.05 here, so order 10 is exact to rounding), then projected onto SU(3):
+    rows 0 and 1 orthonormalised, row 2 = conj(row0 x row1)."""
+    import torch
+
+    Y = X / (2**squarings)
+    eye = torch.eye(3, dtype=X.dtype, device=X.device).expand_as(Y)
+    E = eye.clone()
+    term = eye.clone()
+    for k in range(1, order + 1):
+        term = (term @ Y) / k
+        E = E + term
+    for _ in range(squarings):
+        E = E @ E
+    r0 = E[..., 0, :]
+    r0 = r0 / torch.linalg.vector_norm(r0, dim=-1, keepdim=True)
+    r1 = E[..., 1, :]
+    r1 = r1 - (r0.conj() * r1).sum(-1, keepdim=True) * r0
+    r1 = r1 / torch.linalg.vector_norm(r1, dim=-1, keepdim=True)
+    r2 = torch.linalg.cross(r0, r1).conj()
+    return torch.stack([r0, r1, r2], dim=-2)
+
+
+def _inverse_torch(A):
+    """Batched inverse by Gauss-Jordan elimination without pivoting (A = 1 - small term here,
+    so the pivots stay near 1)."""
+    import torch
+
+    n = A.shape[-1]
+    M = torch.cat([A, torch.eye(n, dtype=A.dtype, device=A.device).expand_as(A)], dim=-1).clone()
+    for k in range(n):
+        M[..., k, :] = M[..., k, :] / M[..., k, k : k + 1]
+        f = M[..., :, k : k + 1].clone()
+        f[..., k, :] = 0
+        M = M - f * M[..., k : k + 1, :]
+    return M[..., n:].contiguous()
 
 
 def unit_gauge(L):
@@ -103,7 +155,7 @@ def _shift(f, L, mu, step):
     return torch.roll(g, -step, dims=3 - mu).reshape(f.shape)
 
 
-def clover_inverse(L, U, csw, kappa):
+def clover_inverse(L, U, csw, kappa, device=None):
     """Inverse clover field F(n) = (1 - c_SW kappa sum_{mu<nu} sigma_mu_nu F_mu_nu(n))^-1 as two
     chiral 6x6 blocks [V, 2, 6, 6]; F_mu_nu is the four-leaf clover (Q - Q^+)/(8i), traceless,
     sigma_mu_nu = (i/2)[gamma_mu, gamma_nu].  Periodic gauge field (no fermion phases).
@@ -112,12 +164,14 @@ def clover_inverse(L, U, csw, kappa):
 
     V = volume(L)
     g = gamma_matrices()
-    Ut = torch.from_numpy(np.ascontiguousarray(U))
-    dag = lambda m: m.conj().transpose(-1, -2)
+    on_dev = isinstance(U, torch.Tensor)
+    dev = U.device if on_dev else torch.device("cpu")
+    Ut = U if on_dev else torch.from_numpy(np.ascontiguousarray(U))
+    dag = lambda m: m.conj().transpose(-1, -2).contiguous()
     # A is block diagonal in the chiral basis: build its two 6x6 blocks directly
-    A = torch.zeros((V, 2, 6, 6), dtype=torch.complex128)
-    A[:] = torch.eye(6, dtype=torch.complex128)
-    eye3 = torch.eye(3, dtype=torch.complex128)
+    A = torch.zeros((V, 2, 6, 6), dtype=torch.complex128, device=dev)
+    A[:] = torch.eye(6, dtype=torch.complex128, device=dev)
+    eye3 = torch.eye(3, dtype=torch.complex128, device=dev)
     for mu in range(4):
         for nu in range(mu + 1, 4):
             Umu = Ut[:, mu].contiguous()
@@ -139,11 +193,13 @@ def clover_inverse(L, U, csw, kappa):
             Fmn = (Q - dag(Q)) / 8j
             tr = Fmn.diagonal(dim1=1, dim2=2).sum(-1) / 3.0
             Fmn -= tr[:, None, None] * eye3
-            sig = torch.from_numpy(0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu]))
+            sig = torch.from_numpy(0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu])).to(dev)
             for k in range(2):
                 sk = sig[2 * k : 2 * k + 2, 2 * k : 2 * k + 2]
                 blk = sk[None, :, None, :, None] * Fmn[:, None, :, None, :]
                 A[:, k] -= csw * kappa * blk.reshape(V, 6, 6)
+    if on_dev:
+        return _inverse_torch(A)
     return np.ascontiguousarray(torch.linalg.inv(A).numpy())
 
 
