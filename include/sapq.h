@@ -95,6 +95,7 @@ typedef struct {
 #define SAPQ_FLAG_PROFILE 2 /* sapq_solve times its kernels with HIP events (see sapq_stats) */
 #define SAPQ_FLAG_NN 4      /* reserve the learned stage (at sapq_create) and use it in the inner
                                solver once weights are set (see sapq_nn_*) */
+#define SAPQ_FLAG_NN_FP32 8 /* learned-stage layers in FP32 FMAs instead of BF16 MFMA */
 
 /* Per-solve statistics (host struct). */
 typedef struct {
@@ -219,8 +220,10 @@ int sapq_autotune(sapq_ctx *ctx, const char *cache_json_path, int *subblock_out)
  * inner solver's preconditioner becomes z = N r + M_SAP (r - D N r), which is linear in r,
  * so the inner BiCGStab still sees a fixed operator, and plain SAP is the fallback.
  * Weight blob: sapq_nn_param_count() floats, layer after layer, W[9][c_out][c_in][4][4]
- * complex as (re, im) pairs.  The layers compute in FP32 with the weights rounded to BF16;
- * Adam keeps FP32 master weights.  All sapq_nn_* calls need a context created with
+ * complex as (re, im) pairs.  The weights are used rounded to BF16 (Adam keeps FP32 master
+ * weights).  By default a layer's spin/channel mixing is a BF16 MFMA contraction with FP32
+ * accumulation over BF16-rounded transported inputs; with SAPQ_FLAG_NN_FP32 the layers use
+ * FP32 FMAs on FP32 inputs instead.  All sapq_nn_* calls need a context created with
  * params.flags & SAPQ_FLAG_NN (else SAPQ_ESTATE); training needs prec_inner = SAPQ_FP32.
  */
 #define SAPQ_NN_CHANNELS 8

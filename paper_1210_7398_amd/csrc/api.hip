@@ -214,6 +214,8 @@ static void carve(Ctx *c, Arena &A, const HostTables &T) {
         for (auto &e : f) *e.p = (float2 *)A.take(nv * e.ch * sizeof(float2));
         c->i_z = A.take(nv * eb);
         c->i_rp = A.take(nv * eb);
+        for (int k = 0; k < 3; ++k) c->nn_afrag[k] = A.take(nn_afrag_elems(NN_CIN[k], NN_COUT[k]) * 2);
+        c->nn_afrag_t = A.take(nn_afrag_elems(NN_C, NN_C) * 2);
     }
     c->partials = (double2 *)A.take(RED_BLOCKS * 3 * sizeof(double2));
     c->dev_res = (double2 *)A.take(8 * sizeof(double2));
@@ -441,12 +443,28 @@ static void msap(Ctx *c, const void *v, void *y) {
 
 namespace sapq {
 
+static bool nn_use_mfma(const Ctx *c) { return !(c->prm.flags & SAPQ_FLAG_NN_FP32); }
+
+// BF16 fragments of the three layers, rebuilt whenever the weights change
+static void nn_prepare(Ctx *c) {
+    const float2 *W = (const float2 *)c->nn_wq;
+    for (int k = 0; k < 3; ++k) launch_nn_afrag(c, NN_CIN[k], NN_COUT[k], W + NN_OFF[k] / 2, c->nn_afrag[k]);
+}
+
+// one layer: MFMA with BF16 operands, or FP32 FMAs when SAPQ_FLAG_NN_FP32 is set
+static void nn_layer(Ctx *c, int k, const float2 *in, float2 *out) {
+    const float2 *W = (const float2 *)c->nn_wq;
+    if (nn_use_mfma(c))
+        launch_nn_layer_mfma(c, NN_CIN[k], NN_COUT[k], in, out, c->nn_afrag[k]);
+    else
+        launch_nn_layer(c, NN_CIN[k], NN_COUT[k], in, out, W + NN_OFF[k] / 2);
+}
+
 // z = N r on FP32 internal fields (nn_a0 holds r; activations stay for a backward pass)
 static void nn_forward(Ctx *c) {
-    const float2 *W = (const float2 *)c->nn_wq;
-    launch_nn_layer(c, NN_CIN[0], NN_COUT[0], c->nn_a0, c->nn_a1, W + NN_OFF[0] / 2);
-    launch_nn_layer(c, NN_CIN[1], NN_COUT[1], c->nn_a1, c->nn_a2, W + NN_OFF[1] / 2);
-    launch_nn_layer(c, NN_CIN[2], NN_COUT[2], c->nn_a2, c->nn_z, W + NN_OFF[2] / 2);
+    nn_layer(c, 0, c->nn_a0, c->nn_a1);
+    nn_layer(c, 1, c->nn_a1, c->nn_a2);
+    nn_layer(c, 2, c->nn_a2, c->nn_z);
 }
 
 // nn_G += dL/dW and nn_gin = N^+ nn_gz, for the activations of the last nn_forward
@@ -459,7 +477,12 @@ static void nn_backward(Ctx *c) {
     for (int k = 2; k >= 0; --k) {
         launch_nn_wgrad(c, NN_CIN[k], NN_COUT[k], gout, acts[k], G + NN_OFF[k] / 2);
         launch_nn_adjoint_weights(c, NN_CIN[k], NN_COUT[k], W + NN_OFF[k] / 2, c->nn_wt);
-        launch_nn_layer(c, NN_COUT[k], NN_CIN[k], gout, gin[k], c->nn_wt);
+        if (nn_use_mfma(c)) {
+            launch_nn_afrag(c, NN_COUT[k], NN_CIN[k], c->nn_wt, c->nn_afrag_t);
+            launch_nn_layer_mfma(c, NN_COUT[k], NN_CIN[k], gout, gin[k], c->nn_afrag_t);
+        } else {
+            launch_nn_layer(c, NN_COUT[k], NN_CIN[k], gout, gin[k], c->nn_wt);
+        }
         gout = gin[k];
     }
 }
@@ -721,6 +744,7 @@ int sapq_nn_set_weights(sapq_ctx *h, const float *w) {
     (void)hipMemsetAsync(c->nn_m, 0, NN_PARAMS * sizeof(float), c->stream);
     (void)hipMemsetAsync(c->nn_v, 0, NN_PARAMS * sizeof(float), c->stream);
     launch_nn_round(c, NN_PARAMS, c->nn_w, c->nn_wq);
+    nn_prepare(c);
     rc = hipcheck(hipGetLastError(), "sapq_nn_set_weights");
     if (rc == SAPQ_OK) c->have_nn = true;
     return rc;
@@ -785,6 +809,7 @@ int sapq_nn_train_step(sapq_ctx *h, const float *e, long n_vec, const int *idx, 
         nn_backward(c);
     }
     launch_nn_adam(c, NN_PARAMS, c->nn_w, c->nn_G, 1.f / batch, c->nn_m, c->nn_v, lr, t, c->nn_wq);
+    nn_prepare(c);
     if (loss) *loss = total / batch;
     return hipcheck(hipGetLastError(), "sapq_nn_train_step");
 }

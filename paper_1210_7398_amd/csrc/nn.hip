@@ -162,6 +162,110 @@ __global__ void k_nn_round(int n, const float *__restrict__ w, float *__restrict
     if (t < n) wq[t] = __bfloat162float(__float2bfloat16(w[t]));
 }
 
+// ---------------------------------------------------------------- MFMA layer
+// For a tile of 16 sites a layer is the real GEMM
+//   [out_r; out_i] (2M x 48) = [[W_r, -W_i], [W_i, W_r]] (2M x 2K) * [T_r; T_i] (2K x 48)
+// with rows (re/im, c', alpha), M = 4 c_out; reduction index (re/im, d, c, beta), K = 36 c_in;
+// columns (site, colour).  The transported inputs T are written to LDS in BF16, the weights
+// are pre-arranged in MFMA fragment order (BF16), and v_mfma_f32_16x16x16bf16 accumulates in
+// FP32.  Fragment layout of that instruction (wave64): lane l holds A[l % 16][4 (l / 16) + q],
+// B[4 (l / 16) + q][l % 16] (q = 0..3) and D[4 (l / 16) + q][l % 16].
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr int nn_k2p(int cin) { return (72 * cin + 15) / 16 * 16; }
+__host__ __device__ constexpr int nn_m2p(int cout) { return 8 * cout < 16 ? 16 : (8 * cout + 15) / 16 * 16; }
+
+// Afrag[mt][ks][lane][q] = A[mt*16 + lane%16][ks*16 + 4*(lane/16) + q] (zero padded)
+__global__ void k_nn_afrag(int cin, int cout, const float2 *__restrict__ W, __hip_bfloat16 *__restrict__ A) {
+    const int K = 36 * cin, K2 = 2 * K, K2P = nn_k2p(cin), M = 4 * cout, M2 = 2 * M, M2P = nn_m2p(cout);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M2P * K2P) return;
+    const int q = t % 4, lane = (t / 4) % 64, rest = t / 256;
+    const int ks = rest % (K2P / 16), mt = rest / (K2P / 16);
+    const int r = mt * 16 + lane % 16, k = ks * 16 + 4 * (lane / 16) + q;
+    float v = 0.f;
+    if (r < M2 && k < K2) {
+        const bool imr = r >= M, imc = k >= K;
+        const int rr = imr ? r - M : r, kk = imc ? k - K : k;
+        const int co = rr / 4, al = rr % 4, d = kk / (4 * cin), c = (kk / 4) % cin, be = kk % 4;
+        const float2 w = W[(((size_t)d * cout + co) * cin + c) * 16 + 4 * al + be];
+        v = !imr ? (!imc ? w.x : -w.y) : (!imc ? w.y : w.x);
+    }
+    A[t] = __float2bfloat16(v);
+}
+
+template <int P, int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_nn_layer_mfma(GeomDev g, const float2 *__restrict__ in,
+                                                      float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
+                                                      const typename Prec<P>::S2 *__restrict__ U) {
+    constexpr int K = 36 * CIN, K2 = 2 * K, K2P = nn_k2p(CIN), M = 4 * COUT, M2P = nn_m2p(COUT);
+    constexpr int NS = 16, NC = 48, BPAD = K2P + 8, KS = K2P / 16, MT = M2P / 16, NT = 3;
+    constexpr int B_BYTES = NC * BPAD * 2, D_BYTES = M2P * (NC + 1) * 4;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[B_BYTES > D_BYTES ? B_BYTES : D_BYTES];
+    __hip_bfloat16 (*Bt)[BPAD] = reinterpret_cast<__hip_bfloat16 (*)[BPAD]>(smem);
+    float (*Dt)[NC + 1] = reinterpret_cast<float (*)[NC + 1]>(smem);
+    const long site0 = (long)blockIdx.x * NS;
+    const size_t chan = (size_t)g.V * 12;
+    // 1. transported inputs of the tile, BF16, column = 3 * site + colour
+    for (int w = threadIdx.x; w < NS * 9 * CIN; w += blockDim.x) {
+        const int t = w % NS, rest = w / NS, c = rest % CIN, d = rest / CIN;
+        const long i = site0 + t;
+        const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        cx<float> T[12];
+        nn_transport<P>(T, in + c * chan, g, U, ib, s, d);
+        const int kb = (d * CIN + c) * 4;
+#pragma unroll
+        for (int be = 0; be < 4; ++be)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                Bt[3 * t + a][kb + be] = __float2bfloat16(T[3 * be + a].r);
+                Bt[3 * t + a][K + kb + be] = __float2bfloat16(T[3 * be + a].i);
+            }
+    }
+    for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
+        Bt[w / (K2P - K2)][K2 + w % (K2P - K2)] = __float2bfloat16(0.f);
+    __syncthreads();
+    // 2. MFMA over the reduction index; each wave owns up to three 16x16 output tiles
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = 4 * (lane >> 4);
+    float4_t acc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
+        const int tile = wave + 4 * j;
+        if (tile < MT * NT) {
+            const int mt = tile / NT, nt = tile % NT;
+            const short4_t *Ap = Afrag + (size_t)mt * KS * 64 + lane;
+            const int col = nt * 16 + (lane & 15);
+            for (int ks = 0; ks < KS; ++ks) {
+                const short4_t a = Ap[(size_t)ks * 64];
+                const short4_t b = *reinterpret_cast<const short4_t *>(&Bt[col][ks * 16 + kq]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int tile = wave + 4 * j;
+        if (tile < MT * NT) {
+            const int mt = tile / NT, nt = tile % NT, col = nt * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Dt[mt * 16 + kq + q][col] = acc[j][q];
+        }
+    }
+    __syncthreads();
+    // 3. complex outputs: out[c'](site)[alpha][a] = D[c' 4 + alpha][col] + i D[M + c' 4 + alpha][col]
+    for (int w = threadIdx.x; w < NS * COUT * 12; w += blockDim.x) {
+        const int t = w % NS, rest = w / NS, comp = rest % 12, co = rest / 12;
+        const int r = co * 4 + comp / 3, col = 3 * t + comp % 3;
+        const long i = site0 + t;
+        const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        out[co * chan + ((size_t)ib * 12 + comp) * g.Vb + s] = make_float2(Dt[r][col], Dt[M + r][col]);
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 template <int P>
 static void nn_layer_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {
@@ -174,6 +278,35 @@ static void nn_layer_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out,
         k_nn_layer<P, 8, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
     else if (cin == 8 && cout == 1)
         k_nn_layer<P, 8, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
+}
+
+template <int P>
+static void nn_layer_mfma_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *Af) {
+    using S2 = typename Prec<P>::S2;
+    const unsigned grid = (unsigned)(c->V / 16);
+    const S2 *U = (const S2 *)c->Uin;
+    const short4_t *A = (const short4_t *)Af;
+    if (cin == 1 && cout == 8)
+        k_nn_layer_mfma<P, 1, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
+    else if (cin == 8 && cout == 8)
+        k_nn_layer_mfma<P, 8, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
+    else if (cin == 8 && cout == 1)
+        k_nn_layer_mfma<P, 8, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
+}
+
+size_t nn_afrag_elems(int cin, int cout) { return (size_t)nn_m2p(cout) * nn_k2p(cin); }
+
+void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A) {
+    const int n = (int)nn_afrag_elems(cin, cout);
+    k_nn_afrag<<<(n + 255) / 256, 256, 0, c->stream>>>(cin, cout, W, (__hip_bfloat16 *)A);
+}
+
+void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *A) {
+    switch (c->prm.prec_inner) {
+    case SAPQ_FP32: nn_layer_mfma_p<SAPQ_FP32>(c, cin, cout, in, out, A); break;
+    case SAPQ_FP16: nn_layer_mfma_p<SAPQ_FP16>(c, cin, cout, in, out, A); break;
+    case SAPQ_BF16: nn_layer_mfma_p<SAPQ_BF16>(c, cin, cout, in, out, A); break;
+    }
 }
 
 void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {

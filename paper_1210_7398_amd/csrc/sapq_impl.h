@@ -281,6 +281,8 @@ struct Ctx {
     float2 *nn_a0, *nn_a1, *nn_a2, *nn_z; // layer inputs (1, 8, 8 channels) and output
     float2 *nn_gz, *nn_g2, *nn_g1, *nn_gin, *nn_e;
     void *i_z, *i_rp;                    // N r and r - D N r in inner storage
+    void *nn_afrag[3];                   // BF16 MFMA fragments of the three layers' weights
+    void *nn_afrag_t;                    // fragments of an adjoint layer
 };
 
 constexpr int NN_C = SAPQ_NN_CHANNELS;
@@ -294,6 +296,9 @@ void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2
 void launch_nn_adjoint_weights(Ctx *c, int cin, int cout, const float2 *W, float2 *Wt);
 void launch_nn_adam(Ctx *c, int n, float *w, const float *grad, float gscale, float *m, float *v, float lr, int t, float *wq);
 void launch_nn_round(Ctx *c, int n, const float *w, float *wq);
+size_t nn_afrag_elems(int cin, int cout);
+void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A);
+void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *A);
 void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src);
 
 // bracket a launch with HIP events when profiling is on

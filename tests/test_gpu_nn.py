@@ -1,8 +1,10 @@
 """GPU parity of the learned stage through the C ABI, against the FP64 oracle.
 
-The layers compute in FP32 with BF16-rounded weights; the tests use weights that BF16
-represents exactly, so the only differences are FP32 rounding of ~300-term sums
-(forward 1e-5) and of site sums over 4096 sites (weight gradients 1e-4)."""
+The tests use weights that BF16 represents exactly.  On the FP32-FMA path the only
+differences are FP32 rounding of ~300-term sums (forward 1e-5) and of site sums over 4096
+sites (weight gradients 1e-4).  The default MFMA path also rounds the transported inputs to
+BF16 (2^-9 relative per term, so ~2e-3 per layer): 1e-2 for the three-layer forward, 2e-2 for
+gradients."""
 import numpy as np
 import pytest
 
@@ -40,6 +42,7 @@ def make(torch, name=NAME, **kw):
 
     L, B, S, kappa, eps, bc = GEOMS[name]
     U, F = fields(name)
+    kw.setdefault("nn_fp32", True)
     s = sapq.Solver(L, B, S, kappa, bc=bc, nn=True, **kw)
     s.load_gauge(to_dev(U))
     s.load_clover(to_dev(F))
@@ -60,6 +63,24 @@ def test_nn_forward_parity(torch_cuda, orc):
     assert relerr(z, z_w) < 1e-5
 
 
+def test_nn_mfma_forward_and_backward_parity(torch_cuda, orc):
+    torch = torch_cuda
+    L, B, S, kappa, eps, bc = GEOMS[NAME]
+    U, F = fields(NAME)
+    s = make(torch, nn_fp32=False)
+    w = rand_weights(orc, 11)
+    s.nn_set_weights(torch.from_numpy(w).cuda())
+    r = synth.gaussian_spinor(L, 211)
+    Ws = orc.nn_unflatten(w)
+    z_w, _ = orc.nn_forward(L, U, Ws, r, bc)
+    assert relerr(to_host(s.nn_forward(to_dev(r))), z_w) < 1e-2
+    gz = synth.gaussian_spinor(L, 212)
+    gw, gin = s.nn_backward(to_dev(gz), to_dev(r))
+    grads, gin_w = orc.nn_backward(L, U, Ws, r, gz, bc)
+    assert relerr(gw.cpu().numpy().astype(np.float64), orc.nn_flatten(grads)) < 2e-2
+    assert relerr(to_host(gin), gin_w) < 1e-2
+
+
 def test_nn_forward_gauge_equivariance(torch_cuda, orc):
     from paper_1210_7398_amd import sapq
 
@@ -72,7 +93,7 @@ def test_nn_forward_gauge_equivariance(torch_cuda, orc):
     r = synth.gaussian_spinor(L, 203)
     outs = []
     for Uk, rk in ((U, r), (H.gauge_transform(L, U, g), H.transform_spinor(r, g))):
-        s = sapq.Solver(L, B, S, kappa, nn=True)
+        s = sapq.Solver(L, B, S, kappa, nn=True, nn_fp32=True)
         s.load_gauge(to_dev(Uk))
         s.nn_set_weights(w)
         outs.append(to_host(s.nn_forward(to_dev(rk))))
@@ -124,7 +145,7 @@ def test_nn_solve_true_residual(torch_cuda, orc, outer):
     torch = torch_cuda
     L, B, S, kappa, eps, bc = GEOMS[NAME]
     U, F = fields(NAME)
-    s = make(torch, outer=outer)
+    s = make(torch, outer=outer, nn_fp32=False)
     b = synth.gaussian_spinor(L, 210)
     x0, st0 = s.solve(to_dev(b), tol=1e-10)
     s.nn_set_weights(torch.zeros(orc.nn_param_count(), dtype=torch.float32, device="cuda"))
