@@ -14,6 +14,8 @@ applications at the full lattice) and scales it by the solve's operation counts.
 """
 import argparse
 import hashlib
+
+import numpy as np
 import json
 import os
 import sys
@@ -196,6 +198,95 @@ def batch_study(args):
     print(json.dumps(out), flush=True)
 
 
+def nn_study(args):
+    """The learned-preconditioner workload: the network is trained on the GPU on 2000
+    residual->error pairs from the plain SAP solver on four 16^3x32 fields (eps 0.25, seeds
+    21-24), then 12 spin-colour point sources are solved at 48^3x96 (seed 31), kappa 0.125, 4^4
+    blocks / 2^4 sub-blocks, with plain SAP and with the learned stage ahead of SAP, each with
+    FP32 and FP16 storage inside an FP64 outer iteration.  Prints one JSON line."""
+    import torch
+
+    from paper_1210_7398_amd import sapq, synth, train_nn
+
+    kappa, B, S = 0.125, (4, 4, 4, 4), (2, 2, 2, 2)
+    dev = torch.device("cuda:0")
+    Lt = (16, 16, 16, 32)
+    n_src = int(os.environ.get("SAPQ_NN_SOURCES_PER_FIELD", "100"))
+    steps = int(os.environ.get("SAPQ_NN_STEPS", "600"))
+    t0 = time.time()
+    sets = []
+    for seed in (21, 22, 23, 24):
+        U = synth.gauge_field(Lt, 0.25, seed, device=dev)
+        F = synth.clover_inverse(Lt, U, 1.0, kappa, device=dev)
+        s = sapq.Solver(Lt, B, S, kappa, nn=True, device=dev)
+        s.load_gauge(U)
+        s.load_clover(F)
+        srcs = [torch.from_numpy(synth.gaussian_spinor(Lt, 100 * seed + k)).to(dev) for k in range(n_src)]
+        sets.append((s, train_nn.make_pairs(s, srcs, n_iter=5)))
+        print(f"# training field {seed}: {sets[-1][1].shape[0]} pairs after {time.time() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    gen_s = time.time() - t0
+    w0 = train_nn.init_weights(0, device=dev)
+    for s, _ in sets:
+        s.nn_set_weights(w0)
+    t0 = time.time()
+    losses = train_nn.train(sets, steps=steps, batch=8, lr=2e-3, log=100)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    w = sets[-1][0].nn_get_weights().clone()
+    for s, e in sets:
+        s.close()
+    del sets
+    torch.cuda.empty_cache()
+    print(f"# trained {steps} steps in {train_s:.1f} s, loss {losses[0]:.3f} -> {np.mean(losses[-20:]):.3f}",
+          file=sys.stderr, flush=True)
+
+    La = (48, 48, 48, 96)
+    t0 = time.time()
+    U = synth.gauge_field(La, 0.25, 31, device=dev)
+    F = synth.clover_inverse(La, U, 1.0, kappa, device=dev)
+    torch.cuda.synchronize()
+    print(f"# 48^3x96 field in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    V = synth.volume(La)
+    n_apply = int(os.environ.get("SAPQ_NN_APPLY_SOURCES", "12"))
+    results = []
+    for prec in ("fp32", "fp16"):
+        s = sapq.Solver(La, B, S, kappa, prec=prec, nn=True, device=dev)
+        s.load_gauge(U)
+        s.load_clover(F)
+        s.nn_set_weights(w)
+        for use in (False, True):
+            s.use_nn(use)
+            tot, its, msap, worst = 0.0, 0, 0, 0.0
+            for k in range(n_apply):
+                b = torch.zeros((V, 4, 3), dtype=torch.complex128, device=dev)
+                b[0, k % 4, k // 4 % 3] = 1.0
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                x, st = s.solve(b, tol=1e-10)
+                torch.cuda.synchronize()
+                tot += time.perf_counter() - t1
+                its += st["inner_its"]
+                msap += st["n_msap"]
+                worst = max(worst, st["true_relres"])
+                del x
+            results.append(dict(prec=prec, learned_stage=use, sources=n_apply, time_s=tot, inner_its=its,
+                                n_msap=msap, max_true_relres=worst))
+            print(f"# {results[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    base = results[0]["time_s"]
+    for r in results:
+        r["speedup_vs_plain_fp32"] = base / r["time_s"]
+    print(json.dumps({"mode": "nn", "metric": "time-to-1e-10 residual (s); learned stage + mixed precision vs plain SAP",
+                      "train": dict(lattice=list(Lt), fields=[21, 22, 23, 24], pairs=4 * n_src * 5, steps=steps,
+                                    batch=8, lr=2e-3, pair_generation_s=gen_s, train_s=train_s,
+                                    loss_first=losses[0], loss_last20=float(np.mean(losses[-20:]))),
+                      "apply": dict(lattice=list(La), seed=31, kappa=kappa, block=list(B), subblock=list(S)),
+                      "results": results}), flush=True)
+
+
 def phase_model(B, n_ssor, prec_bytes):
     """Algorithmic bytes and flops per site of one SAP phase kernel launch (a cycle after the
     first: it gathers the other colour and accumulates y).  Each operand is counted once."""
@@ -256,6 +347,9 @@ def main():
         return
     if args.mode == "batch":
         batch_study(args)
+        return
+    if args.mode == "nn":
+        nn_study(args)
         return
 
     import numpy as np
