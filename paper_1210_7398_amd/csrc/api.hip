@@ -255,6 +255,8 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
     c->lds_bytes = (size_t)T.Vb * 12 * sizeof(float2);
     c->lds_extra = (size_t)T.Vb * 4 * sizeof(unsigned) + (MAX_PLANES + 1) * sizeof(int);
     c->ssor_lds = (long)(c->lds_bytes + c->lds_extra) <= (long)max_lds;
+    c->staged_bytes = c->lds_bytes + c->lds_extra + (size_t)T.Vb * 60 * elem_bytes(prm->prec_inner);
+    c->ssor_staged = (long)c->staged_bytes <= (long)max_lds && c->ssor_threads <= 512 && !getenv("SAPQ_NO_STAGING");
     Arena A{nullptr, 0, 0};
     carve(c, A, T);
     return A.used + 256;

@@ -270,6 +270,132 @@ __global__ void __launch_bounds__(NT) k_sap_phase(GeomDev g, SapArgs a, const ty
     }
 }
 
+// Neighbours of lane j inside the block, for fields staged in LDS (block index 0 there);
+// outside neighbours keep their wrapped slot, a valid LDS address, and are masked by the hop.
+__device__ __forceinline__ LaneNbr lane_nbr_local(unsigned w) {
+    LaneNbr n;
+    n.s_f = (int)(w & 0x7fffu);
+    n.in_f = (w & 0x8000u) != 0;
+    n.s_b = (int)((w >> 16) & 0x7fffu);
+    n.in_b = (w & 0x80000000u) != 0;
+    n.ib_f = n.ib_b = 0;
+    n.ph_f = n.ph_b = 1.f;
+    return n;
+}
+
+// The phase kernel for blocks whose links and clover field fit in LDS next to the iterate:
+// they are copied in once and all sweeps and the block hop read LDS only.
+// LDS: [x 12 Vb float2][links 24 Vb S2][clover 36 Vb S2][neighbour words 4 Vb][plane starts]
+template <int P, int NT>
+__global__ void __launch_bounds__(NT) k_sap_phase_staged(GeomDev g, SapArgs a, const typename Prec<P>::S2 *rsrc,
+                                                         typename Prec<P>::S2 *r, typename Prec<P>::S2 *x,
+                                                         typename Prec<P>::S2 *y, const typename Prec<P>::S2 *__restrict__ U,
+                                                         const typename Prec<P>::S2 *__restrict__ F) {
+    using S2 = typename Prec<P>::S2;
+    using C = float;
+    extern __shared__ float2 lds[];
+    const int ib = a.colour * g.NBc + blockIdx.x;
+    const int Vb = g.Vb;
+    float2 *xs = lds;
+    S2 *Ul = reinterpret_cast<S2 *>(xs + 12 * Vb);
+    S2 *Fl = Ul + 24 * Vb;
+    unsigned *nb_lds = reinterpret_cast<unsigned *>(Fl + 36 * Vb);
+    int *ps_lds = reinterpret_cast<int *>(nb_lds + 4 * Vb);
+    const C kappa = a.kappa, omega = a.omega;
+    const S2 *vb = a.ssor_only ? rsrc : r;
+    const int j = threadIdx.x & 3;
+    const int q0 = threadIdx.x >> 2, nq = blockDim.x >> 2;
+    const BlockSrc bs{xs};
+    const int bl_f = g.blk_nbr[(2 * j) * g.NB + ib], bl_b = g.blk_nbr[(2 * j + 1) * g.NB + ib];
+    const float bc = g.bc[j];
+
+    {
+        const S2 *Ug = U + (size_t)ib * 24 * Vb;
+        const S2 *Fg = F + (size_t)ib * 36 * Vb;
+        for (int t = threadIdx.x; t < 24 * Vb; t += blockDim.x) Ul[t] = Ug[t];
+        for (int t = threadIdx.x; t < 36 * Vb; t += blockDim.x) Fl[t] = Fg[t];
+        for (int t = threadIdx.x; t < 4 * Vb; t += blockDim.x) nb_lds[t] = g.nbr16[t];
+        for (int t = threadIdx.x; t <= g.nplanes; t += blockDim.x) ps_lds[t] = g.plane_start[t];
+    }
+    __syncthreads();
+
+    // 1. v_c (gathering the other colour from global memory), zero the iterate
+    for (int s = q0; s < Vb; s += nq) {
+        if (!a.ssor_only) {
+            cx<C> v[3];
+            load_spin(v, rsrc, g, ib, s, j);
+            if (a.gather) {
+                const LaneNbr n = lane_nbr(nb_lds[j * Vb + s], ib, bl_f, bl_b, bc);
+                cx<C> h[12], fh[3];
+                quad_hop_sum<HOP_OUT, false>(h, g, ib, s, j, n, U, FieldSrc<S2, C>{x});
+                lane_clover(fh, h, Fl, g, 0, s, j);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = v[c] + kappa * fh[c];
+            }
+            store_spin(r, g, ib, s, j, v);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xs[(3 * j + c) * Vb + s] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+
+    // 2. sweeps, from LDS
+    for (int sw = 0; sw < a.n_ssor; ++sw) {
+        for (int dir = 0; dir < 2; ++dir) {
+            for (int pi = 0; pi < g.nplanes; ++pi) {
+                const int p = dir == 0 ? pi : g.nplanes - 1 - pi;
+                const int s0 = ps_lds[p], s1 = ps_lds[p + 1];
+                for (int s = s0 + q0; s < s1; s += nq) {
+                    cx<C> v[3];
+                    load_spin(v, vb, g, ib, s, j);
+                    const LaneNbr n = lane_nbr_local(nb_lds[j * Vb + s]);
+                    cx<C> h[12], fh[3];
+                    quad_hop_sum<HOP_IN, false>(h, g, 0, s, j, n, Ul, bs);
+                    lane_clover(fh, h, Fl, g, 0, s, j);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float2 *o = &xs[(3 * j + c) * Vb + s];
+                        float2 ov = *o;
+                        cx<C> nx = v[c] + kappa * fh[c];
+                        *o = make_float2((1.f - omega) * ov.x + omega * nx.r, (1.f - omega) * ov.y + omega * nx.i);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    // 3. outputs
+    for (int s = q0; s < Vb; s += nq) {
+        cx<C> xv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float2 t = xs[(3 * j + c) * Vb + s];
+            xv[c] = {t.x, t.y};
+        }
+        store_spin(x, g, ib, s, j, xv);
+        if (a.ssor_only) continue;
+        cx<C> yv[3];
+        if (a.first) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yv[c] = xv[c];
+        } else {
+            load_spin(yv, y, g, ib, s, j);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) yv[c] = yv[c] + xv[c];
+        }
+        store_spin(y, g, ib, s, j, yv);
+        const LaneNbr n = lane_nbr_local(nb_lds[j * Vb + s]);
+        cx<C> h[12], fh[3], v[3];
+        quad_hop_sum<HOP_IN, false>(h, g, 0, s, j, n, Ul, bs);
+        lane_clover(fh, h, Fl, g, 0, s, j);
+        load_spin(v, r, g, ib, s, j);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = v[c] - xv[c] + kappa * fh[c];
+        store_spin(r, g, ib, s, j, v);
+    }
+}
+
 // r_c += kappa F sum_{hops leaving the block} H x   (r_c -= D_{c,other} x_other); four lanes per site
 template <int P>
 __global__ void __launch_bounds__(256) k_sap_face(GeomDev g, int colour, float kappa, typename Prec<P>::S2 *r,
@@ -485,6 +611,12 @@ static void sap_phase_nt(Ctx *c, const SapArgs &a, const void *rsrc, void *r, vo
 
 template <int P>
 static void sap_phase_t(Ctx *c, const SapArgs &a, const void *rsrc, void *r, void *x, void *y) {
+    if (c->ssor_staged) {
+        using S2 = typename Prec<P>::S2;
+        k_sap_phase_staged<P, 512><<<dim3(c->g.NBc), dim3(c->ssor_threads), c->staged_bytes, c->stream>>>(
+            c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin);
+        return;
+    }
     if (c->ssor_threads <= 512)
         sap_phase_nt<P, 512>(c, a, rsrc, r, x, y);
     else
@@ -506,6 +638,14 @@ static void set_lds_limit(Ctx *c) {
 }
 
 int set_sap_lds_limits(Ctx *c) {
+    if (c->ssor_staged && c->staged_bytes > 65536) {
+        const int bytes = (int)c->staged_bytes;
+        switch (c->prm.prec_inner) {
+        case SAPQ_FP32: (void)hipFuncSetAttribute((const void *)k_sap_phase_staged<SAPQ_FP32, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes); break;
+        case SAPQ_FP16: (void)hipFuncSetAttribute((const void *)k_sap_phase_staged<SAPQ_FP16, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes); break;
+        case SAPQ_BF16: (void)hipFuncSetAttribute((const void *)k_sap_phase_staged<SAPQ_BF16, 512>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes); break;
+        }
+    }
     const size_t need = c->ssor_lds ? c->lds_bytes + c->lds_extra : c->lds_extra;
     if (need <= 65536) return 0;
     set_lds_limit<SAPQ_FP32>(c);

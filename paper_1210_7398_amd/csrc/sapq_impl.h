@@ -253,6 +253,8 @@ struct Ctx {
     bool ssor_lds;
     size_t lds_bytes;   // SSOR iterate in LDS
     size_t lds_extra;   // neighbour words and plane starts in LDS
+    bool ssor_staged;   // links and clover field of a block staged in LDS as well
+    size_t staged_bytes;
     long V;
     size_t nvec;  // 12 V complex entries
     // fields
