@@ -63,14 +63,6 @@ void prof_harvest(Ctx *c) {
     p.used = 0;
 }
 
-// ---------------------------------------------------------------- geometry tables (host)
-struct HostTables {
-    int Vb = 0, NB = 0, nplanes = 0, max_plane = 0;
-    int nbk[4];
-    std::vector<int> loc_nbr, blk_nbr, plane_start, slot_lex, blk_lex;
-    std::vector<int> nbr16;  // packed forward/backward slots per direction (stored as unsigned)
-};
-
 static int check_geom(const sapq_geom *g, std::string &why) {
     for (int m = 0; m < 4; ++m) {
         int L = g->L[m], B = g->block[m], S = g->subblock[m];
@@ -83,90 +75,6 @@ static int check_geom(const sapq_geom *g, std::string &why) {
         if (g->bc_sign[m] != 1 && g->bc_sign[m] != -1) { why = "bc_sign must be +1 or -1"; return SAPQ_EINVAL; }
     }
     return SAPQ_OK;
-}
-
-// Slots sorted by hyperplane h = sum_mu (x_mu mod S_mu); inside a plane by the ll key.
-static void build_tables(const sapq_geom *G, HostTables &T) {
-    const int *B = G->block, *S = G->subblock;
-    int Vb = B[0] * B[1] * B[2] * B[3];
-    int ns[4];
-    for (int m = 0; m < 4; ++m) { ns[m] = B[m] / S[m]; T.nbk[m] = G->L[m] / B[m]; }
-    int Nsub = ns[0] * ns[1] * ns[2] * ns[3];
-    struct Key { int h; long ll; int lex; };
-    std::vector<Key> keys(Vb);
-    for (int l = 0; l < Vb; ++l) {
-        int c[4], r = l;
-        for (int m = 0; m < 4; ++m) { c[m] = r % B[m]; r /= B[m]; }
-        int h = 0; long pos = 0, sub = 0, pm = 1, sm = 1;
-        for (int m = 0; m < 4; ++m) {
-            h += c[m] % S[m];
-            pos += (c[m] % S[m]) * pm; pm *= S[m];
-            sub += (c[m] / S[m]) * sm; sm *= ns[m];
-        }
-        keys[l] = {h, pos * Nsub + sub, l};
-    }
-    std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) { return a.h != b.h ? a.h < b.h : a.ll < b.ll; });
-    T.Vb = Vb;
-    T.slot_lex.resize(Vb);
-    std::vector<int> slot_of(Vb);
-    for (int s = 0; s < Vb; ++s) { T.slot_lex[s] = keys[s].lex; slot_of[keys[s].lex] = s; }
-    int H = keys.back().h + 1;
-    T.nplanes = H;
-    T.plane_start.assign(H + 1, 0);
-    for (auto &k : keys) T.plane_start[k.h + 1]++;
-    for (int p = 0; p < H; ++p) T.plane_start[p + 1] += T.plane_start[p];
-    T.max_plane = 0;
-    for (int p = 0; p < H; ++p) T.max_plane = std::max(T.max_plane, T.plane_start[p + 1] - T.plane_start[p]);
-    // in-block neighbours
-    T.loc_nbr.resize(8 * Vb);
-    for (int s = 0; s < Vb; ++s) {
-        int c[4], r = T.slot_lex[s];
-        for (int m = 0; m < 4; ++m) { c[m] = r % B[m]; r /= B[m]; }
-        for (int mu = 0; mu < 4; ++mu)
-            for (int dir = 0; dir < 2; ++dir) {
-                int cc[4] = {c[0], c[1], c[2], c[3]};
-                cc[mu] += dir == 0 ? 1 : -1;
-                bool inside = cc[mu] >= 0 && cc[mu] < B[mu];
-                cc[mu] = (cc[mu] + B[mu]) % B[mu];
-                int l = cc[0] + B[0] * (cc[1] + B[1] * (cc[2] + B[2] * cc[3]));
-                int t = slot_of[l];
-                T.loc_nbr[(2 * mu + dir) * Vb + s] = inside ? t : -1 - t;
-            }
-    }
-    T.nbr16.resize(4 * Vb);
-    for (int mu = 0; mu < 4; ++mu)
-        for (int s = 0; s < Vb; ++s) {
-            int f = T.loc_nbr[(2 * mu) * Vb + s], b = T.loc_nbr[(2 * mu + 1) * Vb + s];
-            unsigned wf = f >= 0 ? (unsigned)f | 0x8000u : (unsigned)(-1 - f);
-            unsigned wb = b >= 0 ? (unsigned)b | 0x8000u : (unsigned)(-1 - b);
-            T.nbr16[mu * Vb + s] = (int)(wf | (wb << 16));
-        }
-    // blocks: E (colour 0) first, then O, each in lexicographic order
-    int NB = T.nbk[0] * T.nbk[1] * T.nbk[2] * T.nbk[3];
-    T.NB = NB;
-    T.blk_lex.clear();
-    for (int col = 0; col < 2; ++col)
-        for (int b = 0; b < NB; ++b) {
-            int r = b, sum = 0;
-            for (int m = 0; m < 4; ++m) { sum += r % T.nbk[m]; r /= T.nbk[m]; }
-            if ((sum & 1) == col) T.blk_lex.push_back(b);
-        }
-    std::vector<int> ib_of(NB);
-    for (int i = 0; i < NB; ++i) ib_of[T.blk_lex[i]] = i;
-    T.blk_nbr.resize(8 * NB);
-    for (int i = 0; i < NB; ++i) {
-        int c[4], r = T.blk_lex[i];
-        for (int m = 0; m < 4; ++m) { c[m] = r % T.nbk[m]; r /= T.nbk[m]; }
-        for (int mu = 0; mu < 4; ++mu)
-            for (int dir = 0; dir < 2; ++dir) {
-                int cc[4] = {c[0], c[1], c[2], c[3]};
-                cc[mu] += dir == 0 ? 1 : -1;
-                bool wrap = cc[mu] < 0 || cc[mu] >= T.nbk[mu];
-                cc[mu] = (cc[mu] + T.nbk[mu]) % T.nbk[mu];
-                int l = cc[0] + T.nbk[0] * (cc[1] + T.nbk[1] * (cc[2] + T.nbk[2] * cc[3]));
-                T.blk_nbr[(2 * mu + dir) * NB + i] = ib_of[l] | (wrap ? WRAP_BIT : 0);
-            }
-    }
 }
 
 // ---------------------------------------------------------------- arena
@@ -182,7 +90,7 @@ struct Arena {
 
 static const int RED_BLOCKS = 512;
 
-static void carve(Ctx *c, Arena &A, const HostTables &T) {
+static void carve(Ctx *c, Arena &A, const HostTables &T, const PartTables &PT) {
     long V = c->V;
     size_t nv = c->nvec;
     int pi = c->prm.prec_inner;
@@ -202,7 +110,21 @@ static void carve(Ctx *c, Arena &A, const HostTables &T) {
     for (auto p : d64) *p = (double2 *)A.take(nv * 16);
     void **din[] = {&c->i_r, &c->i_rt, &c->i_p, &c->i_v, &c->i_s, &c->i_t, &c->i_e, &c->i_ph, &c->i_sh, &c->i_rin, &c->i_tmp, &c->sap_r, &c->sap_x};
     for (auto p : din) *p = A.take(nv * eb);
-    c->ssor_scratch = c->ssor_lds ? nullptr : (float2 *)A.take(nv * 8);
+    c->ssor_scratch = (c->ssor_lds || c->use_parts) ? nullptr : (float2 *)A.take(nv * 8);
+    c->Ud = nullptr;
+    c->xch = nullptr;
+    c->xsync = nullptr;
+    if (c->use_parts) {
+        c->Ud = A.take((size_t)V * 24 * eb);
+        c->part_gslot = ints(PT.gslot.size());
+        c->part_pstart = ints(MAX_PLANES + 1);
+        c->part_exp = ints(PT.exp_idx.size());
+        c->part_imp = ints(PT.imp.size());
+        c->part_imps = ints(PT.imp_start.size());
+        c->part_nb = (uint2 *)A.take(PT.pnb.size() * sizeof(unsigned));
+        c->xch = (unsigned long long *)A.take((size_t)(T.NB / 2) * PT.NP * 3 * 24 * std::max(PT.Hp, 1) * 8);
+        c->xsync = (unsigned *)A.take(4 * sizeof(unsigned));
+    }
     if (c->prm.flags & SAPQ_FLAG_NN) {
         c->nn_alloc = true;
         float **w[] = {&c->nn_w, &c->nn_wq, &c->nn_G, &c->nn_m, &c->nn_v};
@@ -241,7 +163,38 @@ static int check_params(const sapq_params *p, std::string &why) {
     return SAPQ_OK;
 }
 
-static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTables &T, int max_lds) {
+static int upload_parts(Ctx *c, const PartTables &PT) {
+    struct { void *dst; const void *src; size_t bytes; } cp[] = {
+        {c->part_gslot, PT.gslot.data(), PT.gslot.size() * sizeof(int)},
+        {c->part_pstart, PT.pstart.data(), PT.pstart.size() * sizeof(int)},
+        {c->part_exp, PT.exp_idx.data(), PT.exp_idx.size() * sizeof(int)},
+        {c->part_imp, PT.imp.data(), PT.imp.size() * sizeof(int)},
+        {c->part_imps, PT.imp_start.data(), PT.imp_start.size() * sizeof(int)},
+        {c->part_nb, PT.pnb.data(), PT.pnb.size() * sizeof(unsigned)}};
+    for (auto &e : cp) {
+        int rc = hipcheck(hipMemcpyAsync(e.dst, e.src, e.bytes, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync(part tables)");
+        if (rc) return rc;
+    }
+    return SAPQ_OK;
+}
+
+// The two workgroups of a block wait on each other with a bounded spin; a time-out (or a
+// ticket counter out of step) is recorded on the device and turned into an error here.
+static int parts_status(Ctx *c) {
+    if (!c->use_parts || c->sap_np < 2) return SAPQ_OK;
+    unsigned flag = 0;
+    int rc = hipcheck(hipMemcpyAsync(&flag, c->xsync + 3, sizeof flag, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync(sync)");
+    if (rc == SAPQ_OK) rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    if (flag == 0) return SAPQ_OK;
+    (void)hipMemsetAsync(c->xsync, 0, 4 * sizeof(unsigned), c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    set_error(flag == 1 ? "SAP phase: a workgroup timed out waiting for the other half of its block"
+                        : "SAP phase: workgroup ticket counter out of step");
+    return SAPQ_EHIP;
+}
+
+static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTables &T, PartTables &PT, int max_lds) {
     build_tables(geom, T);
     c->geom = *geom;
     c->prm = *prm;
@@ -257,8 +210,28 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
     c->ssor_lds = (long)(c->lds_bytes + c->lds_extra) <= (long)max_lds;
     c->staged_bytes = c->lds_bytes + c->lds_extra + (size_t)T.Vb * 60 * elem_bytes(prm->prec_inner);
     c->ssor_staged = (long)c->staged_bytes <= (long)max_lds && c->ssor_threads <= 512 && !getenv("SAPQ_NO_STAGING");
+    // Two lanes per site with the block split in two workgroups along t, for blocks whose
+    // iterate does not fit LDS.  SAPQ_PARTS=0 keeps the four-lane kernels, =1 / =2 ask for
+    // one / two parts wherever they fit.
+    int mode = -1;
+    if (const char *e = getenv("SAPQ_PARTS")) mode = atoi(e);
+    c->use_parts = false;
+    c->sap_np = 1;
+    const int np = mode == 1 ? 1 : mode == 2 ? 2 : (mode < 0 && !c->ssor_lds) ? 2 : 0;
+    if (np && build_parts(geom, T, np, PT)) {
+        const size_t lds = 6 * sizeof(float4) * (size_t)(PT.Vp + PT.Hp + 1);
+        if ((long)lds <= (long)max_lds && 2 * PT.max_plane <= 512) {
+            c->use_parts = true;
+            c->sap_np = np;
+            c->part_Vp = PT.Vp;
+            c->part_Hp = PT.Hp;
+            c->part_threads = std::max(64, ((2 * PT.max_plane + 63) / 64) * 64);
+            c->parts_lds = lds;
+            c->ssor_staged = false;
+        }
+    }
     Arena A{nullptr, 0, 0};
-    carve(c, A, T);
+    carve(c, A, T, PT);
     return A.used + 256;
 }
 
@@ -279,10 +252,14 @@ static int device_max_lds() {
 size_t sapq_arena_bytes(const sapq_geom *geom, const sapq_params *params) {
     std::string why;
     if (!geom || !params || check_geom(geom, why) != SAPQ_OK || check_params(params, why) != SAPQ_OK) return 0;
-    Ctx c{};
-    HostTables T;
-    // the LDS decision changes the arena only by the SSOR scratch; plan for the larger case
-    return plan(geom, params, &c, T, 0);
+    // the LDS decisions change the arena (SSOR scratch, or the split kernel's fields and
+    // tables): plan for the larger of no LDS and the 160 KiB of a gfx950 workgroup
+    Ctx c0{}, c1{};
+    HostTables T0, T1;
+    PartTables P0, P1;
+    const size_t a = plan(geom, params, &c0, T0, P0, 0);
+    const size_t b = plan(geom, params, &c1, T1, P1, std::max(device_max_lds(), 160 * 1024));
+    return std::max(a, b);
 }
 
 int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, size_t arena_bytes, void *stream,
@@ -296,7 +273,8 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     sapq_ctx *h = new sapq_ctx();
     Ctx *c = &h->c;
     HostTables T;
-    size_t need = plan(geom, params, c, T, device_max_lds());
+    PartTables PT;
+    size_t need = plan(geom, params, c, T, PT, device_max_lds());
     if (T.max_plane > 4096 || T.Vb > 32767) { delete h; set_error("block too large"); return SAPQ_ESHAPE; }
     if ((long)c->lds_extra > (long)device_max_lds()) { delete h; set_error("block too large for LDS tables"); return SAPQ_ESHAPE; }
     if (T.nplanes > MAX_PLANES) { delete h; set_error("too many hyperplanes"); return SAPQ_ESHAPE; }
@@ -308,7 +286,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     }
     Arena A{(char *)arena, arena_bytes, 0};
     c->nn_alloc = false;
-    carve(c, A, T);
+    carve(c, A, T, PT);
     c->stream = (hipStream_t)stream;
     c->g.Vb = T.Vb;
     c->g.NB = T.NB;
@@ -333,9 +311,17 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
                       "hipMemcpyAsync(tables)");
         if (rc) { hipHostFree(c->host_res); delete h; return rc; }
     }
+    if (c->use_parts) {
+        rc = upload_parts(c, PT);
+        if (rc == SAPQ_OK)
+            rc = hipcheck(hipMemsetAsync(c->xch, 0, (size_t)c->g.NBc * PT.NP * 3 * 24 * std::max(PT.Hp, 1) * 8, c->stream),
+                          "hipMemsetAsync(halo)");
+        if (rc == SAPQ_OK) rc = hipcheck(hipMemsetAsync(c->xsync, 0, 4 * sizeof(unsigned), c->stream), "hipMemsetAsync(sync)");
+        if (rc) { hipHostFree(c->host_res); delete h; return rc; }
+    }
     rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (rc) { hipHostFree(c->host_res); delete h; return rc; }
-    if (set_sap_lds_limits(c)) {
+    if (set_sap_lds_limits(c) || set_parts_lds_limit(c)) {
         hipHostFree(c->host_res);
         delete h;
         set_error("hipFuncSetAttribute refused the LDS size of the SAP kernel");
@@ -368,6 +354,7 @@ int sapq_load_gauge(sapq_ctx *h, const double *U, double *max_dev) {
     Ctx *c = &h->c;
     double dev = 0;
     if (launch_pack_links(c, U, &dev)) return hipcheck(hipGetLastError(), "load_gauge");
+    launch_pack_links_dag(c, U);
     int rc = hipcheck(hipGetLastError(), "k_pack_links");
     if (rc) return rc;
     if (max_dev) *max_dev = dev;
@@ -421,7 +408,8 @@ int sapq_ssor(sapq_ctx *h, double *x, const double *v, int colour) {
     blas_zero(c, pi, c->i_v);
     launch_ssor_only(c, colour, c->i_tmp, c->i_v);
     launch_unpack_spinor(c, pi, x, c->i_v, 1.0);
-    return hipcheck(hipGetLastError(), "sapq_ssor");
+    rc = hipcheck(hipGetLastError(), "sapq_ssor");
+    return rc ? rc : parts_status(c);
 }
 
 // M_SAP on internal inner-precision vectors: y = M_SAP v; c->sap_r = v - D y
@@ -506,7 +494,8 @@ int sapq_dk(sapq_ctx *h, double *x, double *w, const double *v) {
     blas_xpay(c, pi, c->i_v, c->i_tmp, make_double2(-1, 0), c->sap_r);  // w = v - r
     launch_unpack_spinor(c, pi, x, c->sap_x, 1.0);
     launch_unpack_spinor(c, pi, w, c->i_v, 1.0);
-    return hipcheck(hipGetLastError(), "sapq_dk");
+    rc = hipcheck(hipGetLastError(), "sapq_dk");
+    return rc ? rc : parts_status(c);
 }
 
 int sapq_sap_precondition(sapq_ctx *h, double *out, double *d_out, const double *in) {
@@ -522,7 +511,8 @@ int sapq_sap_precondition(sapq_ctx *h, double *out, double *d_out, const double 
         blas_xpay(c, pi, c->i_v, c->i_tmp, make_double2(-1, 0), c->sap_r);
         launch_unpack_spinor(c, pi, d_out, c->i_v, 1.0);
     }
-    return hipcheck(hipGetLastError(), "sapq_sap_precondition");
+    rc = hipcheck(hipGetLastError(), "sapq_sap_precondition");
+    return rc ? rc : parts_status(c);
 }
 
 }  // extern "C"
@@ -825,7 +815,18 @@ static int apply_subblock(Ctx *c, const int S[4]) {
     if (rc) { set_error(why); return rc; }
     HostTables T;
     build_tables(&G, T);
-    if (T.nplanes > MAX_PLANES || T.max_plane * 4 > 512) { set_error("sub-block shape gives too large a hyperplane"); return SAPQ_ESHAPE; }
+    PartTables PT;
+    if (c->use_parts) {
+        if (T.nplanes > MAX_PLANES || !build_parts(&G, T, c->sap_np, PT) || PT.Hp != c->part_Hp || 2 * PT.max_plane > 512) {
+            set_error("sub-block shape does not fit the split of the block");
+            return SAPQ_ESHAPE;
+        }
+        rc = upload_parts(c, PT);
+        if (rc) return rc;
+    } else if (T.nplanes > MAX_PLANES || T.max_plane * 4 > 512) {
+        set_error("sub-block shape gives too large a hyperplane");
+        return SAPQ_ESHAPE;
+    }
     struct { const void *dst; const std::vector<int> *src; } cp[] = {
         {c->g.loc_nbr, &T.loc_nbr}, {c->g.nbr16, &T.nbr16}, {c->g.plane_start, &T.plane_start}, {c->g.slot_lex, &T.slot_lex}};
     for (auto &e : cp) {
@@ -839,6 +840,7 @@ static int apply_subblock(Ctx *c, const int S[4]) {
     c->g.nplanes = T.nplanes;
     c->max_plane = T.max_plane;
     c->ssor_threads = std::min(512, ((4 * T.max_plane + 63) / 64) * 64);
+    if (c->use_parts) c->part_threads = std::max(64, ((2 * PT.max_plane + 63) / 64) * 64);
     return SAPQ_OK;
 }
 
@@ -934,6 +936,7 @@ int sapq_inner_solve(sapq_ctx *h, double *e, const double *r, int *iters) {
     (void)pi;
     if (iters) *iters = its;
     int hr = hipcheck(hipGetLastError(), "sapq_inner_solve");
+    if (hr == SAPQ_OK) hr = parts_status(c);
     return hr ? hr : rc;
 }
 
@@ -956,6 +959,7 @@ int sapq_solve(sapq_ctx *h, double *x, const double *b, double tol, sapq_stats *
     launch_unpack_spinor(c, SAPQ_FP64, x, c->d_x, 1.0);
     int hr = hipcheck(hipStreamSynchronize(c->stream), "sapq_solve");
     if (hr == SAPQ_OK) hr = hipcheck(hipGetLastError(), "sapq_solve");
+    if (hr == SAPQ_OK) hr = parts_status(c);
     prof_harvest(c);
     c->prof.on = false;
     if (st) {

@@ -4,23 +4,6 @@
 
 namespace sapq {
 
-// ================================================================ site index helpers
-// lexicographic site index of internal site (ib, s)
-__device__ __forceinline__ long lex_site(const GeomDev &g, int ib, int s) {
-    int bl = g.blk_lex[ib], l = g.slot_lex[s];
-    long n = 0, stride = 1;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        int bc = bl % g.nbk[m];
-        bl /= g.nbk[m];
-        int c = l % g.B[m];
-        l /= g.B[m];
-        n += (long)(bc * g.B[m] + c) * stride;
-        stride *= (long)g.B[m] * g.nbk[m];
-    }
-    return n;
-}
-
 // ================================================================ layout conversion
 template <int P>
 __global__ void k_pack_spinor(GeomDev g, typename Prec<P>::S2 *dst, const double2 *src, double scale) {
@@ -533,23 +516,6 @@ __global__ void k_zero(size_t n, typename Prec<P>::S2 *d) {
 }
 
 // ================================================================ launchers
-#define PREC_SWITCH(prec, BODY)                                   \
-    switch (prec) {                                               \
-    case SAPQ_FP64: { constexpr int P_ = SAPQ_FP64; BODY; } break; \
-    case SAPQ_FP32: { constexpr int P_ = SAPQ_FP32; BODY; } break; \
-    case SAPQ_FP16: { constexpr int P_ = SAPQ_FP16; BODY; } break; \
-    case SAPQ_BF16: { constexpr int P_ = SAPQ_BF16; BODY; } break; \
-    default: break;                                               \
-    }
-
-#define INNER_SWITCH(prec, BODY)                                  \
-    switch (prec) {                                               \
-    case SAPQ_FP32: { constexpr int P_ = SAPQ_FP32; BODY; } break; \
-    case SAPQ_FP16: { constexpr int P_ = SAPQ_FP16; BODY; } break; \
-    case SAPQ_BF16: { constexpr int P_ = SAPQ_BF16; BODY; } break; \
-    default: break;                                               \
-    }
-
 static inline unsigned grid_for(long n, int t) { return (unsigned)((n + t - 1) / t); }
 static constexpr unsigned BLAS_GRID = 1024;
 
@@ -655,6 +621,10 @@ int set_sap_lds_limits(Ctx *c) {
 }
 
 void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y) {
+    if (c->use_parts) {
+        launch_sap_phase_parts(c, colour, (colour == 1 || !first) ? 1 : 0, first ? 1 : 0, 0, rsrc, r, x, y);
+        return;
+    }
     SapArgs a;
     a.colour = colour;
     a.gather = (colour == 1 || !first) ? 1 : 0;
@@ -667,6 +637,10 @@ void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r,
 }
 
 void launch_ssor_only(Ctx *c, int colour, const void *v, void *x) {
+    if (c->use_parts) {
+        launch_sap_phase_parts(c, colour, 0, 1, 1, v, nullptr, x, nullptr);
+        return;
+    }
     SapArgs a;
     a.colour = colour;
     a.gather = 0;

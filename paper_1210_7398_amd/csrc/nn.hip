@@ -223,8 +223,10 @@ __global__ void __launch_bounds__(256) k_nn_layer_mfma(GeomDev g, const float2 *
                 Bt[3 * t + a][K + kb + be] = __float2bfloat16(T[3 * be + a].i);
             }
     }
-    for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
-        Bt[w / (K2P - K2)][K2 + w % (K2P - K2)] = __float2bfloat16(0.f);
+    if constexpr (K2P > K2) {
+        for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
+            Bt[w / (K2P - K2)][K2 + w % (K2P - K2)] = __float2bfloat16(0.f);
+    }
     __syncthreads();
     // 2. MFMA over the reduction index; each wave owns up to three 16x16 output tiles
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;

@@ -23,12 +23,10 @@
 #include <vector>
 
 #include "../../include/sapq.h"
+#include "tables.h"
 
 namespace sapq {
 
-constexpr int WRAP_BIT = 1 << 30;  // in blk_nbr: the hop crosses the lattice boundary
-constexpr int BLK_MASK = WRAP_BIT - 1;
-constexpr int MAX_PLANES = 64;
 
 // ---------------------------------------------------------------- device geometry
 struct GeomDev {
@@ -88,23 +86,6 @@ __device__ __forceinline__ void st(__hip_bfloat162 *p, cx<float> v) {
     *p = h;
 }
 
-// ---------------------------------------------------------------- neighbours
-// Neighbour of (ib, s) in direction d = 2*mu + (0 forward, 1 backward).
-struct Nbr { int ib, s; float phase; bool inside; };
-
-__device__ __forceinline__ Nbr neighbour(const GeomDev &g, int ib, int s, int d) {
-    int t = g.loc_nbr[d * g.Vb + s];
-    Nbr n;
-    if (t >= 0) {
-        n.ib = ib; n.s = t; n.phase = 1.f; n.inside = true;
-    } else {
-        int b = g.blk_nbr[d * g.NB + ib];
-        n.ib = b & BLK_MASK; n.s = -1 - t; n.inside = false;
-        n.phase = (b & WRAP_BIT) ? g.bc[d >> 1] : 1.f;
-    }
-    return n;
-}
-
 // ---------------------------------------------------------------- spinor / link access
 template <typename S2>
 __device__ __forceinline__ const S2 *spin_at(const S2 *f, const GeomDev &g, int ib, int s) {
@@ -147,65 +128,23 @@ __device__ __forceinline__ void su3_mul(cx<C> out[3], const cx<C> u[9], const cx
     }
 }
 
-// ---------------------------------------------------------------- spin projection
-// Hop term (1 - sgn*gamma_mu) W psi for W = U or U^+ in the chiral basis: project to the
-// two-component half spinor h = (h0, h1), transport it, and rebuild the lower spins.
-template <int MU, int SGN, typename C>
-__device__ __forceinline__ void hop_accum(cx<C> acc[12], const cx<C> psi[12], const cx<C> u[9], bool dag, C phase) {
-    cx<C> h0[3], h1[3];
-    const C s = C(SGN);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const cx<C> p0 = psi[a], p1 = psi[3 + a], p2 = psi[6 + a], p3 = psi[9 + a];
-        if (MU == 0) { h0[a] = p0 + s * itimes(p3); h1[a] = p1 + s * itimes(p2); }
-        if (MU == 1) { h0[a] = p0 + s * p3;         h1[a] = p1 - s * p2; }
-        if (MU == 2) { h0[a] = p0 + s * itimes(p2); h1[a] = p1 - s * itimes(p3); }
-        if (MU == 3) { h0[a] = p0 - s * p2;         h1[a] = p1 - s * p3; }
+// ---------------------------------------------------------------- host dispatch on the storage precision
+#define PREC_SWITCH(prec, BODY)                                   \
+    switch (prec) {                                               \
+    case SAPQ_FP64: { constexpr int P_ = SAPQ_FP64; BODY; } break; \
+    case SAPQ_FP32: { constexpr int P_ = SAPQ_FP32; BODY; } break; \
+    case SAPQ_FP16: { constexpr int P_ = SAPQ_FP16; BODY; } break; \
+    case SAPQ_BF16: { constexpr int P_ = SAPQ_BF16; BODY; } break; \
+    default: break;                                               \
     }
-    cx<C> g0[3], g1[3];
-    su3_mul(g0, u, h0, dag);
-    su3_mul(g1, u, h1, dag);
-    const C ps = phase * s;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const cx<C> q0 = phase * g0[a], q1 = phase * g1[a];
-        acc[a] = acc[a] + q0;
-        acc[3 + a] = acc[3 + a] + q1;
-        if (MU == 0) { acc[6 + a] = acc[6 + a] - ps * itimes(g1[a]); acc[9 + a] = acc[9 + a] - ps * itimes(g0[a]); }
-        if (MU == 1) { acc[6 + a] = acc[6 + a] - ps * g1[a];         acc[9 + a] = acc[9 + a] + ps * g0[a]; }
-        if (MU == 2) { acc[6 + a] = acc[6 + a] - ps * itimes(g0[a]); acc[9 + a] = acc[9 + a] + ps * itimes(g1[a]); }
-        if (MU == 3) { acc[6 + a] = acc[6 + a] - ps * g0[a];         acc[9 + a] = acc[9 + a] - ps * g1[a]; }
-    }
-}
 
-// ---------------------------------------------------------------- clover
-// y = F(n) x with the packed hermitian chiral blocks of (ib, s)
-template <typename S2, typename C>
-__device__ __forceinline__ void clover_mul(cx<C> y[12], const cx<C> x[12], const S2 *F, const GeomDev &g, int ib, int s) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const S2 *p = F + ((size_t)ib * 2 + k) * 18 * g.Vb + s;
-        cx<C> d01 = ld(p), d23 = ld(p + g.Vb), d45 = ld(p + 2 * (size_t)g.Vb);
-        C d[6] = {d01.r, d01.i, d23.r, d23.i, d45.r, d45.i};
-        const cx<C> *xk = x + 6 * k;
-        cx<C> yk[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) yk[i] = d[i] * xk[i];
-        int e = 3;
-#pragma unroll
-        for (int i = 1; i < 6; ++i) {
-#pragma unroll
-            for (int j = 0; j < i; ++j) {
-                cx<C> f = ld(p + (size_t)e * g.Vb);
-                ++e;
-                yk[i] = yk[i] + cmul(f, xk[j]);
-                yk[j] = yk[j] + cmulc(f, xk[i]);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) y[6 * k + i] = yk[i];
+#define INNER_SWITCH(prec, BODY)                                  \
+    switch (prec) {                                               \
+    case SAPQ_FP32: { constexpr int P_ = SAPQ_FP32; BODY; } break; \
+    case SAPQ_FP16: { constexpr int P_ = SAPQ_FP16; BODY; } break; \
+    case SAPQ_BF16: { constexpr int P_ = SAPQ_BF16; BODY; } break; \
+    default: break;                                               \
     }
-}
 
 // ---------------------------------------------------------------- context
 struct Ctx;
@@ -218,6 +157,10 @@ void launch_pack_clover(Ctx *c, const double *F);
 void launch_dslash(Ctx *c, int prec, void *out, const void *in);
 void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y);
 void launch_sap_face(Ctx *c, int colour, void *r, const void *x);
+void launch_pack_links_dag(Ctx *c, const double *U);
+void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_only, const void *rsrc, void *r,
+                            void *x, void *y);
+int set_parts_lds_limit(Ctx *c);
 void launch_ssor_only(Ctx *c, int colour, const void *v, void *x);
 
 // BLAS-1 on internal vectors (n = 12 V complex entries)
@@ -255,6 +198,15 @@ struct Ctx {
     size_t lds_extra;   // neighbour words and plane starts in LDS
     bool ssor_staged;   // links and clover field of a block staged in LDS as well
     size_t staged_bytes;
+    // two-lanes-per-site phase kernel, the block split along t into sap_np workgroups
+    bool use_parts = false;
+    int sap_np = 1, part_Vp = 0, part_Hp = 0, part_threads = 512;
+    size_t parts_lds = 0;
+    int *part_gslot, *part_pstart, *part_exp, *part_imp, *part_imps;
+    uint2 *part_nb;
+    unsigned long long *xch;  // tagged halo words exchanged between the two workgroups of a block
+    unsigned *xsync;          // ticket, done, epoch, error
+    void *Ud;                 // rows 0 and 1 of U_mu(n - mu)^+, inner storage
     long V;
     size_t nvec;  // 12 V complex entries
     // fields

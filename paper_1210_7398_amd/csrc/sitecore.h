@@ -6,6 +6,24 @@
 
 namespace sapq {
 
+// ================================================================ site index
+// lexicographic site index of internal site (ib, s)
+__device__ __forceinline__ long lex_site(const GeomDev &g, int ib, int s) {
+    int bl = g.blk_lex[ib], l = g.slot_lex[s];
+    long n = 0, stride = 1;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        int bc = bl % g.nbk[m];
+        bl /= g.nbk[m];
+        int c = l % g.B[m];
+        l /= g.B[m];
+        n += (long)(bc * g.B[m] + c) * stride;
+        stride *= (long)g.B[m] * g.nbk[m];
+    }
+    return n;
+}
+
+
 // ================================================================ four lanes per site
 // A site is handled by a group of four adjacent lanes; lane j takes direction mu = j
 // (its forward and its backward hop), the four partial hopping sums are added with a

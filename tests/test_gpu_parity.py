@@ -161,3 +161,74 @@ def test_low_precision_solve(torch_cuda, orc, prec, outer):
     assert rr <= 1e-10, (rr, st)
     xo, _, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
     assert ok and relerr(x, xo) < 1e-8
+
+
+# ---------------------------------------------------------------- phase kernel variants
+# The library picks a phase kernel per geometry; SAPQ_PARTS (read when a context is
+# created) forces one: "0" the four-lanes-per-site kernels, "1" two lanes per site in one
+# workgroup per block, "2" two lanes per site with the block split along t into two
+# workgroups that exchange their boundary layers.  Each must reproduce the oracle.
+KERNELS = {"four-lane": "0", "two-lane": "1", "two-lane split": "2"}
+
+
+def _variant_applies(name, kernel):
+    L, B, S, kappa, eps, bc = GEOMS[name]
+    Vb = int(np.prod(B))
+    if kernel == "two-lane":  # the whole iterate and a zero slot in LDS
+        return 96 * (Vb + 1) <= 160 * 1024
+    if kernel == "two-lane split":
+        return (B[3] // S[3]) % 2 == 0 and 96 * (Vb // 2 + Vb // B[3] + 1) <= 160 * 1024
+    return True
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+@pytest.mark.parametrize("kernel", list(KERNELS))
+def test_phase_kernel_variants(torch_cuda, orc, name, kernel, monkeypatch):
+    if not _variant_applies(name, kernel):
+        pytest.skip("variant does not fit this block in LDS")
+    monkeypatch.setenv("SAPQ_PARTS", KERNELS[kernel])
+    L, B, S, kappa, eps, bc = GEOMS[name]
+    U, F = fields(name)
+    s = make_solver(name, n_sap=2)
+    v = synth.gaussian_spinor(L, 121)
+    prm = orc.params(kappa, n_sap=2)
+    for colour in (0, 1):
+        want = orc.ssor(L, B, S, U, F, prm, colour, v, bc=bc)
+        assert relerr(to_host(s.ssor(to_dev(v), colour)), want) < 2e-5, colour
+    y_w, dy_w = orc.msap(L, B, S, U, F, prm, v, bc=bc)
+    # twice in a row: the split kernel's tickets and epochs must carry over between launches
+    for _ in range(2):
+        y, dy = (to_host(t) for t in s.sap_precondition(to_dev(v)))
+        assert relerr(y, y_w) < 2e-5
+        assert relerr(dy, dy_w) < 2e-5
+
+
+@pytest.mark.parametrize("kernel", ["two-lane", "two-lane split"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+def test_phase_kernel_variants_low_precision(torch_cuda, orc, kernel, prec, monkeypatch):
+    name = "12^4/6^4/3^4"
+    monkeypatch.setenv("SAPQ_PARTS", KERNELS[kernel])
+    L, B, S, kappa, eps, bc = GEOMS[name]
+    U, F = fields(name)
+    s = make_solver(name, prec=prec)
+    v = synth.gaussian_spinor(L, 122)
+    y_w, dy_w = orc.msap(L, B, S, U, F, orc.params(kappa), v, bc=bc)
+    y, dy = (to_host(t) for t in s.sap_precondition(to_dev(v)))
+    assert relerr(y, y_w) < PREC_TOL[prec]["msap"]
+    assert relerr(dy, dy_w) < PREC_TOL[prec]["msap"]
+
+
+def test_split_kernel_solve_24x24x24x48_block(torch_cuda, orc):
+    """The split kernel on the 6^3x12 blocks of the 24^3x48 workload, inside a full solve on
+    a 12^3x24 lattice: FP64 true residual 1e-10 and agreement with the oracle's solution."""
+    name = "12^3x24/6^3x12/3^3x6"
+    L, B, S, kappa, eps, bc = GEOMS[name]
+    U, F = fields(name)
+    s = make_solver(name)
+    b = synth.gaussian_spinor(L, 123)
+    for _ in range(2):
+        x, st = s.solve(to_dev(b), tol=1e-10)
+        x = to_host(x)
+        assert relerr(orc.dslash(L, U, F, kappa, x, bc=bc), b) <= 1e-10, st
+    xo, _, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
+    assert ok and relerr(x, xo) < 1e-8
