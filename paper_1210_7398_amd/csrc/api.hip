@@ -111,17 +111,16 @@ static void carve(Ctx *c, Arena &A, const HostTables &T, const PartTables &PT) {
     void **din[] = {&c->i_r, &c->i_rt, &c->i_p, &c->i_v, &c->i_s, &c->i_t, &c->i_e, &c->i_ph, &c->i_sh, &c->i_rin, &c->i_tmp, &c->sap_r, &c->sap_x};
     for (auto p : din) *p = A.take(nv * eb);
     c->ssor_scratch = (c->ssor_lds || c->use_parts) ? nullptr : (float2 *)A.take(nv * 8);
-    c->Ud = nullptr;
     c->xch = nullptr;
     c->xsync = nullptr;
     if (c->use_parts) {
-        c->Ud = A.take((size_t)V * 24 * eb);
         c->part_gslot = ints(PT.gslot.size());
         c->part_pstart = ints(MAX_PLANES + 1);
         c->part_exp = ints(PT.exp_idx.size());
         c->part_imp = ints(PT.imp.size());
         c->part_imps = ints(PT.imp_start.size());
         c->part_nb = (uint2 *)A.take(PT.pnb.size() * sizeof(unsigned));
+        c->part_gnb = (uint2 *)A.take(PT.gnb.size() * sizeof(unsigned));
         c->xch = (unsigned long long *)A.take((size_t)(T.NB / 2) * PT.NP * 3 * 24 * std::max(PT.Hp, 1) * 8);
         c->xsync = (unsigned *)A.take(4 * sizeof(unsigned));
     }
@@ -170,7 +169,8 @@ static int upload_parts(Ctx *c, const PartTables &PT) {
         {c->part_exp, PT.exp_idx.data(), PT.exp_idx.size() * sizeof(int)},
         {c->part_imp, PT.imp.data(), PT.imp.size() * sizeof(int)},
         {c->part_imps, PT.imp_start.data(), PT.imp_start.size() * sizeof(int)},
-        {c->part_nb, PT.pnb.data(), PT.pnb.size() * sizeof(unsigned)}};
+        {c->part_nb, PT.pnb.data(), PT.pnb.size() * sizeof(unsigned)},
+        {c->part_gnb, PT.gnb.data(), PT.gnb.size() * sizeof(unsigned)}};
     for (auto &e : cp) {
         int rc = hipcheck(hipMemcpyAsync(e.dst, e.src, e.bytes, hipMemcpyHostToDevice, c->stream), "hipMemcpyAsync(part tables)");
         if (rc) return rc;
@@ -210,15 +210,17 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
     c->ssor_lds = (long)(c->lds_bytes + c->lds_extra) <= (long)max_lds;
     c->staged_bytes = c->lds_bytes + c->lds_extra + (size_t)T.Vb * 60 * elem_bytes(prm->prec_inner);
     c->ssor_staged = (long)c->staged_bytes <= (long)max_lds && c->ssor_threads <= 512 && !getenv("SAPQ_NO_STAGING");
-    // Two lanes per site with the block split in two workgroups along t, for blocks whose
-    // iterate does not fit LDS.  SAPQ_PARTS=0 keeps the four-lane kernels, =1 / =2 ask for
-    // one / two parts wherever they fit.
+    // Phase kernel: two lanes per site with the block's iterate in LDS, in one workgroup per
+    // block when it fits, else split along t into two workgroups; the four-lane kernels
+    // remain for blocks neither fits.  SAPQ_PARTS=0 keeps the four-lane kernels, =1 / =2
+    // ask for one / two workgroups per block wherever they fit.
     int mode = -1;
     if (const char *e = getenv("SAPQ_PARTS")) mode = atoi(e);
     c->use_parts = false;
     c->sap_np = 1;
-    const int np = mode == 1 ? 1 : mode == 2 ? 2 : (mode < 0 && !c->ssor_lds) ? 2 : 0;
-    if (np && build_parts(geom, T, np, PT)) {
+    for (int np = 1; np <= 2 && !c->use_parts; ++np) {
+        if (mode == 0 || (mode > 0 && mode != np)) continue;
+        if (!build_parts(geom, T, np, PT)) continue;
         const size_t lds = 6 * sizeof(float4) * (size_t)(PT.Vp + PT.Hp + 1);
         if ((long)lds <= (long)max_lds && 2 * PT.max_plane <= 512) {
             c->use_parts = true;
@@ -354,7 +356,6 @@ int sapq_load_gauge(sapq_ctx *h, const double *U, double *max_dev) {
     Ctx *c = &h->c;
     double dev = 0;
     if (launch_pack_links(c, U, &dev)) return hipcheck(hipGetLastError(), "load_gauge");
-    launch_pack_links_dag(c, U);
     int rc = hipcheck(hipGetLastError(), "k_pack_links");
     if (rc) return rc;
     if (max_dev) *max_dev = dev;

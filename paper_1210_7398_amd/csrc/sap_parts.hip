@@ -7,10 +7,11 @@
 //   x_c = n_ssor forward + backward sweeps from 0,  y_c += x_c,  r_c = v_c - D_cc x_c.
 //
 // Lanes.  Lane d = 0 of a pair takes the four forward hops of its site, lane d = 1 the
-// four backward hops; with the backward links stored daggered at the site itself
-// (Ud_mu(n) = U_mu(n - mu)^+), both lanes run the same instructions with the projection
-// sign s = +1 / -1.  After a pair butterfly each lane owns one chiral half (spins 2d and
-// 2d + 1), applies its 6x6 block of F and updates those six components.
+// four backward hops.  Both run the same instructions: the projection sign is s = +1 / -1,
+// and lane 1 reads U_mu at its backward neighbour and turns it into U^+ with selects (a
+// daggered copy of the links at the site would cost a quarter more bytes per sweep).  After
+// a pair butterfly each lane owns one chiral half (spins 2d and 2d + 1), applies its 6x6
+// block of F and updates those six components.
 //
 // Parts.  The sub-block layers along t are split in halves.  Only hops in t cross between
 // the halves, and they connect the last t-layer of a sub-block to the first one of the
@@ -33,6 +34,7 @@ struct PartArgs {
     int NP, Vp, Hp;
     const int *gslot;         // [NP][Vp] block slot of each part-local site
     const uint2 *pnb;         // [NP][Vp][2] LDS slots of the 4 neighbours of lane d (16 bits each)
+    const uint2 *gnb;         // [NP][Vp] block slots of the 4 backward neighbours (16 bits each)
     const int *pstart;        // [MAX_PLANES + 1] part-local hyperplane starts
     const int *exp_idx;       // [NP][Vp] index in the part's boundary layer, or -1
     const int *imp;           // [NP][Hp] halo slots, ordered by the hyperplane that reads them
@@ -72,7 +74,7 @@ __device__ __forceinline__ float xch_wait(unsigned long long w, unsigned long lo
     return __uint_as_float((unsigned)w);
 }
 
-// barrier for LDS traffic only: global loads (prefetches, halo words) and stores stay in flight
+// barrier for LDS traffic only: global loads (halo words) and stores stay in flight
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // (1 - s gamma_mu) M psi accumulated into acc, M a full SU(3) matrix; the projection and
@@ -102,24 +104,45 @@ __device__ __forceinline__ void hop_lane(cx<float> acc[12], const cx<float> psi[
 }
 
 // rows 0, 1 of a stored link and row 2 = conj(row0 x row1)
-template <typename S2>
-__device__ __forceinline__ void link_rows(cx<float> u[9], const S2 *p, int Vb) {
-#pragma unroll
-    for (int e = 0; e < 6; ++e) u[e] = ld(p + (size_t)e * Vb);
+__device__ __forceinline__ void link_rebuild(cx<float> u[9]) {
     u[6] = conjx(cmul(u[1], u[5]) - cmul(u[2], u[4]));
     u[7] = conjx(cmul(u[2], u[3]) - cmul(u[0], u[5]));
     u[8] = conjx(cmul(u[0], u[4]) - cmul(u[1], u[3]));
 }
-
-// out = F_k in for one hermitian chiral block [[A, B], [B^+, C]] (18 slots, see k_pack_clover)
 template <typename S2>
-__device__ __forceinline__ void clover_block(cx<float> out[6], const cx<float> in[6], const S2 *p, int Vb) {
-    const cx<float> d01 = ld(p), d23 = ld(p + Vb), d45 = ld(p + 2 * (size_t)Vb);
-    const cx<float> a10 = ld(p + 3 * (size_t)Vb), a20 = ld(p + 4 * (size_t)Vb), a21 = ld(p + 5 * (size_t)Vb);
-    const cx<float> c10 = ld(p + 6 * (size_t)Vb), c20 = ld(p + 7 * (size_t)Vb), c21 = ld(p + 8 * (size_t)Vb);
-    cx<float> B[9];
+__device__ __forceinline__ void link_rows(cx<float> u[9], const S2 *p, int Vb) {
 #pragma unroll
-    for (int e = 0; e < 9; ++e) B[e] = ld(p + (size_t)(9 + e) * Vb);
+    for (int e = 0; e < 6; ++e) u[e] = ld(p + (size_t)e * Vb);
+    link_rebuild(u);
+}
+
+// u <- u^+ on the lanes with dag set, u unchanged on the others (same instructions on both)
+__device__ __forceinline__ void dagger_if(cx<float> u[9], bool dag) {
+    cx<float> t[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) t[3 * a + b] = sel(dag, u[3 * b + a], u[3 * a + b]);
+    const float sg = dag ? -1.f : 1.f;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = {t[e].r, sg * t[e].i};
+}
+
+// one hermitian chiral block [[A, B], [B^+, C]] of F (18 slots, see k_pack_clover)
+struct Clov { cx<float> f[18]; };
+
+template <typename S2>
+__device__ __forceinline__ void load_clov(Clov &F, const S2 *p, int Vb) {
+#pragma unroll
+    for (int e = 0; e < 18; ++e) F.f[e] = ld(p + (size_t)e * Vb);
+}
+
+// out = F_k in:  slots 0-2 the six real diagonal entries pairwise, 3-5 / 6-8 the strict
+// lower triangles of A / C, 9-17 B row by row
+__device__ __forceinline__ void clover_apply(cx<float> out[6], const cx<float> in[6], const Clov &F) {
+    const cx<float> d01 = F.f[0], d23 = F.f[1], d45 = F.f[2];
+    const cx<float> a10 = F.f[3], a20 = F.f[4], a21 = F.f[5], c10 = F.f[6], c20 = F.f[7], c21 = F.f[8];
+    const cx<float> *B = F.f + 9;
     const cx<float> u0 = in[0], u1 = in[1], u2 = in[2], l0 = in[3], l1 = in[4], l2 = in[5];
     out[0] = d01.r * u0 + cmulc(a10, u1) + cmulc(a20, u2) + cmul(B[0], l0) + cmul(B[1], l1) + cmul(B[2], l2);
     out[1] = cmul(a10, u0) + d01.i * u1 + cmulc(a21, u2) + cmul(B[3], l0) + cmul(B[4], l1) + cmul(B[5], l2);
@@ -127,6 +150,13 @@ __device__ __forceinline__ void clover_block(cx<float> out[6], const cx<float> i
     out[3] = cmulc(B[0], u0) + cmulc(B[3], u1) + cmulc(B[6], u2) + d23.i * l0 + cmulc(c10, l1) + cmulc(c20, l2);
     out[4] = cmulc(B[1], u0) + cmulc(B[4], u1) + cmulc(B[7], u2) + cmul(c10, l0) + d45.r * l1 + cmulc(c21, l2);
     out[5] = cmulc(B[2], u0) + cmulc(B[5], u1) + cmulc(B[8], u2) + cmul(c20, l0) + cmul(c21, l1) + d45.i * l2;
+}
+
+template <typename S2>
+__device__ __forceinline__ void clover_block(cx<float> out[6], const cx<float> in[6], const S2 *p, int Vb) {
+    Clov F;
+    load_clov(F, p, Vb);
+    clover_apply(out, in, F);
 }
 
 __device__ __forceinline__ void pair_reduce(cx<float> acc[12]) {
@@ -161,27 +191,32 @@ __device__ __forceinline__ void lds_spinor(cx<float> psi[12], const float4 *xs, 
     }
 }
 
+// One in-block hop of the lane: the neighbour spinor from LDS slot `slot`, the link U_mu
+// at block slot sl (the site for lane 0, the backward neighbour for lane 1, daggered there).
 template <int MU, typename S2>
-__device__ __forceinline__ void lds_hop(cx<float> acc[12], const float4 *xs, int NS, unsigned slot, const S2 *Lk,
-                                        int ib, int s, int Vb, float sg) {
+__device__ __forceinline__ void lds_hop(cx<float> acc[12], const float4 *xs, int NS, unsigned slot, const S2 *U,
+                                        int ib, int sl, int Vb, float sg) {
     cx<float> psi[12], u[9];
     lds_spinor(psi, xs, NS, (int)slot);
-    link_rows(u, Lk + ((size_t)ib * 4 + MU) * 6 * Vb + s, Vb);
+    link_rows(u, U + ((size_t)ib * 4 + MU) * 6 * Vb + sl, Vb);
+    dagger_if(u, sg < 0.f);
     hop_lane<MU>(acc, psi, u, sg);
 }
 
 // sum over the lane's in-block hops of site (ib, s), reduced over the pair, and F of the
 // lane's chiral half:  out = (F sum_{m in block} H_nm x_m) restricted to spins 2d, 2d + 1
+// gl: block slots of the backward neighbours, where lane 1 finds its links
 template <typename S2>
-__device__ __forceinline__ void block_hop_clover(cx<float> out[6], const float4 *xs, int NS, uint2 nb, const S2 *Lk,
-                                                 const S2 *Fk, int ib, int s, int d, int Vb, float sg) {
+__device__ __forceinline__ void block_hop_clover(cx<float> out[6], const float4 *xs, int NS, uint2 nb, uint2 gl,
+                                                 const S2 *U, const S2 *Fk, int ib, int s, int d, int Vb, float sg) {
     cx<float> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
-    lds_hop<0>(acc, xs, NS, nb.x & 0xffffu, Lk, ib, s, Vb, sg);
-    lds_hop<1>(acc, xs, NS, nb.x >> 16, Lk, ib, s, Vb, sg);
-    lds_hop<2>(acc, xs, NS, nb.y & 0xffffu, Lk, ib, s, Vb, sg);
-    lds_hop<3>(acc, xs, NS, nb.y >> 16, Lk, ib, s, Vb, sg);
+    const bool at_site = d == 0;
+    lds_hop<0>(acc, xs, NS, nb.x & 0xffffu, U, ib, at_site ? s : (int)(gl.x & 0xffffu), Vb, sg);
+    lds_hop<1>(acc, xs, NS, nb.x >> 16, U, ib, at_site ? s : (int)(gl.x >> 16), Vb, sg);
+    lds_hop<2>(acc, xs, NS, nb.y & 0xffffu, U, ib, at_site ? s : (int)(gl.y & 0xffffu), Vb, sg);
+    lds_hop<3>(acc, xs, NS, nb.y >> 16, U, ib, at_site ? s : (int)(gl.y >> 16), Vb, sg);
     pair_reduce(acc);
     cx<float> own[6];
 #pragma unroll
@@ -191,18 +226,20 @@ __device__ __forceinline__ void block_hop_clover(cx<float> out[6], const float4 
 
 // one hop leaving the block (neighbour in another block, from the global iterate x)
 template <int MU, typename S2>
-__device__ __forceinline__ void gather_hop(cx<float> acc[12], const GeomDev &g, const S2 *x, const S2 *Lk, int ib,
+__device__ __forceinline__ void gather_hop(cx<float> acc[12], const GeomDev &g, const S2 *x, const S2 *U, int ib,
                                            int s, int d, int bl, float sg) {
     const unsigned w = g.nbr16[MU * g.Vb + s];
     const unsigned hw = d ? (w >> 16) : (w & 0xffffu);
     if (hw & 0x8000u) return;  // inside the block: not part of the gather
-    const int sn = (int)(hw & 0x7fffu);
+    const int sn = (int)(hw & 0x7fffu), ibn = bl & BLK_MASK;
     const float ph = (bl & WRAP_BIT) ? g.bc[MU] : 1.f;
     cx<float> psi[12], u[9];
-    load_spinor(psi, x, g, bl & BLK_MASK, sn);
+    load_spinor(psi, x, g, ibn, sn);
 #pragma unroll
     for (int c = 0; c < 12; ++c) psi[c] = ph * psi[c];
-    link_rows(u, Lk + ((size_t)ib * 4 + MU) * 6 * g.Vb + s, g.Vb);
+    const bool at_site = d == 0;
+    link_rows(u, U + ((size_t)(at_site ? ib : ibn) * 4 + MU) * 6 * g.Vb + (at_site ? s : sn), g.Vb);
+    dagger_if(u, d != 0);
     hop_lane<MU>(acc, psi, u, sg);
 }
 
@@ -211,7 +248,6 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                                                          typename Prec<P>::S2 *r, typename Prec<P>::S2 *x,
                                                          typename Prec<P>::S2 *y,
                                                          const typename Prec<P>::S2 *__restrict__ U,
-                                                         const typename Prec<P>::S2 *__restrict__ Ud,
                                                          const typename Prec<P>::S2 *__restrict__ F) {
     using S2 = typename Prec<P>::S2;
     extern __shared__ float4 xs[];
@@ -244,7 +280,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
     const size_t xstride = (size_t)3 * 24 * Hp;
     unsigned long long *xo = a.xch + ((size_t)blk * a.NP + part) * xstride;
     unsigned long long *xi = a.xch + ((size_t)blk * a.NP + (part ^ 1)) * xstride;
-    const S2 *Lk = d ? Ud : U;
+    const uint2 *gnb = a.gnb + (size_t)part * Vp;
     const S2 *Fk = F + ((size_t)ib * 2 + d) * 18 * Vb;
     const S2 *vb = a.ssor_only ? rsrc : r;
     float *xsf = reinterpret_cast<float *>(xs);
@@ -264,10 +300,10 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     cx<float> acc[12];
 #pragma unroll
                     for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
-                    gather_hop<0>(acc, g, x, Lk, ib, s, d, bl[0], sg);
-                    gather_hop<1>(acc, g, x, Lk, ib, s, d, bl[1], sg);
-                    gather_hop<2>(acc, g, x, Lk, ib, s, d, bl[2], sg);
-                    gather_hop<3>(acc, g, x, Lk, ib, s, d, bl[3], sg);
+                    gather_hop<0>(acc, g, x, U, ib, s, d, bl[0], sg);
+                    gather_hop<1>(acc, g, x, U, ib, s, d, bl[1], sg);
+                    gather_hop<2>(acc, g, x, U, ib, s, d, bl[2], sg);
+                    gather_hop<3>(acc, g, x, U, ib, s, d, bl[3], sg);
                     pair_reduce(acc);
                     cx<float> own[6], out[6];
 #pragma unroll
@@ -286,15 +322,24 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
     }
     __syncthreads();
 
-    // 2. sweeps: x_n <- (1 - omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m)
+    // 2. sweeps: x_n <- (1 - omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m).
+    // A hyperplane has at most blockDim.x / 2 sites of the part, so a lane pair updates at
+    // most one site per step.
     const int H = g.nplanes, nsw = 2 * a.n_ssor;
+    const int *pst = a.pstart;
     for (int w = 0; w < nsw; ++w) {
         const bool fwd = (w & 1) == 0;
         for (int pi = 0; pi < H; ++pi) {
             const int h = fwd ? pi : H - 1 - pi;
-            // halo words for the next step, loaded now and stored to LDS after this step's
-            // updates.  At the turn of a sweep the plane repeats and its halo slots already
-            // hold the right sweep (or the plane reads none), so nothing is fetched.
+            const int i = pst[h] + q0;
+            const bool ok = i < pst[h + 1];
+            // block slot of the site: each part owns one contiguous slot range of every
+            // hyperplane, part 0 first
+            const int s = a.NP == 2 ? i + pst[h] + part * (pst[h + 1] - pst[h]) : i;
+            const int kx = (ok && a.NP == 2) ? expi[i] : -1;
+            // (1) halo words for the next step, stored to LDS after this step's updates.  At
+            // the turn of a sweep the plane repeats and its halo slots already hold the right
+            // sweep (or the plane reads none), so nothing is fetched.
             int nw = 0, ne = 0, e0 = 0;
             unsigned tag = 0;
             unsigned long long *src = nullptr;
@@ -320,11 +365,10 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     }
                 }
             }
-            const int i1 = a.pstart[h + 1];
-            for (int i = a.pstart[h] + q0; i < i1; i += nq) {
-                const int s = gslot[i];
+            // (2) the update
+            if (ok) {
                 cx<float> out[6], v[6];
-                block_hop_clover(out, xs, NS, pnb[2 * i + d], Lk, Fk, ib, s, d, Vb, sg);
+                block_hop_clover(out, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
                 load6(v, vb, ib, s, d, Vb);
                 cx<float> xn[6];
 #pragma unroll
@@ -336,19 +380,17 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     xn[2 * q + 1] = {(1.f - omega) * ov.z + omega * n1.r, (1.f - omega) * ov.w + omega * n1.i};
                     *o = make_float4(xn[2 * q].r, xn[2 * q].i, xn[2 * q + 1].r, xn[2 * q + 1].i);
                 }
-                if (a.NP == 2) {
-                    const int k = expi[i];
-                    if (k >= 0) {
-                        const unsigned wt = xch_tag(epoch, w);
-                        unsigned long long *dst = xo + (size_t)(w % 3) * 24 * Hp + k;
+                if (kx >= 0) {
+                    const unsigned wt = xch_tag(epoch, w);
+                    unsigned long long *dst = xo + (size_t)(w % 3) * 24 * Hp + kx;
 #pragma unroll
-                        for (int e = 0; e < 6; ++e) {
-                            xch_put(dst + (size_t)(12 * d + 2 * e) * Hp, xn[e].r, wt);
-                            xch_put(dst + (size_t)(12 * d + 2 * e + 1) * Hp, xn[e].i, wt);
-                        }
+                    for (int e = 0; e < 6; ++e) {
+                        xch_put(dst + (size_t)(12 * d + 2 * e) * Hp, xn[e].r, wt);
+                        xch_put(dst + (size_t)(12 * d + 2 * e + 1) * Hp, xn[e].i, wt);
                     }
                 }
             }
+            // (3) the halo words into LDS
             if (nw) {
 #pragma unroll
                 for (int u = 0; u < IMP_REGS; ++u) {
@@ -402,7 +444,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
         }
         store6(y, ib, s, d, Vb, yv);
         cx<float> out[6], v[6];
-        block_hop_clover(out, xs, NS, pnb[2 * i + d], Lk, Fk, ib, s, d, Vb, sg);
+        block_hop_clover(out, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
         load6(v, r, ib, s, d, Vb);
 #pragma unroll
         for (int e = 0; e < 6; ++e) v[e] = v[e] - xv[e] + kappa * out[e];
@@ -423,45 +465,6 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
     }
 }
 
-// Ud_mu(n): rows 0 and 1 of U_mu(n - mu)^+, from the full FP64 input links [site][mu][3][3]
-template <int P>
-__global__ void k_pack_links_dag(GeomDev g, const double2 *src, typename Prec<P>::S2 *Ud) {
-    using C = typename Prec<P>::C;
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.V) return;
-    const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
-    long n = lex_site(g, ib, s);
-    int c[4], L[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        L[m] = g.B[m] * g.nbk[m];
-        c[m] = (int)(n % L[m]);
-        n /= L[m];
-    }
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        int cc[4] = {c[0], c[1], c[2], c[3]};
-        cc[mu] = (cc[mu] + L[mu] - 1) % L[mu];
-        const long lm = cc[0] + (long)L[0] * (cc[1] + (long)L[1] * (cc[2] + (long)L[2] * cc[3]));
-        const double2 *p = src + lm * 36 + 9 * mu;
-        const size_t base = ((size_t)ib * 4 + mu) * 6 * g.Vb + s;
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const double2 e = p[3 * b + a];  // (U^+)_{ab} = conj(U_{ba})
-                st(Ud + base + (size_t)(3 * a + b) * g.Vb, cx<C>{C(e.x), C(-e.y)});
-            }
-    }
-}
-
-void launch_pack_links_dag(Ctx *c, const double *U) {
-    if (!c->Ud) return;
-    const unsigned nb = (unsigned)((c->V + 255) / 256);
-    INNER_SWITCH(c->prm.prec_inner, (k_pack_links_dag<P_><<<nb, 256, 0, c->stream>>>(
-                                         c->g, (const double2 *)U, (typename Prec<P_>::S2 *)c->Ud)));
-}
-
 void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_only, const void *rsrc, void *r,
                             void *x, void *y) {
     PartArgs a;
@@ -477,6 +480,7 @@ void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_
     a.Hp = c->part_Hp;
     a.gslot = c->part_gslot;
     a.pnb = c->part_nb;
+    a.gnb = c->part_gnb;
     a.pstart = c->part_pstart;
     a.exp_idx = c->part_exp;
     a.imp = c->part_imp;
@@ -487,19 +491,15 @@ void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_
     INNER_SWITCH(c->prm.prec_inner, ({
                      using S2 = typename Prec<P_>::S2;
                      k_sap_phase_parts<P_><<<grid, block, c->parts_lds, c->stream>>>(
-                         c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Ud,
-                         (const S2 *)c->Fin);
+                         c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin);
                  }));
 }
 
 int set_parts_lds_limit(Ctx *c) {
     if (!c->use_parts || c->parts_lds <= 65536) return 0;
     const int bytes = (int)c->parts_lds;
-    switch (c->prm.prec_inner) {
-    case SAPQ_FP32: (void)hipFuncSetAttribute((const void *)k_sap_phase_parts<SAPQ_FP32>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes); break;
-    case SAPQ_FP16: (void)hipFuncSetAttribute((const void *)k_sap_phase_parts<SAPQ_FP16>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes); break;
-    case SAPQ_BF16: (void)hipFuncSetAttribute((const void *)k_sap_phase_parts<SAPQ_BF16>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes); break;
-    }
+    INNER_SWITCH(c->prm.prec_inner, (void)hipFuncSetAttribute((const void *)k_sap_phase_parts<P_>,
+                                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

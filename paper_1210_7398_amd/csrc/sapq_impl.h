@@ -157,7 +157,6 @@ void launch_pack_clover(Ctx *c, const double *F);
 void launch_dslash(Ctx *c, int prec, void *out, const void *in);
 void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y);
 void launch_sap_face(Ctx *c, int colour, void *r, const void *x);
-void launch_pack_links_dag(Ctx *c, const double *U);
 void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_only, const void *rsrc, void *r,
                             void *x, void *y);
 int set_parts_lds_limit(Ctx *c);
@@ -203,10 +202,9 @@ struct Ctx {
     int sap_np = 1, part_Vp = 0, part_Hp = 0, part_threads = 512;
     size_t parts_lds = 0;
     int *part_gslot, *part_pstart, *part_exp, *part_imp, *part_imps;
-    uint2 *part_nb;
+    uint2 *part_nb, *part_gnb;
     unsigned long long *xch;  // tagged halo words exchanged between the two workgroups of a block
     unsigned *xsync;          // ticket, done, epoch, error
-    void *Ud;                 // rows 0 and 1 of U_mu(n - mu)^+, inner storage
     long V;
     size_t nvec;  // 12 V complex entries
     // fields

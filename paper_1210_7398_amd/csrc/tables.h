@@ -24,14 +24,17 @@ struct HostTables {
     std::vector<int> nbr16;  // packed forward/backward slots per direction (stored as unsigned)
 };
 
-// Slots sorted by hyperplane h = sum_mu (x_mu mod S_mu); inside a plane by the ll key.
+// Slots sorted by hyperplane h = sum_mu (x_mu mod S_mu); inside a plane first by the half
+// of the block in t that the site lies in (when the sub-block layers in t split evenly),
+// then by the ll key.  The order inside a hyperplane is free (its sites are independent);
+// this one gives each half of the block one contiguous slot range per hyperplane.
 inline void build_tables(const sapq_geom *G, HostTables &T) {
     const int *B = G->block, *S = G->subblock;
     int Vb = B[0] * B[1] * B[2] * B[3];
     int ns[4];
     for (int m = 0; m < 4; ++m) { ns[m] = B[m] / S[m]; T.nbk[m] = G->L[m] / B[m]; }
     int Nsub = ns[0] * ns[1] * ns[2] * ns[3];
-    struct Key { int h; long ll; int lex; };
+    struct Key { int h, half; long ll; int lex; };
     std::vector<Key> keys(Vb);
     for (int l = 0; l < Vb; ++l) {
         int c[4], r = l;
@@ -42,9 +45,12 @@ inline void build_tables(const sapq_geom *G, HostTables &T) {
             pos += (c[m] % S[m]) * pm; pm *= S[m];
             sub += (c[m] / S[m]) * sm; sm *= ns[m];
         }
-        keys[l] = {h, pos * Nsub + sub, l};
+        const int half = ns[3] % 2 == 0 ? (c[3] / S[3]) * 2 / ns[3] : 0;
+        keys[l] = {h, half, pos * Nsub + sub, l};
     }
-    std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) { return a.h != b.h ? a.h < b.h : a.ll < b.ll; });
+    std::sort(keys.begin(), keys.end(), [](const Key &a, const Key &b) {
+        return a.h != b.h ? a.h < b.h : a.half != b.half ? a.half < b.half : a.ll < b.ll;
+    });
     T.Vb = Vb;
     T.slot_lex.resize(Vb);
     std::vector<int> slot_of(Vb);
@@ -115,6 +121,7 @@ struct PartTables {
     int NP = 1, Vp = 0, Hp = 0, max_plane = 0;
     std::vector<int> gslot, pstart, exp_idx, imp, imp_start;
     std::vector<unsigned> pnb;  // [NP][Vp][2 lanes][2 words]
+    std::vector<unsigned> gnb;  // [NP][Vp][2 words]: block slots of the backward neighbours
 };
 
 inline bool build_parts(const sapq_geom *G, const HostTables &T, int NP, PartTables &P) {
@@ -143,10 +150,14 @@ inline bool build_parts(const sapq_geom *G, const HostTables &T, int NP, PartTab
         P.pstart[h] = T.plane_start[h] / NP;
     }
     for (int h = 0; h < H; ++h) P.max_plane = std::max(P.max_plane, P.pstart[h + 1] - P.pstart[h]);
+    // the kernel computes the block slot of part-local site i in hyperplane h as
+    // i + pstart[h] + p (pstart[h + 1] - pstart[h]) for NP = 2, and i for NP = 1
     for (int p = 0; p < NP; ++p)
         for (int i = 0; i < Vp; ++i) {
-            const int h = plane_of[P.gslot[(size_t)p * Vp + i]];
+            const int s = P.gslot[(size_t)p * Vp + i], h = plane_of[s];
             if (i < P.pstart[h] || i >= P.pstart[h + 1]) return false;
+            const int want = NP == 2 ? i + P.pstart[h] + p * (P.pstart[h + 1] - P.pstart[h]) : i;
+            if (s != want) return false;
         }
     // boundary layer of each part: its sites with a neighbour in the other part
     P.exp_idx.assign((size_t)NP * Vp, -1);
@@ -167,6 +178,8 @@ inline bool build_parts(const sapq_geom *G, const HostTables &T, int NP, PartTab
     // the halo slots each hyperplane reads, in the order of the hyperplanes
     const unsigned zero = (unsigned)(Vp + P.Hp);
     P.pnb.assign((size_t)NP * Vp * 4, 0);
+    P.gnb.assign((size_t)NP * Vp * 2, 0);
+    if (Vb > 65535) return false;
     P.imp.assign((size_t)NP * std::max(P.Hp, 1), 0);
     P.imp_start.assign((size_t)NP * (MAX_PLANES + 1), 0);
     for (int p = 0; p < NP; ++p) {
@@ -194,6 +207,17 @@ inline bool build_parts(const sapq_geom *G, const HostTables &T, int NP, PartTab
                 const size_t o = (((size_t)p * Vp + i) * 2 + d) * 2;
                 P.pnb[o] = sl[0] | (sl[1] << 16);
                 P.pnb[o + 1] = sl[2] | (sl[3] << 16);
+                if (d == 1) {
+                    // the link of a backward hop sits at the neighbour (the site itself when
+                    // the neighbour is outside the block: that hop is masked)
+                    unsigned gs[4];
+                    for (int mu = 0; mu < 4; ++mu) {
+                        const int t = T.loc_nbr[(size_t)(2 * mu + 1) * Vb + s];
+                        gs[mu] = (unsigned)(t >= 0 ? t : s);
+                    }
+                    P.gnb[((size_t)p * Vp + i) * 2] = gs[0] | (gs[1] << 16);
+                    P.gnb[((size_t)p * Vp + i) * 2 + 1] = gs[2] | (gs[3] << 16);
+                }
             }
         }
         if ((int)li.size() != P.Hp) return false;  // every halo slot is read by exactly one site

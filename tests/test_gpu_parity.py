@@ -174,11 +174,15 @@ KERNELS = {"four-lane": "0", "two-lane": "1", "two-lane split": "2"}
 def _variant_applies(name, kernel):
     L, B, S, kappa, eps, bc = GEOMS[name]
     Vb = int(np.prod(B))
-    if kernel == "two-lane":  # the whole iterate and a zero slot in LDS
-        return 96 * (Vb + 1) <= 160 * 1024
-    if kernel == "two-lane split":
+    if kernel.startswith("two-lane split"):
         return (B[3] // S[3]) % 2 == 0 and 96 * (Vb // 2 + Vb // B[3] + 1) <= 160 * 1024
+    if kernel.startswith("two-lane"):  # the whole iterate and a zero slot in LDS
+        return 96 * (Vb + 1) <= 160 * 1024
     return True
+
+
+def _set_kernel(monkeypatch, kernel):
+    monkeypatch.setenv("SAPQ_PARTS", KERNELS[kernel])
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
@@ -186,7 +190,7 @@ def _variant_applies(name, kernel):
 def test_phase_kernel_variants(torch_cuda, orc, name, kernel, monkeypatch):
     if not _variant_applies(name, kernel):
         pytest.skip("variant does not fit this block in LDS")
-    monkeypatch.setenv("SAPQ_PARTS", KERNELS[kernel])
+    _set_kernel(monkeypatch, kernel)
     L, B, S, kappa, eps, bc = GEOMS[name]
     U, F = fields(name)
     s = make_solver(name, n_sap=2)
@@ -207,7 +211,7 @@ def test_phase_kernel_variants(torch_cuda, orc, name, kernel, monkeypatch):
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
 def test_phase_kernel_variants_low_precision(torch_cuda, orc, kernel, prec, monkeypatch):
     name = "12^4/6^4/3^4"
-    monkeypatch.setenv("SAPQ_PARTS", KERNELS[kernel])
+    _set_kernel(monkeypatch, kernel)
     L, B, S, kappa, eps, bc = GEOMS[name]
     U, F = fields(name)
     s = make_solver(name, prec=prec)
