@@ -302,21 +302,40 @@ def phase_model(B, n_ssor, prec_bytes):
     return bytes_, gather + ssor + final
 
 
+def phase_stream_model(B, n_ssor, prec_bytes):
+    """Bytes per site of one phase launch when the block's links, clover field and v cannot stay
+    on chip between sweeps (6^3x12 blocks: one colour's fields exceed the chip's LDS and
+    registers): the operands-once bytes plus one re-read of U (4 x 12 reals), F (72 reals) and
+    v (24 reals) per sweep, 2 n_ssor sweeps."""
+    once, _ = phase_model(B, n_ssor, prec_bytes)
+    return once + 2 * n_ssor * prec_bytes * (48 + 72 + 24)
+
+
 def dslash_model(prec_bytes):
     S = prec_bytes
     return S * (24 + 48 + 72 + 24), 8 * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS
 
 
-def traffic_from_profiles(kernel_name):
+def csrc_sha256():
+    """Hash of every kernel and host source of the library (sorted by name)."""
+    d = os.path.join(ROOT, "paper_1210_7398_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_from_profiles(kernel_name, workload):
     """HBM bytes per launch measured by rocprofv3 counters, if they were taken on the current
-    kernel source (profiles/counters.json records the source hash)."""
+    sources and this workload (profiles/counters.json records both)."""
     path = os.path.join(ROOT, "profiles", "counters.json")
     if not os.path.exists(path):
         return None
     try:
         data = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_1210_7398_amd", "csrc", "kernels.hip"), "rb").read()
-        if data.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+        if data.get("csrc_sha256") != csrc_sha256() or data.get("workload") != workload:
             return None
         k = data["kernels"].get(kernel_name)
         return None if k is None else k.get("bytes_per_launch")
@@ -390,6 +409,9 @@ def main():
     prec_bytes = 4 if args.prec == "fp32" else 2
     sites_per_phase = V // 2
     ph_bytes, ph_flops = phase_model(B, 4, prec_bytes)
+    st_bytes = phase_stream_model(B, 4, prec_bytes) * sites_per_phase
+    phase_kernel = solver.phase_kernel
+    kname = "k_sap_phase" if phase_kernel == "four-lane" else "k_sap_phase_parts"
     k = {}
     for name in ("phase_E", "phase_O", "face", "dslash64"):
         ms = sum(s["kernels"].get(name, {}).get("ms", 0.0) for s in stats)
@@ -401,17 +423,22 @@ def main():
     alg_flops = ph_flops * sites_per_phase
     t_hbm = alg_bytes / (HBM_PEAK_GBS * 1e9)
     t_alu = alg_flops / (FP32_PEAK_TFLOPS * 1e12)
-    traffic = traffic_from_profiles("k_sap_phase")
+    traffic = traffic_from_profiles(kname, args.workload)
     if t_hbm >= t_alu:
         roof = dict(bound="hbm", achieved=alg_bytes / avg_ph_s / 1e9, peak=HBM_PEAK_GBS, unit="GB/s")
     else:
         roof = dict(bound="alu", achieved=alg_flops / avg_ph_s / 1e12, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s")
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = traffic
-    roof["kernel"] = "k_sap_phase"
+    roof["kernel"] = kname
+    roof["phase_kernel"] = phase_kernel
     roof["avg_launch_us"] = avg_ph_s * 1e6
     roof["alg_bytes_per_launch"] = alg_bytes
     roof["alg_flops_per_launch"] = alg_flops
+    # the same launch against the bytes of the implemented form when the block's operands
+    # are re-read from HBM on every sweep
+    roof["streamed"] = dict(bytes_per_launch=st_bytes, achieved=st_bytes / avg_ph_s / 1e9, unit="GB/s",
+                            frac=st_bytes / avg_ph_s / 1e9 / HBM_PEAK_GBS)
 
     d_bytes, d_flops = dslash_model(8)
     d_avg = k["dslash64"]["avg_us"] * 1e-6 if k["dslash64"]["avg_us"] else None
@@ -465,7 +492,7 @@ def main():
                          f"SSOR omega 1.0 x4, N_SAP 4, {args.prec} inner BiCGStab, fp64 flexible outer, "
                          "tol 1e-10, 1 Gaussian source"),
             "lattice": list(L), "block": list(B), "subblock": list(S), "kappa": w["kappa"],
-            "inner_precision": args.prec, "rhs": 1,
+            "inner_precision": args.prec, "rhs": 1, "phase_kernel": phase_kernel,
         },
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -255,6 +255,15 @@ int sapq_nn_backward(sapq_ctx *ctx, float *grad_w, double *grad_in, const double
 int sapq_nn_train_step(sapq_ctx *ctx, const float *e, long n_vec, const int *idx, int batch, float lr, int t,
                        double *loss);
 
+/*
+ * The SAP phase kernel a context runs, chosen at creation from the block and the device's
+ * LDS: 0 four lanes per site and one workgroup per block (the SSOR iterate in LDS, or in a
+ * global scratch when it does not fit); 1 two lanes per site (forward / backward hops), one
+ * workgroup per block, iterate in LDS; 2 two lanes per site with the block split along t into
+ * two workgroups that exchange their boundary layers.  -1 for a null context.
+ */
+int sapq_phase_kernel(const sapq_ctx *ctx);
+
 /* Release the context (host memory only; the arena stays the caller's). */
 void sapq_destroy(sapq_ctx *ctx);
 

@@ -102,6 +102,7 @@ static void carve(Ctx *c, Arena &A, const HostTables &T, const PartTables &PT) {
     c->g.plane_start = ints(MAX_PLANES + 1);  // room for any sub-block shape of this block
     c->g.slot_lex = ints(T.slot_lex.size());
     c->g.blk_lex = ints(T.blk_lex.size());
+    c->g.lex_blk = ints(T.lex_blk.size());
     c->U64 = (double2 *)A.take((size_t)V * 24 * 16);
     c->F64 = (double2 *)A.take((size_t)V * 36 * 16);
     c->Uin = A.take((size_t)V * 24 * eb);
@@ -222,12 +223,12 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
         if (mode == 0 || (mode > 0 && mode != np)) continue;
         if (!build_parts(geom, T, np, PT)) continue;
         const size_t lds = 6 * sizeof(float4) * (size_t)(PT.Vp + PT.Hp + 1);
-        if ((long)lds <= (long)max_lds && 2 * PT.max_plane <= 512) {
+        if ((long)lds <= (long)max_lds) {
             c->use_parts = true;
             c->sap_np = np;
             c->part_Vp = PT.Vp;
             c->part_Hp = PT.Hp;
-            c->part_threads = std::max(64, ((2 * PT.max_plane + 63) / 64) * 64);
+            c->part_threads = std::min(512, std::max(64, ((2 * PT.max_plane + 63) / 64) * 64));
             c->parts_lds = lds;
             c->ssor_staged = false;
         }
@@ -307,7 +308,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     if (rc) { delete h; return rc; }
     struct { const void *dst; const std::vector<int> *src; } cp[] = {
         {c->g.loc_nbr, &T.loc_nbr}, {c->g.nbr16, &T.nbr16}, {c->g.blk_nbr, &T.blk_nbr}, {c->g.plane_start, &T.plane_start},
-        {c->g.slot_lex, &T.slot_lex}, {c->g.blk_lex, &T.blk_lex}};
+        {c->g.slot_lex, &T.slot_lex}, {c->g.blk_lex, &T.blk_lex}, {c->g.lex_blk, &T.lex_blk}};
     for (auto &e : cp) {
         rc = hipcheck(hipMemcpyAsync((void *)e.dst, e.src->data(), e.src->size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
                       "hipMemcpyAsync(tables)");
@@ -341,6 +342,11 @@ int sapq_set_params(sapq_ctx *h, const sapq_params *p) {
     if (p->prec_inner != h->c.prm.prec_inner) { set_error("prec_inner is fixed at creation"); return SAPQ_EINVAL; }
     h->c.prm = *p;
     return SAPQ_OK;
+}
+
+int sapq_phase_kernel(const sapq_ctx *h) {
+    if (!h) return -1;
+    return h->c.use_parts ? h->c.sap_np : 0;
 }
 
 void sapq_destroy(sapq_ctx *h) {
@@ -818,7 +824,7 @@ static int apply_subblock(Ctx *c, const int S[4]) {
     build_tables(&G, T);
     PartTables PT;
     if (c->use_parts) {
-        if (T.nplanes > MAX_PLANES || !build_parts(&G, T, c->sap_np, PT) || PT.Hp != c->part_Hp || 2 * PT.max_plane > 512) {
+        if (T.nplanes > MAX_PLANES || !build_parts(&G, T, c->sap_np, PT) || PT.Hp != c->part_Hp) {
             set_error("sub-block shape does not fit the split of the block");
             return SAPQ_ESHAPE;
         }
@@ -841,7 +847,7 @@ static int apply_subblock(Ctx *c, const int S[4]) {
     c->g.nplanes = T.nplanes;
     c->max_plane = T.max_plane;
     c->ssor_threads = std::min(512, ((4 * T.max_plane + 63) / 64) * 64);
-    if (c->use_parts) c->part_threads = std::max(64, ((2 * PT.max_plane + 63) / 64) * 64);
+    if (c->use_parts) c->part_threads = std::min(512, std::max(64, ((2 * PT.max_plane + 63) / 64) * 64));
     return SAPQ_OK;
 }
 

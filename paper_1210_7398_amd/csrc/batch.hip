@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "sitecore.h"
+#include "twolane.h"
 
 namespace sapq {
 
@@ -35,6 +35,11 @@ struct BField {
     size_t nvec;
     void *iv[NIV];
     double2 *dv[NDV];
+    // two-lane kernel (contexts with one workgroup per block): neighbour LDS slots, block
+    // slots of the backward neighbours, hyperplane starts, threads per right-hand side
+    const uint2 *pnb, *gnb;
+    const int *pst;
+    int tpr;
 };
 
 struct BatchDev {
@@ -195,6 +200,129 @@ __global__ void __launch_bounds__(512) k_bsap_phase(const BatchDev *__restrict__
     }
 }
 
+// The multi-source phase kernel with two lanes per site, for blocks whose iterate fits LDS:
+// the workgroup is NR slices of a single-source workgroup (k_sap_phase_parts with one part),
+// slice k working on right-hand side k0 + k of its group with its own iterate in LDS.  The
+// slices read the same links and clover rows at the same time, so the group fetches them
+// from HBM once and the other slices find them in L1/L2.
+template <int P, int NR>
+__global__ void __launch_bounds__(768) k_bsap_phase_2l(const BatchDev *__restrict__ Bd, int colour, int first,
+                                                        int s_src, int s_r, int s_x, int s_y,
+                                                        const BState *__restrict__ bst) {
+    using S2 = typename Prec<P>::S2;
+    extern __shared__ float4 xb[];
+    const BatchDev &B = *Bd;
+    const int w = blockIdx.x;
+    const int fi = field_of_work(B, w);
+    const BField &F = B.f[fi];
+    const GeomDev &g = F.g;
+    const int local = w - B.work0[fi];
+    const int ib = colour * g.NBc + local / F.ngroups;
+    const int k0 = (local % F.ngroups) * NR;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < NR; ++k)
+        if (k0 + k < F.nrhs && !bst[F.rhs0 + k0 + k].done) any = true;
+    if (!any) return;  // uniform over the workgroup
+    const int tpr = F.tpr;
+    const int k = threadIdx.x / tpr, tt = threadIdx.x - k * tpr;
+    const int d = tt & 1, q0 = tt >> 1, nq = tpr >> 1;
+    const int Vb = g.Vb, NS = Vb + 1;
+    const bool live = k < NR && k0 + k < F.nrhs;
+    float4 *xs = xb + (size_t)min(k, NR - 1) * 6 * NS;
+    const size_t ko = (size_t)(k0 + min(k, NR - 1)) * F.nvec;
+    const S2 *U = (const S2 *)F.Uin;
+    const S2 *Fk = (const S2 *)F.Fin + ((size_t)ib * 2 + d) * 18 * Vb;
+    const S2 *src = (const S2 *)F.iv[s_src] + ko;
+    S2 *r = (S2 *)F.iv[s_r] + ko;
+    S2 *x = (S2 *)F.iv[s_x] + ko;
+    S2 *y = (S2 *)F.iv[s_y] + ko;
+    const float sg = d ? -1.f : 1.f, kappa = F.kappa, omega = F.omega;
+    const bool gather = colour == 1 || !first;
+
+    // 1. v_c (gathering the other colour), zero the iterate and the zero slot
+    if (live) {
+        int bl[4];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) bl[mu] = g.blk_nbr[(2 * mu + d) * g.NB + ib];
+        for (int i = q0; i < Vb; i += nq) {
+            cx<float> v[6];
+            load6(v, src, ib, i, d, Vb);
+            if (gather) {
+                cx<float> acc[12];
+#pragma unroll
+                for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
+                gather_hop<0>(acc, g, x, U, ib, i, d, bl[0], sg);
+                gather_hop<1>(acc, g, x, U, ib, i, d, bl[1], sg);
+                gather_hop<2>(acc, g, x, U, ib, i, d, bl[2], sg);
+                gather_hop<3>(acc, g, x, U, ib, i, d, bl[3], sg);
+                pair_reduce(acc);
+                cx<float> own[6], out[6];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) own[e] = sel(d != 0, acc[6 + e], acc[e]);
+                clover_block(out, own, Fk + i, Vb);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) v[e] = v[e] + kappa * out[e];
+            }
+            store6(r, ib, i, d, Vb, v);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) xs[(3 * d + q) * NS + i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        for (int t = tt; t < 6; t += tpr) xs[t * NS + Vb] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+
+    // 2. sweeps, one hyperplane per step
+    const int H = g.nplanes;
+    for (int sw = 0; sw < 2 * F.n_ssor; ++sw) {
+        for (int pi = 0; pi < H; ++pi) {
+            const int h = (sw & 1) == 0 ? pi : H - 1 - pi;
+            for (int i = F.pst[h] + q0; live && i < F.pst[h + 1]; i += nq) {
+                cx<float> out[6], v[6];
+                block_hop_clover(out, xs, NS, F.pnb[2 * i + d], F.gnb[i], U, Fk, ib, i, d, Vb, sg);
+                load6(v, r, ib, i, d, Vb);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    float4 *o = &xs[(3 * d + q) * NS + i];
+                    const float4 ov = *o;
+                    const cx<float> n0 = v[2 * q] + kappa * out[2 * q], n1 = v[2 * q + 1] + kappa * out[2 * q + 1];
+                    *o = make_float4((1.f - omega) * ov.x + omega * n0.r, (1.f - omega) * ov.y + omega * n0.i,
+                                     (1.f - omega) * ov.z + omega * n1.r, (1.f - omega) * ov.w + omega * n1.i);
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    // 3. outputs: x_c, y_c += x_c, r_c = v_c - D_cc x_c
+    if (!live) return;
+    for (int i = q0; i < Vb; i += nq) {
+        cx<float> xv[6], yv[6];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float4 f = xs[(3 * d + q) * NS + i];
+            xv[2 * q] = {f.x, f.y};
+            xv[2 * q + 1] = {f.z, f.w};
+        }
+        store6(x, ib, i, d, Vb, xv);
+        if (first) {
+#pragma unroll
+            for (int e = 0; e < 6; ++e) yv[e] = xv[e];
+        } else {
+            load6(yv, y, ib, i, d, Vb);
+#pragma unroll
+            for (int e = 0; e < 6; ++e) yv[e] = yv[e] + xv[e];
+        }
+        store6(y, ib, i, d, Vb, yv);
+        cx<float> out[6], v[6];
+        block_hop_clover(out, xs, NS, F.pnb[2 * i + d], F.gnb[i], U, Fk, ib, i, d, Vb, sg);
+        load6(v, r, ib, i, d, Vb);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v[e] = v[e] - xv[e] + kappa * out[e];
+        store6(r, ib, i, d, Vb, v);
+    }
+}
+
 // allow the batched phase kernels the dynamic LDS they are launched with
 static void batch_lds_attr(int bytes) {
     const void *fns[] = {(const void *)k_bsap_phase<SAPQ_FP32, 1>, (const void *)k_bsap_phase<SAPQ_FP32, 2>,
@@ -203,6 +331,12 @@ static void batch_lds_attr(int bytes) {
                          (const void *)k_bsap_phase<SAPQ_BF16, 1>, (const void *)k_bsap_phase<SAPQ_BF16, 2>,
                          (const void *)k_bsap_phase<SAPQ_BF16, 4>};
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    const void *fns2[] = {(const void *)k_bsap_phase_2l<SAPQ_FP32, 1>, (const void *)k_bsap_phase_2l<SAPQ_FP32, 2>,
+                          (const void *)k_bsap_phase_2l<SAPQ_FP32, 4>, (const void *)k_bsap_phase_2l<SAPQ_FP16, 1>,
+                          (const void *)k_bsap_phase_2l<SAPQ_FP16, 2>, (const void *)k_bsap_phase_2l<SAPQ_FP16, 4>,
+                          (const void *)k_bsap_phase_2l<SAPQ_BF16, 1>, (const void *)k_bsap_phase_2l<SAPQ_BF16, 2>,
+                          (const void *)k_bsap_phase_2l<SAPQ_BF16, 4>};
+    for (const void *f : fns2) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // r_c += kappa F sum_{hops leaving the block} H x for every field and right-hand side
@@ -538,6 +672,8 @@ struct Batch {
     int nf = 0, total = 0, max_rhs = 0;
     long max_V = 0;
     int prec = SAPQ_FP32, NR = 1;
+    bool two_lane = false;  // k_bsap_phase_2l (else the four-lane k_bsap_phase)
+    int threads = 0;
     size_t lds = 0;
     hipStream_t stream = nullptr;
     BatchDev host;
@@ -599,12 +735,21 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
     // right-hand sides per workgroup: as many as the LDS holds (1, 2 or 4)
     int max_lds = 65536, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    const size_t per = (size_t)c0->g.Vb * 12 * sizeof(float2);
+    // two lanes per site when every context runs the one-workgroup two-lane kernel (same
+    // block and sub-block shape, so the same decision and tables in all of them)
+    B.two_lane = true;
+    for (Ctx *c : B.ctx) B.two_lane = B.two_lane && c->use_parts && c->sap_np == 1;
+    const size_t per = B.two_lane ? (size_t)(c0->g.Vb + 1) * 6 * sizeof(float4) : (size_t)c0->g.Vb * 12 * sizeof(float2);
+    const size_t extra = B.two_lane ? 0 : c0->lds_extra;
+    const int tpr = B.two_lane ? c0->part_threads : c0->ssor_threads;
     B.NR = 0;
     for (int nr : {4, 2, 1})
-        if (B.NR == 0 && nr <= std::max(1, B.max_rhs) && per * nr + c0->lds_extra <= (size_t)max_lds) B.NR = nr;
+        if (B.NR == 0 && nr <= std::max(1, B.max_rhs) && per * nr + extra <= (size_t)max_lds &&
+            (!B.two_lane || nr * tpr <= 768))
+            B.NR = nr;
     if (B.NR == 0) { why = "the SAP block is too large for the batched kernel's LDS"; return SAPQ_ESHAPE; }
-    B.lds = per * B.NR + c0->lds_extra;
+    B.lds = per * B.NR + extra;
+    B.threads = B.two_lane ? B.NR * tpr : c0->ssor_threads;
     if (B.lds > 65536) {
         batch_lds_attr((int)B.lds);
         (void)hipGetLastError();  // clears the runtime's last-error slot
@@ -627,6 +772,10 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
         F.rhs0 = B.total;
         F.ngroups = (nrhs[f] + B.NR - 1) / B.NR;
         F.nvec = c->nvec;
+        F.pnb = c->part_nb;
+        F.gnb = c->part_gnb;
+        F.pst = c->part_pstart;
+        F.tpr = c->part_threads;
         B.host.work0[f] = work;
         work += c->g.NBc * F.ngroups;
         B.total += nrhs[f];
@@ -648,8 +797,11 @@ static dim3 vgrid(const Batch &B) { return dim3(256, (unsigned)B.nf, (unsigned)B
 
 template <int P, int NR>
 static void bphase(Batch &B, int colour, int first, int src, int r, int x, int y) {
-    k_bsap_phase<P, NR><<<(unsigned)B.host.work0[B.nf], B.ctx[0]->ssor_threads, B.lds, B.stream>>>(B.dev, colour, first, src,
-                                                                                                  r, x, y, B.st);
+    const unsigned nw = (unsigned)B.host.work0[B.nf];
+    if (B.two_lane)
+        k_bsap_phase_2l<P, NR><<<nw, B.threads, B.lds, B.stream>>>(B.dev, colour, first, src, r, x, y, B.st);
+    else
+        k_bsap_phase<P, NR><<<nw, B.threads, B.lds, B.stream>>>(B.dev, colour, first, src, r, x, y, B.st);
 }
 
 static void bmsap(Batch &B, int src, int y) {

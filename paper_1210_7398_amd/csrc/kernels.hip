@@ -114,7 +114,10 @@ __global__ void k_pack_clover(GeomDev g, const double2 *src, double2 *F64, typen
 }
 
 // ================================================================ full operator D
-// out = in - kappa F H in; four lanes per site
+// out = in - kappa F H in; four lanes per site.  Workgroups are dealt to the 8 XCDs in turn
+// (each with its own L2); the grid is a multiple of 8 and XCD x takes the x-th eighth of the
+// sites, blocks in lexicographic order, so that most neighbours a workgroup reads were
+// fetched into the same L2 by its neighbouring workgroups.
 template <int P>
 __global__ void __launch_bounds__(256) k_dslash(GeomDev g, typename Prec<P>::S2 *__restrict__ out,
                                                const typename Prec<P>::S2 *__restrict__ in,
@@ -122,11 +125,11 @@ __global__ void __launch_bounds__(256) k_dslash(GeomDev g, typename Prec<P>::S2 
                                                const typename Prec<P>::S2 *__restrict__ F, double kappa) {
     using S2 = typename Prec<P>::S2;
     using C = typename Prec<P>::C;
-    const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long i = gt >> 2;
-    const int j = (int)(gt & 3);
+    const long i = xcd_site_base(64) + (threadIdx.x >> 2);
+    const int j = (int)(threadIdx.x & 3);
     if (i >= g.V) return;
-    const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    const int bl = (int)(i / g.Vb), s = (int)(i - (long)bl * g.Vb);
+    const int ib = g.lex_blk[bl];
     const LaneNbr n = lane_nbr(g.nbr16[j * g.Vb + s], ib, g.blk_nbr[(2 * j) * g.NB + ib], g.blk_nbr[(2 * j + 1) * g.NB + ib],
                                g.bc[j]);
     cx<C> h[12], fh[3], v[3];
@@ -553,12 +556,13 @@ void launch_pack_clover(Ctx *c, const double *F) {
 }
 
 void launch_dslash(Ctx *c, int prec, void *out, const void *in) {
+    const unsigned grid = (grid_for(4 * c->V, 256) + N_XCD - 1) / N_XCD * N_XCD;
     if (prec == SAPQ_FP64) {
-        k_dslash<SAPQ_FP64><<<grid_for(4 * c->V, 256), 256, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in,
-                                                                         c->U64, c->F64, c->prm.kappa);
+        k_dslash<SAPQ_FP64><<<grid, 256, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in, c->U64, c->F64,
+                                                         c->prm.kappa);
         return;
     }
-    INNER_SWITCH(prec, (k_dslash<P_><<<grid_for(4 * c->V, 256), 256, 0, c->stream>>>(
+    INNER_SWITCH(prec, (k_dslash<P_><<<grid, 256, 0, c->stream>>>(
                            c->g, (typename Prec<P_>::S2 *)out, (const typename Prec<P_>::S2 *)in,
                            (const typename Prec<P_>::S2 *)c->Uin, (const typename Prec<P_>::S2 *)c->Fin, c->prm.kappa)));
 }
@@ -653,6 +657,10 @@ void launch_ssor_only(Ctx *c, int colour, const void *v, void *x) {
 }
 
 void launch_sap_face(Ctx *c, int colour, void *r, const void *x) {
+    if (c->use_parts) {
+        launch_sap_face_2l(c, colour, r, x);
+        return;
+    }
     long nc = (long)c->g.NBc * c->g.Vb;
     INNER_SWITCH(c->prm.prec_inner, (k_sap_face<P_><<<grid_for(4 * nc, 256), 256, 0, c->stream>>>(
                                          c->g, colour, (float)c->prm.kappa, (typename Prec<P_>::S2 *)r,

@@ -24,7 +24,7 @@
 // moved on (writing sweep w + 3 needs the reader's sweep w + 2 data).  The two parts of a
 // block take their block from a ticket counter in start order, so a part only ever waits
 // on a part that is already running; the last workgroup resets the counter.
-#include "sitecore.h"
+#include "twolane.h"
 
 namespace sapq {
 
@@ -76,172 +76,6 @@ __device__ __forceinline__ float xch_wait(unsigned long long w, unsigned long lo
 
 // barrier for LDS traffic only: global loads (halo words) and stores stay in flight
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-// (1 - s gamma_mu) M psi accumulated into acc, M a full SU(3) matrix; the projection and
-// the rebuild of the lower spins follow the chiral-basis gamma matrices (see sitecore.h)
-template <int MU>
-__device__ __forceinline__ void hop_lane(cx<float> acc[12], const cx<float> psi[12], const cx<float> u[9], float s) {
-    cx<float> h0[3], h1[3], g0[3], g1[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const cx<float> p0 = psi[a], p1 = psi[3 + a], p2 = psi[6 + a], p3 = psi[9 + a];
-        if (MU == 0) { h0[a] = p0 + s * itimes(p3); h1[a] = p1 + s * itimes(p2); }
-        if (MU == 1) { h0[a] = p0 + s * p3;         h1[a] = p1 - s * p2; }
-        if (MU == 2) { h0[a] = p0 + s * itimes(p2); h1[a] = p1 - s * itimes(p3); }
-        if (MU == 3) { h0[a] = p0 - s * p2;         h1[a] = p1 - s * p3; }
-    }
-    su3_mul(g0, u, h0, false);
-    su3_mul(g1, u, h1, false);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        acc[a] = acc[a] + g0[a];
-        acc[3 + a] = acc[3 + a] + g1[a];
-        if (MU == 0) { acc[6 + a] = acc[6 + a] - s * itimes(g1[a]); acc[9 + a] = acc[9 + a] - s * itimes(g0[a]); }
-        if (MU == 1) { acc[6 + a] = acc[6 + a] - s * g1[a];         acc[9 + a] = acc[9 + a] + s * g0[a]; }
-        if (MU == 2) { acc[6 + a] = acc[6 + a] - s * itimes(g0[a]); acc[9 + a] = acc[9 + a] + s * itimes(g1[a]); }
-        if (MU == 3) { acc[6 + a] = acc[6 + a] - s * g0[a];         acc[9 + a] = acc[9 + a] - s * g1[a]; }
-    }
-}
-
-// rows 0, 1 of a stored link and row 2 = conj(row0 x row1)
-__device__ __forceinline__ void link_rebuild(cx<float> u[9]) {
-    u[6] = conjx(cmul(u[1], u[5]) - cmul(u[2], u[4]));
-    u[7] = conjx(cmul(u[2], u[3]) - cmul(u[0], u[5]));
-    u[8] = conjx(cmul(u[0], u[4]) - cmul(u[1], u[3]));
-}
-template <typename S2>
-__device__ __forceinline__ void link_rows(cx<float> u[9], const S2 *p, int Vb) {
-#pragma unroll
-    for (int e = 0; e < 6; ++e) u[e] = ld(p + (size_t)e * Vb);
-    link_rebuild(u);
-}
-
-// u <- u^+ on the lanes with dag set, u unchanged on the others (same instructions on both)
-__device__ __forceinline__ void dagger_if(cx<float> u[9], bool dag) {
-    cx<float> t[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) t[3 * a + b] = sel(dag, u[3 * b + a], u[3 * a + b]);
-    const float sg = dag ? -1.f : 1.f;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) u[e] = {t[e].r, sg * t[e].i};
-}
-
-// one hermitian chiral block [[A, B], [B^+, C]] of F (18 slots, see k_pack_clover)
-struct Clov { cx<float> f[18]; };
-
-template <typename S2>
-__device__ __forceinline__ void load_clov(Clov &F, const S2 *p, int Vb) {
-#pragma unroll
-    for (int e = 0; e < 18; ++e) F.f[e] = ld(p + (size_t)e * Vb);
-}
-
-// out = F_k in:  slots 0-2 the six real diagonal entries pairwise, 3-5 / 6-8 the strict
-// lower triangles of A / C, 9-17 B row by row
-__device__ __forceinline__ void clover_apply(cx<float> out[6], const cx<float> in[6], const Clov &F) {
-    const cx<float> d01 = F.f[0], d23 = F.f[1], d45 = F.f[2];
-    const cx<float> a10 = F.f[3], a20 = F.f[4], a21 = F.f[5], c10 = F.f[6], c20 = F.f[7], c21 = F.f[8];
-    const cx<float> *B = F.f + 9;
-    const cx<float> u0 = in[0], u1 = in[1], u2 = in[2], l0 = in[3], l1 = in[4], l2 = in[5];
-    out[0] = d01.r * u0 + cmulc(a10, u1) + cmulc(a20, u2) + cmul(B[0], l0) + cmul(B[1], l1) + cmul(B[2], l2);
-    out[1] = cmul(a10, u0) + d01.i * u1 + cmulc(a21, u2) + cmul(B[3], l0) + cmul(B[4], l1) + cmul(B[5], l2);
-    out[2] = cmul(a20, u0) + cmul(a21, u1) + d23.r * u2 + cmul(B[6], l0) + cmul(B[7], l1) + cmul(B[8], l2);
-    out[3] = cmulc(B[0], u0) + cmulc(B[3], u1) + cmulc(B[6], u2) + d23.i * l0 + cmulc(c10, l1) + cmulc(c20, l2);
-    out[4] = cmulc(B[1], u0) + cmulc(B[4], u1) + cmulc(B[7], u2) + cmul(c10, l0) + d45.r * l1 + cmulc(c21, l2);
-    out[5] = cmulc(B[2], u0) + cmulc(B[5], u1) + cmulc(B[8], u2) + cmul(c20, l0) + cmul(c21, l1) + d45.i * l2;
-}
-
-template <typename S2>
-__device__ __forceinline__ void clover_block(cx<float> out[6], const cx<float> in[6], const S2 *p, int Vb) {
-    Clov F;
-    load_clov(F, p, Vb);
-    clover_apply(out, in, F);
-}
-
-__device__ __forceinline__ void pair_reduce(cx<float> acc[12]) {
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        acc[c].r += quad_get<QUAD_XOR1>(acc[c].r);
-        acc[c].i += quad_get<QUAD_XOR1>(acc[c].i);
-    }
-}
-
-// the six components (spins 2d, 2d + 1) of site (ib, s) owned by lane d
-template <typename S2>
-__device__ __forceinline__ void load6(cx<float> v[6], const S2 *f, int ib, int s, int d, int Vb) {
-    const S2 *p = f + ((size_t)ib * 12 + 6 * d) * Vb + s;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) v[e] = ld(p + (size_t)e * Vb);
-}
-template <typename S2>
-__device__ __forceinline__ void store6(S2 *f, int ib, int s, int d, int Vb, const cx<float> v[6]) {
-    S2 *p = f + ((size_t)ib * 12 + 6 * d) * Vb + s;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) st(p + (size_t)e * Vb, v[e]);
-}
-
-// iterate in LDS: float4 [6][NS], float4 q holding components 2q and 2q + 1
-__device__ __forceinline__ void lds_spinor(cx<float> psi[12], const float4 *xs, int NS, int slot) {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        const float4 f = xs[q * NS + slot];
-        psi[2 * q] = {f.x, f.y};
-        psi[2 * q + 1] = {f.z, f.w};
-    }
-}
-
-// One in-block hop of the lane: the neighbour spinor from LDS slot `slot`, the link U_mu
-// at block slot sl (the site for lane 0, the backward neighbour for lane 1, daggered there).
-template <int MU, typename S2>
-__device__ __forceinline__ void lds_hop(cx<float> acc[12], const float4 *xs, int NS, unsigned slot, const S2 *U,
-                                        int ib, int sl, int Vb, float sg) {
-    cx<float> psi[12], u[9];
-    lds_spinor(psi, xs, NS, (int)slot);
-    link_rows(u, U + ((size_t)ib * 4 + MU) * 6 * Vb + sl, Vb);
-    dagger_if(u, sg < 0.f);
-    hop_lane<MU>(acc, psi, u, sg);
-}
-
-// sum over the lane's in-block hops of site (ib, s), reduced over the pair, and F of the
-// lane's chiral half:  out = (F sum_{m in block} H_nm x_m) restricted to spins 2d, 2d + 1
-// gl: block slots of the backward neighbours, where lane 1 finds its links
-template <typename S2>
-__device__ __forceinline__ void block_hop_clover(cx<float> out[6], const float4 *xs, int NS, uint2 nb, uint2 gl,
-                                                 const S2 *U, const S2 *Fk, int ib, int s, int d, int Vb, float sg) {
-    cx<float> acc[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
-    const bool at_site = d == 0;
-    lds_hop<0>(acc, xs, NS, nb.x & 0xffffu, U, ib, at_site ? s : (int)(gl.x & 0xffffu), Vb, sg);
-    lds_hop<1>(acc, xs, NS, nb.x >> 16, U, ib, at_site ? s : (int)(gl.x >> 16), Vb, sg);
-    lds_hop<2>(acc, xs, NS, nb.y & 0xffffu, U, ib, at_site ? s : (int)(gl.y & 0xffffu), Vb, sg);
-    lds_hop<3>(acc, xs, NS, nb.y >> 16, U, ib, at_site ? s : (int)(gl.y >> 16), Vb, sg);
-    pair_reduce(acc);
-    cx<float> own[6];
-#pragma unroll
-    for (int e = 0; e < 6; ++e) own[e] = sel(d != 0, acc[6 + e], acc[e]);
-    clover_block(out, own, Fk + s, Vb);
-}
-
-// one hop leaving the block (neighbour in another block, from the global iterate x)
-template <int MU, typename S2>
-__device__ __forceinline__ void gather_hop(cx<float> acc[12], const GeomDev &g, const S2 *x, const S2 *U, int ib,
-                                           int s, int d, int bl, float sg) {
-    const unsigned w = g.nbr16[MU * g.Vb + s];
-    const unsigned hw = d ? (w >> 16) : (w & 0xffffu);
-    if (hw & 0x8000u) return;  // inside the block: not part of the gather
-    const int sn = (int)(hw & 0x7fffu), ibn = bl & BLK_MASK;
-    const float ph = (bl & WRAP_BIT) ? g.bc[MU] : 1.f;
-    cx<float> psi[12], u[9];
-    load_spinor(psi, x, g, ibn, sn);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) psi[c] = ph * psi[c];
-    const bool at_site = d == 0;
-    link_rows(u, U + ((size_t)(at_site ? ib : ibn) * 4 + MU) * 6 * g.Vb + (at_site ? s : sn), g.Vb);
-    dagger_if(u, d != 0);
-    hop_lane<MU>(acc, psi, u, sg);
-}
 
 template <int P>
 __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, const typename Prec<P>::S2 *rsrc,
@@ -322,21 +156,13 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
     }
     __syncthreads();
 
-    // 2. sweeps: x_n <- (1 - omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m).
-    // A hyperplane has at most blockDim.x / 2 sites of the part, so a lane pair updates at
-    // most one site per step.
+    // 2. sweeps: x_n <- (1 - omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m)
     const int H = g.nplanes, nsw = 2 * a.n_ssor;
     const int *pst = a.pstart;
     for (int w = 0; w < nsw; ++w) {
         const bool fwd = (w & 1) == 0;
         for (int pi = 0; pi < H; ++pi) {
             const int h = fwd ? pi : H - 1 - pi;
-            const int i = pst[h] + q0;
-            const bool ok = i < pst[h + 1];
-            // block slot of the site: each part owns one contiguous slot range of every
-            // hyperplane, part 0 first
-            const int s = a.NP == 2 ? i + pst[h] + part * (pst[h + 1] - pst[h]) : i;
-            const int kx = (ok && a.NP == 2) ? expi[i] : -1;
             // (1) halo words for the next step, stored to LDS after this step's updates.  At
             // the turn of a sweep the plane repeats and its halo slots already hold the right
             // sweep (or the plane reads none), so nothing is fetched.
@@ -365,8 +191,13 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     }
                 }
             }
-            // (2) the update
-            if (ok) {
+            // (2) the updates; a part-local site i of plane h sits at block slot
+            // i + pst[h] + part (pst[h + 1] - pst[h]) (each part owns one contiguous slot
+            // range of every hyperplane, part 0 first)
+            const int shift = a.NP == 2 ? pst[h] + part * (pst[h + 1] - pst[h]) : 0;
+            for (int i = pst[h] + q0; i < pst[h + 1]; i += nq) {
+                const int s = i + shift;
+                const int kx = a.NP == 2 ? expi[i] : -1;
                 cx<float> out[6], v[6];
                 block_hop_clover(out, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
                 load6(v, vb, ib, s, d, Vb);
@@ -463,6 +294,54 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
             }
         }
     }
+}
+
+// r_c += kappa F sum_{hops leaving the block} H x  (r_c -= D_{c,other} x_other, the last step
+// of M_SAP), two lanes per site; a site with no hop leaving its block is left alone.
+template <int P>
+__global__ void __launch_bounds__(256) k_sap_face_2l(GeomDev g, int colour, float kappa, typename Prec<P>::S2 *r,
+                                                     const typename Prec<P>::S2 *x,
+                                                     const typename Prec<P>::S2 *__restrict__ U,
+                                                     const typename Prec<P>::S2 *__restrict__ F) {
+    const long i = xcd_site_base(128) + (threadIdx.x >> 1);
+    const int d = threadIdx.x & 1;
+    const long nc = (long)g.NBc * g.Vb;
+    if (i >= nc) return;
+    const int ib = colour * g.NBc + (int)(i / g.Vb), s = (int)(i % g.Vb);
+    int outside = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const unsigned w = g.nbr16[mu * g.Vb + s];
+        outside |= ((d ? (w >> 16) : w) & 0x8000u) ? 0 : 1;
+    }
+    outside |= __builtin_amdgcn_update_dpp(0, outside, QUAD_XOR1, 0xF, 0xF, true);
+    if (!outside) return;  // both lanes of the pair leave together
+    const float sg = d ? -1.f : 1.f;
+    cx<float> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
+    gather_hop<0>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 0 + d) * g.NB + ib], sg);
+    gather_hop<1>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 1 + d) * g.NB + ib], sg);
+    gather_hop<2>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 2 + d) * g.NB + ib], sg);
+    gather_hop<3>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 3 + d) * g.NB + ib], sg);
+    pair_reduce(acc);
+    cx<float> own[6], out[6], v[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) own[e] = sel(d != 0, acc[6 + e], acc[e]);
+    clover_block(out, own, F + ((size_t)ib * 2 + d) * 18 * g.Vb + s, g.Vb);
+    load6(v, r, ib, s, d, g.Vb);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) v[e] = v[e] + kappa * out[e];
+    store6(r, ib, s, d, g.Vb, v);
+}
+
+void launch_sap_face_2l(Ctx *c, int colour, void *r, const void *x) {
+    const long nc = (long)c->g.NBc * c->g.Vb;
+    const unsigned grid = (unsigned)((2 * nc + 255) / 256 + N_XCD - 1) / N_XCD * N_XCD;
+    INNER_SWITCH(c->prm.prec_inner, (k_sap_face_2l<P_><<<grid, 256, 0, c->stream>>>(
+                                         c->g, colour, (float)c->prm.kappa, (typename Prec<P_>::S2 *)r,
+                                         (const typename Prec<P_>::S2 *)x, (const typename Prec<P_>::S2 *)c->Uin,
+                                         (const typename Prec<P_>::S2 *)c->Fin)));
 }
 
 void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_only, const void *rsrc, void *r,

@@ -42,6 +42,7 @@ struct GeomDev {
     const int *plane_start; // [nplanes + 1]
     const int *slot_lex;    // [Vb] block-local lexicographic index of each slot
     const int *blk_lex;     // [NB] lexicographic block index of each internal block id
+    const int *lex_blk;     // [NB] internal block id of each lexicographic block index
     int B[4];
     int nbk[4];             // blocks per direction
 };
@@ -160,6 +161,7 @@ void launch_sap_face(Ctx *c, int colour, void *r, const void *x);
 void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_only, const void *rsrc, void *r,
                             void *x, void *y);
 int set_parts_lds_limit(Ctx *c);
+void launch_sap_face_2l(Ctx *c, int colour, void *r, const void *x);
 void launch_ssor_only(Ctx *c, int colour, const void *v, void *x);
 
 // BLAS-1 on internal vectors (n = 12 V complex entries)

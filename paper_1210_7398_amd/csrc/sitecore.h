@@ -24,6 +24,18 @@ __device__ __forceinline__ long lex_site(const GeomDev &g, int ib, int s) {
 }
 
 
+// ================================================================ XCD-aware site order
+// Workgroups are dealt to the 8 XCDs in turn, each XCD with its own L2.  For a grid that is
+// a multiple of 8, XCD x gets workgroups x, x + 8, ...; mapping them to the x-th eighth of
+// the sites keeps the sites an XCD works on (and most of their neighbours) contiguous.
+constexpr int N_XCD = 8;
+
+__device__ __forceinline__ long xcd_site_base(int sites_per_wg) {
+    const unsigned per = gridDim.x / N_XCD;
+    const unsigned v = (blockIdx.x % N_XCD) * per + blockIdx.x / N_XCD;
+    return (long)v * sites_per_wg;
+}
+
 // ================================================================ four lanes per site
 // A site is handled by a group of four adjacent lanes; lane j takes direction mu = j
 // (its forward and its backward hop), the four partial hopping sums are added with a

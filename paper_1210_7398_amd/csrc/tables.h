@@ -20,7 +20,7 @@ constexpr int MAX_PLANES = 64;
 struct HostTables {
     int Vb = 0, NB = 0, nplanes = 0, max_plane = 0;
     int nbk[4];
-    std::vector<int> loc_nbr, blk_nbr, plane_start, slot_lex, blk_lex;
+    std::vector<int> loc_nbr, blk_nbr, plane_start, slot_lex, blk_lex, lex_blk;
     std::vector<int> nbr16;  // packed forward/backward slots per direction (stored as unsigned)
 };
 
@@ -98,6 +98,7 @@ inline void build_tables(const sapq_geom *G, HostTables &T) {
         }
     std::vector<int> ib_of(NB);
     for (int i = 0; i < NB; ++i) ib_of[T.blk_lex[i]] = i;
+    T.lex_blk = ib_of;
     T.blk_nbr.resize(8 * NB);
     for (int i = 0; i < NB; ++i) {
         int c[4], r = T.blk_lex[i];

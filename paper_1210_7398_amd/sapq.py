@@ -81,6 +81,7 @@ _SIGS = {
     "sapq_solve_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_P),
                                         ctypes.POINTER(_P), ctypes.c_double, _P, ctypes.c_size_t, ctypes.POINTER(Stats)]),
     "sapq_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
+    "sapq_phase_kernel": (ctypes.c_int, [_P]),
     "sapq_destroy": (None, [_P]),
     "sapq_last_error": (ctypes.c_char_p, []),
 }
@@ -211,6 +212,11 @@ class Solver:
         if check:
             _check(rc)
         return x, st.as_dict()
+
+    @property
+    def phase_kernel(self):
+        """Name of the SAP phase kernel this context runs (sapq_phase_kernel)."""
+        return {0: "four-lane", 1: "two-lane", 2: "two-lane split"}[lib().sapq_phase_kernel(self.h)]
 
     def autotune(self, cache_path=None):
         """Pick the fastest sub-block shape (sapq_autotune); returns it."""

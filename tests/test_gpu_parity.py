@@ -194,6 +194,7 @@ def test_phase_kernel_variants(torch_cuda, orc, name, kernel, monkeypatch):
     L, B, S, kappa, eps, bc = GEOMS[name]
     U, F = fields(name)
     s = make_solver(name, n_sap=2)
+    assert s.phase_kernel == kernel
     v = synth.gaussian_spinor(L, 121)
     prm = orc.params(kappa, n_sap=2)
     for colour in (0, 1):
@@ -215,6 +216,7 @@ def test_phase_kernel_variants_low_precision(torch_cuda, orc, kernel, prec, monk
     L, B, S, kappa, eps, bc = GEOMS[name]
     U, F = fields(name)
     s = make_solver(name, prec=prec)
+    assert s.phase_kernel == kernel
     v = synth.gaussian_spinor(L, 122)
     y_w, dy_w = orc.msap(L, B, S, U, F, orc.params(kappa), v, bc=bc)
     y, dy = (to_host(t) for t in s.sap_precondition(to_dev(v)))
@@ -229,6 +231,7 @@ def test_split_kernel_solve_24x24x24x48_block(torch_cuda, orc):
     L, B, S, kappa, eps, bc = GEOMS[name]
     U, F = fields(name)
     s = make_solver(name)
+    assert s.phase_kernel == "two-lane split"
     b = synth.gaussian_spinor(L, 123)
     for _ in range(2):
         x, st = s.solve(to_dev(b), tol=1e-10)
