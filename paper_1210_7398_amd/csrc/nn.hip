@@ -47,6 +47,50 @@ __device__ __forceinline__ void nn_transport(cx<float> t[12], const float2 *__re
     }
 }
 
+// Neighbour of (ib, s) for transport d (0: the site itself): block, slot and boundary sign.
+__device__ __forceinline__ void nn_neighbour(const GeomDev &g, int ib, int s, int d, int &nb, int &ns, float &ph) {
+    nb = ib;
+    ns = s;
+    ph = 1.f;
+    if (d == 0) return;
+    const int mu = (d - 1) >> 1;
+    const bool fwd = ((d - 1) & 1) == 0;
+    const unsigned w = g.nbr16[mu * g.Vb + s];
+    const unsigned half = fwd ? (w & 0xffffu) : (w >> 16);
+    ns = (int)(half & 0x7fffu);
+    if (!(half & 0x8000u)) {
+        const int bl = g.blk_nbr[(2 * mu + (fwd ? 0 : 1)) * g.NB + ib];
+        nb = bl & BLK_MASK;
+        ph = (bl & WRAP_BIT) ? g.bc[mu] : 1.f;
+    }
+}
+
+// (T_d psi)(ib, s) with the neighbour (nb, ns, ph) already known
+template <int P>
+__device__ __forceinline__ void nn_transport_at(cx<float> t[12], const float2 *__restrict__ psi, const GeomDev &g,
+                                                const typename Prec<P>::S2 *__restrict__ U, int ib, int s, int d, int nb,
+                                                int ns, float ph) {
+    if (d == 0) {
+        load_spinor(t, psi, g, ib, s);
+        return;
+    }
+    const int mu = (d - 1) >> 1;
+    const bool fwd = ((d - 1) & 1) == 0;
+    cx<float> p[12], u[9];
+    load_spinor(p, psi, g, nb, ns);
+    if (fwd)
+        load_link(u, U, g, ib, s, mu);
+    else
+        load_link(u, U, g, nb, ns, mu);
+#pragma unroll
+    for (int be = 0; be < 4; ++be) {
+        cx<float> h[3] = {p[3 * be], p[3 * be + 1], p[3 * be + 2]}, o[3];
+        su3_mul(o, u, h, !fwd);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t[3 * be + a] = ph * o[a];
+    }
+}
+
 // out[c'] for one output channel c' = blockIdx.y; weights W[9][COUT][CIN][16] complex (float2)
 template <int P, int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_nn_layer(GeomDev g, const float2 *__restrict__ in, float2 *__restrict__ out,
@@ -173,6 +217,8 @@ __global__ void k_nn_round(int n, const float *__restrict__ w, float *__restrict
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
+struct __attribute__((aligned(8))) bf16x4 { __hip_bfloat16 v[4]; };
+
 __host__ __device__ constexpr int nn_k2p(int cin) { return (72 * cin + 15) / 16 * 16; }
 __host__ __device__ constexpr int nn_m2p(int cout) { return 8 * cout < 16 ? 16 : (8 * cout + 15) / 16 * 16; }
 
@@ -203,25 +249,40 @@ __global__ void __launch_bounds__(256) k_nn_layer_mfma(GeomDev g, const float2 *
     constexpr int NS = 16, NC = 48, BPAD = K2P + 8, KS = K2P / 16, MT = M2P / 16, NT = 3;
     constexpr int B_BYTES = NC * BPAD * 2, D_BYTES = M2P * (NC + 1) * 4;
     __shared__ __attribute__((aligned(16))) unsigned char smem[B_BYTES > D_BYTES ? B_BYTES : D_BYTES];
+    __shared__ int nb_blk[9][NS], nb_slot[9][NS];
+    __shared__ float nb_ph[9][NS];
     __hip_bfloat16 (*Bt)[BPAD] = reinterpret_cast<__hip_bfloat16 (*)[BPAD]>(smem);
     float (*Dt)[NC + 1] = reinterpret_cast<float (*)[NC + 1]>(smem);
     const long site0 = (long)blockIdx.x * NS;
     const size_t chan = (size_t)g.V * 12;
+    // 0. the neighbours of the tile's sites, once for all channels
+    for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
+        const int t = w % NS, d = w / NS;
+        const long i = site0 + t;
+        const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        nn_neighbour(g, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
+    }
+    __syncthreads();
     // 1. transported inputs of the tile, BF16, column = 3 * site + colour
     for (int w = threadIdx.x; w < NS * 9 * CIN; w += blockDim.x) {
         const int t = w % NS, rest = w / NS, c = rest % CIN, d = rest / CIN;
         const long i = site0 + t;
         const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
         cx<float> T[12];
-        nn_transport<P>(T, in + c * chan, g, U, ib, s, d);
+        nn_transport_at<P>(T, in + c * chan, g, U, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
         const int kb = (d * CIN + c) * 4;
+        // the four spins of one (colour, re / im) are adjacent in k: one 8-byte store each
 #pragma unroll
-        for (int be = 0; be < 4; ++be)
+        for (int a = 0; a < 3; ++a) {
+            bf16x4 re, im;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                Bt[3 * t + a][kb + be] = __float2bfloat16(T[3 * be + a].r);
-                Bt[3 * t + a][K + kb + be] = __float2bfloat16(T[3 * be + a].i);
+            for (int be = 0; be < 4; ++be) {
+                re.v[be] = __float2bfloat16(T[3 * be + a].r);
+                im.v[be] = __float2bfloat16(T[3 * be + a].i);
             }
+            *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][kb]) = re;
+            *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][K + kb]) = im;
+        }
     }
     if constexpr (K2P > K2) {
         for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
