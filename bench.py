@@ -44,7 +44,8 @@ WORKLOADS = {
 
 def copy_calibration(nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE
-    counters of rocprofv3 (run this mode under the profiler)."""
+    counters of rocprofv3 (run this mode under the profiler), and without the profiler the
+    copy and fill rates the box reaches."""
     import torch
 
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
@@ -55,8 +56,14 @@ def copy_calibration(nbytes=1 << 30, reps=5):
         b.copy_(a)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.fill_(2.0)
+    torch.cuda.synchronize()
+    df = (time.perf_counter() - t0) / reps
     print(json.dumps({"mode": "copy", "bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
-                      "launches": reps, "GBps_read_plus_write": 2 * nbytes / dt / 1e9}), flush=True)
+                      "launches": reps, "GBps_read_plus_write": 2 * nbytes / dt / 1e9,
+                      "fill_GBps": nbytes / df / 1e9}), flush=True)
 
 
 def make_inputs(w):
