@@ -122,6 +122,100 @@ def precision_study(args):
           flush=True)
 
 
+def _solve_stats(s, bd, steps):
+    """Median time of `steps` solves after one warm-up, with the last solve's statistics."""
+    import torch
+
+    s.solve(bd, tol=1e-10)
+    times, st = [], None
+    for _ in range(max(1, steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st = s.solve(bd, tol=1e-10, profile=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    ph = st["kernels"].get("phase_E", {}), st["kernels"].get("phase_O", {})
+    n_ph = ph[0].get("n", 0) + ph[1].get("n", 0)
+    return sorted(times)[len(times) // 2], st, (1e3 * (ph[0].get("ms", 0) + ph[1].get("ms", 0)) / n_ph) if n_ph else None
+
+
+# SAP block and sub-block shapes of the block-shape study at 24^3x48 (sub-block = block is the
+# natural-order SSOR, the paper's reference point for the ll ordering)
+BLOCK_SHAPES = [((6, 6, 6, 12), (3, 3, 3, 6)), ((6, 6, 6, 12), (2, 2, 2, 4)), ((6, 6, 6, 12), (3, 3, 3, 3)),
+                ((6, 6, 6, 12), (6, 6, 6, 12)), ((6, 6, 6, 6), (3, 3, 3, 3)), ((6, 6, 6, 6), (2, 2, 2, 2)),
+                ((6, 6, 6, 6), (6, 6, 6, 6)), ((4, 4, 4, 4), (2, 2, 2, 2)), ((4, 4, 4, 4), (4, 4, 4, 4))]
+
+
+def blocks_study(args):
+    """Block and sub-block shapes at 24^3x48 (the default workload's fields and source): M_SAP
+    applications and time to 1e-10 for each shape, with the phase kernel each one runs."""
+    import torch
+
+    from paper_1210_7398_amd import sapq
+
+    w = WORKLOADS["24^3x48"]
+    U, F, b = make_inputs(w)
+    dev = torch.device("cuda:0")
+    Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
+    del U, F
+    res = []
+    for B, S in BLOCK_SHAPES:
+        s = sapq.Solver(w["L"], B, S, w["kappa"], device=dev)
+        s.load_gauge(Ud)
+        s.load_clover(Fd)
+        t, st, ph_us = _solve_stats(s, bd, args.steps)
+        res.append(dict(block=list(B), subblock=list(S), phase_kernel=s.phase_kernel, time_s=t, n_msap=st["n_msap"],
+                        inner_its=st["inner_its"], outer_its=st["outer_its"], true_relres=st["true_relres"],
+                        sap_phase_avg_us=ph_us))
+        print(f"# {res[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "blocks", "lattice": list(w["L"]), "kappa": w["kappa"], "tol": 1e-10, "results": res}),
+          flush=True)
+
+
+def msap_flops(B, V, n_ssor=4, n_sap=4):
+    """Algorithmic flops of one M_SAP application on V sites (phase model, Table 1 counts)."""
+    face = sum(2.0 / b for b in B)
+    _, ph = phase_model(B, n_ssor, 4)
+    return n_sap * V * ph + (V // 2) * (face * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS)
+
+
+def sustained_study(args):
+    """Sustained rate of the solver at three lattice sizes with 6^3x12 blocks: algorithmic flops
+    of the M_SAP applications and FP64 operator applications of a solve, divided by its time
+    (the BiCGStab vector updates are not counted)."""
+    import torch
+
+    from paper_1210_7398_amd import sapq, synth
+
+    dev = torch.device("cuda:0")
+    res = []
+    for L, seed in (((12, 12, 12, 24), 41), ((24, 24, 24, 48), 2), ((48, 48, 48, 96), 43)):
+        B, S, kappa = (6, 6, 6, 12), (3, 3, 3, 6), 0.125
+        Ud = synth.gauge_field(L, 0.25, seed, device=dev)
+        Fd = synth.clover_inverse(L, Ud, 1.0, kappa, device=dev)
+        bd = torch.from_numpy(synth.gaussian_spinor(L, 1000 + seed)).to(dev)
+        s = sapq.Solver(L, B, S, kappa, device=dev)
+        s.load_gauge(Ud)
+        s.load_clover(Fd)
+        del Ud, Fd
+        t, st, ph_us = _solve_stats(s, bd, args.steps)
+        V = int(np.prod(L))
+        fl = st["n_msap"] * msap_flops(B, V) + st["n_dslash64"] * V * (8 * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS)
+        res.append(dict(lattice=list(L), time_s=t, n_msap=st["n_msap"], n_dslash64=st["n_dslash64"],
+                        true_relres=st["true_relres"], flops=fl, TFLOPs=fl / t / 1e12,
+                        frac_fp32_peak=fl / t / 1e12 / FP32_PEAK_TFLOPS,
+                        frac_fp32_unpacked=fl / t / 1e12 / (FP32_PEAK_TFLOPS / 2), sap_phase_avg_us=ph_us))
+        print(f"# {res[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s, bd
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "sustained", "block": [6, 6, 6, 12], "subblock": [3, 3, 3, 6], "tol": 1e-10,
+                      "results": res}), flush=True)
+
+
 BATCH_FIELDS = [((16, 16, 16, 32), 0.2, 11), ((24, 24, 24, 48), 0.25, 12), ((24, 24, 24, 48), 0.3, 13),
                 ((32, 32, 32, 64), 0.25, 14)]
 
@@ -358,7 +452,8 @@ def main():
     ap.add_argument("--workload", default="24^3x48", choices=list(WORKLOADS))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision", "batch", "nn"])
+    ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision", "batch", "nn", "blocks",
+                                                        "sustained"])
     ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -376,6 +471,12 @@ def main():
         return
     if args.mode == "nn":
         nn_study(args)
+        return
+    if args.mode == "blocks":
+        blocks_study(args)
+        return
+    if args.mode == "sustained":
+        sustained_study(args)
         return
 
     import numpy as np
