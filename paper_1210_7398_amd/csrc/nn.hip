@@ -7,7 +7,7 @@
 // with the fermion boundary sign on hops that wrap.  Activations are FP32 fields in the
 // internal layout, one [NB][12][Vb] spinor field per channel.  The forward pass uses the
 // weights rounded to BF16 (FP32 arithmetic); Adam keeps an FP32 master copy.
-#include "sapq_impl.h"
+#include "sitecore.h"
 
 namespace sapq {
 
@@ -89,6 +89,26 @@ __device__ __forceinline__ void nn_transport_at(cx<float> t[12], const float2 *_
 #pragma unroll
         for (int a = 0; a < 3; ++a) t[3 * be + a] = ph * o[a];
     }
+}
+
+// Tile of 16 sites of a layer workgroup.  Workgroups are dealt to the 8 XCDs in turn; with
+// a grid that is a multiple of 8, XCD x takes the x-th eighth of the tiles, and tiles run
+// through whole blocks in lexicographic block order, so that the neighbours a tile reads
+// (mostly in the same block or the next one) were fetched into the same L2.  ib < 0 marks a
+// workgroup past the last tile; n_valid sites of the tile exist (blocks need not hold a
+// multiple of 16 sites).
+__device__ __forceinline__ void nn_tile(const GeomDev &g, int &ib, int &s0, int &n_valid) {
+    const long vt = xcd_site_base(1);
+    const int tpb = (g.Vb + 15) / 16;
+    const long bl = vt / tpb;
+    ib = bl < g.NB ? g.lex_blk[bl] : -1;
+    s0 = (int)(vt - bl * tpb) * 16;
+    n_valid = min(16, g.Vb - s0);
+}
+
+unsigned nn_grid(const Ctx *c) {
+    const long tiles = (long)c->g.NB * ((c->g.Vb + 15) / 16);
+    return (unsigned)((tiles + N_XCD - 1) / N_XCD * N_XCD);
 }
 
 // out[c'] for one output channel c' = blockIdx.y; weights W[9][COUT][CIN][16] complex (float2)
@@ -253,21 +273,22 @@ __global__ void __launch_bounds__(256) k_nn_layer_mfma(GeomDev g, const float2 *
     __shared__ float nb_ph[9][NS];
     __hip_bfloat16 (*Bt)[BPAD] = reinterpret_cast<__hip_bfloat16 (*)[BPAD]>(smem);
     float (*Dt)[NC + 1] = reinterpret_cast<float (*)[NC + 1]>(smem);
-    const long site0 = (long)blockIdx.x * NS;
+    int ib, s0, nv;
+    nn_tile(g, ib, s0, nv);
+    if (ib < 0) return;
     const size_t chan = (size_t)g.V * 12;
-    // 0. the neighbours of the tile's sites, once for all channels
+    // 0. the neighbours of the tile's sites, once for all channels (missing sites of a short
+    // tile repeat the last one; their columns are not stored)
     for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
         const int t = w % NS, d = w / NS;
-        const long i = site0 + t;
-        const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        const int s = s0 + min(t, nv - 1);
         nn_neighbour(g, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
     }
     __syncthreads();
     // 1. transported inputs of the tile, BF16, column = 3 * site + colour
     for (int w = threadIdx.x; w < NS * 9 * CIN; w += blockDim.x) {
         const int t = w % NS, rest = w / NS, c = rest % CIN, d = rest / CIN;
-        const long i = site0 + t;
-        const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        const int s = s0 + min(t, nv - 1);
         cx<float> T[12];
         nn_transport_at<P>(T, in + c * chan, g, U, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
         const int kb = (d * CIN + c) * 4;
@@ -323,9 +344,98 @@ __global__ void __launch_bounds__(256) k_nn_layer_mfma(GeomDev g, const float2 *
     for (int w = threadIdx.x; w < NS * COUT * 12; w += blockDim.x) {
         const int t = w % NS, rest = w / NS, comp = rest % 12, co = rest / 12;
         const int r = co * 4 + comp / 3, col = 3 * t + comp % 3;
-        const long i = site0 + t;
-        const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
-        out[co * chan + ((size_t)ib * 12 + comp) * g.Vb + s] = make_float2(Dt[r][col], Dt[M + r][col]);
+        if (t < nv) out[co * chan + ((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
+    }
+}
+
+// The same layer for 8 input channels, with the reduction index taken in chunks of two
+// transport directions (128 rows: re and im of 2 directions x 8 channels x 4 spins).  A chunk
+// is one transport per thread, all loads in flight together, written to a 13 KB LDS tile
+// that the MFMA consumes before the next chunk; the accumulators stay in registers.  The
+// small LDS footprint lets about five workgroups share a CU.
+template <int P, int COUT>
+__global__ void __launch_bounds__(256) k_nn_layer8_mfma(GeomDev g, const float2 *__restrict__ in,
+                                                       float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
+                                                       const typename Prec<P>::S2 *__restrict__ U) {
+    constexpr int CIN = 8, K = 36 * CIN, K2P = nn_k2p(CIN), M = 4 * COUT, M2P = nn_m2p(COUT);
+    constexpr int NS = 16, NC = 48, KS = K2P / 16, MT = M2P / 16, NT = 3;
+    constexpr int CR = 128, BPAD = CR + 8;  // rows of a chunk (local: re 0..63, im 64..127)
+    static_assert(K2P == 2 * K && K % 16 == 0, "8 input channels fill whole k-tiles");
+    __shared__ __attribute__((aligned(16))) __hip_bfloat16 Bt[NC][BPAD];
+    __shared__ float Dt[M2P][NC + 1];
+    __shared__ int nb_blk[9][NS], nb_slot[9][NS];
+    __shared__ float nb_ph[9][NS];
+    int ib, s0, nv;
+    nn_tile(g, ib, s0, nv);
+    if (ib < 0) return;
+    const size_t chan = (size_t)g.V * 12;
+    for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
+        const int t = w % NS, d = w / NS;
+        const int s = s0 + min(t, nv - 1);
+        nn_neighbour(g, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kq = 4 * (lane >> 4);
+    float4_t acc[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    for (int d0 = 0; d0 < 9; d0 += 2) {
+        const int nd = d0 == 8 ? 1 : 2;
+        // transports of directions d0, d0 + 1 for all channels: one per thread
+        for (int w = threadIdx.x; w < NS * CIN * nd; w += blockDim.x) {
+            const int t = w % NS, c = (w / NS) % CIN, dd = w / (NS * CIN), d = d0 + dd;
+            const int s = s0 + min(t, nv - 1);
+            cx<float> T[12];
+            nn_transport_at<P>(T, in + c * chan, g, U, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
+            const int lr = (dd * CIN + c) * 4;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                bf16x4 re, im;
+#pragma unroll
+                for (int be = 0; be < 4; ++be) {
+                    re.v[be] = __float2bfloat16(T[3 * be + a].r);
+                    im.v[be] = __float2bfloat16(T[3 * be + a].i);
+                }
+                *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][lr]) = re;
+                *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][64 + lr]) = im;
+            }
+        }
+        __syncthreads();
+        // k-tiles of the chunk: re rows of d0 (global tile 2 d0 + lt), im rows (K / 16 + 2 d0 + lt)
+        const int ntile = 2 * nd;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int tile = wave + 4 * j;
+            if (tile < MT * NT) {
+                const int mt = tile / NT, nt = tile % NT, col = nt * 16 + (lane & 15);
+                const short4_t *Ap = Afrag + (size_t)mt * KS * 64 + lane;
+                for (int lt = 0; lt < ntile; ++lt) {
+                    const short4_t a_re = Ap[(size_t)(2 * d0 + lt) * 64];
+                    const short4_t b_re = *reinterpret_cast<const short4_t *>(&Bt[col][lt * 16 + kq]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_re, b_re, acc[j], 0, 0, 0);
+                    const short4_t a_im = Ap[(size_t)(K / 16 + 2 * d0 + lt) * 64];
+                    const short4_t b_im = *reinterpret_cast<const short4_t *>(&Bt[col][64 + lt * 16 + kq]);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_im, b_im, acc[j], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int tile = wave + 4 * j;
+        if (tile < MT * NT) {
+            const int mt = tile / NT, nt = tile % NT, col = nt * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Dt[mt * 16 + kq + q][col] = acc[j][q];
+        }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < NS * COUT * 12; w += blockDim.x) {
+        const int t = w % NS, rest = w / NS, comp = rest % 12, co = rest / 12;
+        const int r = co * 4 + comp / 3, col = 3 * t + comp % 3;
+        if (t < nv) out[co * chan + ((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
     }
 }
 
@@ -346,15 +456,15 @@ static void nn_layer_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out,
 template <int P>
 static void nn_layer_mfma_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *Af) {
     using S2 = typename Prec<P>::S2;
-    const unsigned grid = (unsigned)(c->V / 16);
+    const unsigned grid = nn_grid(c);
     const S2 *U = (const S2 *)c->Uin;
     const short4_t *A = (const short4_t *)Af;
     if (cin == 1 && cout == 8)
         k_nn_layer_mfma<P, 1, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
     else if (cin == 8 && cout == 8)
-        k_nn_layer_mfma<P, 8, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
+        k_nn_layer8_mfma<P, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
     else if (cin == 8 && cout == 1)
-        k_nn_layer_mfma<P, 8, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
+        k_nn_layer8_mfma<P, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
 }
 
 size_t nn_afrag_elems(int cin, int cout) { return (size_t)nn_m2p(cout) * nn_k2p(cin); }
