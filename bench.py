@@ -377,15 +377,46 @@ def nn_study(args):
         s.close()
         del s
         torch.cuda.empty_cache()
+    # the same sources through the batched solver, in sub-batches of 6 (FP64 defect correction)
+    sub = int(os.environ.get("SAPQ_NN_SUB_BATCH", "6"))
+    batched = []
+    for prec in ("fp32", "fp16"):
+        s = sapq.Solver(La, B, S, kappa, prec=prec, outer="defect", nn=True, device=dev)
+        s.load_gauge(U)
+        s.load_clover(F)
+        s.nn_set_weights(w)
+        for use in (False, True):
+            s.use_nn(use)
+            tot, its, worst = 0.0, 0, 0.0
+            for k0 in range(0, n_apply, sub):
+                ks = list(range(k0, min(k0 + sub, n_apply)))
+                bb = torch.zeros((len(ks), V, 4, 3), dtype=torch.complex128, device=dev)
+                for j, k in enumerate(ks):
+                    bb[j, 0, k % 4, k // 4 % 3] = 1.0
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                xs, sts = sapq.solve_batch([s], [bb], tol=1e-10)
+                torch.cuda.synchronize()
+                tot += time.perf_counter() - t1
+                its += sum(q["inner_its"] for q in sts)
+                worst = max(worst, max(q["true_relres"] for q in sts))
+                del xs, bb
+                torch.cuda.empty_cache()
+            batched.append(dict(prec=prec, learned_stage=use, sources=n_apply, sub_batch=sub, time_s=tot,
+                                inner_its=its, max_true_relres=worst))
+            print(f"# batched {batched[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
     base = results[0]["time_s"]
-    for r in results:
+    for r in results + batched:
         r["speedup_vs_plain_fp32"] = base / r["time_s"]
     print(json.dumps({"mode": "nn", "metric": "time-to-1e-10 residual (s); learned stage + mixed precision vs plain SAP",
                       "train": dict(lattice=list(Lt), fields=[21, 22, 23, 24], pairs=4 * n_src * 5, steps=steps,
                                     batch=8, lr=2e-3, pair_generation_s=gen_s, train_s=train_s,
                                     loss_first=losses[0], loss_last20=float(np.mean(losses[-20:]))),
                       "apply": dict(lattice=list(La), seed=31, kappa=kappa, block=list(B), subblock=list(S)),
-                      "results": results}), flush=True)
+                      "results": results, "batched": batched}), flush=True)
 
 
 def phase_model(B, n_ssor, prec_bytes):

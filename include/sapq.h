@@ -190,7 +190,11 @@ int sapq_solve(sapq_ctx *ctx, double *x, const double *b, double tol, sapq_stats
  * (x += Inner(b - D x), true residual per right-hand side), each inner BiCGStab iteration is one
  * hipGraph replay, and each SAP phase is one kernel launch over all fields, blocks and groups of
  * right-hand sides, the links and clover rows of a site being loaded once per group.  Krylov
- * scalars are per right-hand side; converged ones are masked.  Parameters (kappa, n_ssor, n_sap,
+ * scalars are per right-hand side; converged ones are masked.  When every context has the
+ * learned stage on (weights set, params.flags & SAPQ_FLAG_NN), the inner preconditioner is
+ * z = N r + M_SAP (r - D N r) for each right-hand side, the network applied per right-hand side
+ * on its context and the SAP phases batched.  The arena size depends on that setting: size it
+ * after setting the flags.  Parameters (kappa, n_ssor, n_sap,
  * tol_inner, maxit_*) are each context's; the stream is ctxs[0]'s.  arena: device memory of at
  * least sapq_batch_arena_bytes() bytes, 256-byte aligned.  stats (host, nullable): one entry per
  * right-hand side, contexts in order.  Returns SAPQ_ENOTCONV if any right-hand side missed tol.

@@ -537,6 +537,16 @@ static double2 dot1(Ctx *c, int prec, const void *a, const void *b) {
     return r;
 }
 
+// z = N p and rp = p - D z, on inner-precision vectors of the context's lattice
+void nn_apply(Ctx *c, const void *p, void *z, void *rp) {
+    const int pi = c->prm.prec_inner;
+    blas_convert(c, SAPQ_FP32, c->nn_a0, pi, p, 1.0);
+    nn_forward(c);
+    blas_convert(c, pi, z, SAPQ_FP32, c->nn_z, 1.0);
+    launch_dslash(c, pi, rp, z);
+    blas_xpay(c, pi, rp, p, make_double2(-1, 0), rp);  // rp = p - D z
+}
+
 // The inner preconditioner: ph = M_SAP p, or with the learned stage ph = z + M_SAP (p - D z),
 // z = N p.  Either way D ph = p - r_N comes out of the SAP recurrence: v = p - sap_r.
 static void precondition(Ctx *c, const void *p, void *ph) {
@@ -545,11 +555,7 @@ static void precondition(Ctx *c, const void *p, void *ph) {
         msap(c, p, ph);
         return;
     }
-    blas_convert(c, SAPQ_FP32, c->nn_a0, pi, p, 1.0);
-    nn_forward(c);
-    blas_convert(c, pi, c->i_z, SAPQ_FP32, c->nn_z, 1.0);
-    launch_dslash(c, pi, c->i_rp, c->i_z);
-    blas_xpay(c, pi, c->i_rp, p, make_double2(-1, 0), c->i_rp);  // r' = p - D z
+    nn_apply(c, p, c->i_z, c->i_rp);
     msap(c, c->i_rp, ph);
     blas_xpay(c, pi, ph, ph, make_double2(1, 0), c->i_z);         // ph = M r' + z
     // the SAP recurrence left sap_r = r' - D M r', so p - sap_r = D z + D M r' = D ph

@@ -18,7 +18,7 @@
 namespace sapq {
 
 // inner vector slots (storage precision), rhs-major: slot base + k * nvec
-enum { IV_R, IV_RT, IV_P, IV_V, IV_S, IV_T, IV_E, IV_PH, IV_SH, IV_SAPR, IV_SAPX, IV_RIN, NIV };
+enum { IV_R, IV_RT, IV_P, IV_V, IV_S, IV_T, IV_E, IV_PH, IV_SH, IV_SAPR, IV_SAPX, IV_RIN, IV_Z, IV_RP, NIV };
 // outer vector slots (FP64)
 enum { DV_B, DV_X, DV_R, DV_T, NDV };
 
@@ -325,18 +325,20 @@ __global__ void __launch_bounds__(768) k_bsap_phase_2l(const BatchDev *__restric
 
 // allow the batched phase kernels the dynamic LDS they are launched with
 static void batch_lds_attr(int bytes) {
-    const void *fns[] = {(const void *)k_bsap_phase<SAPQ_FP32, 1>, (const void *)k_bsap_phase<SAPQ_FP32, 2>,
-                         (const void *)k_bsap_phase<SAPQ_FP32, 4>, (const void *)k_bsap_phase<SAPQ_FP16, 1>,
-                         (const void *)k_bsap_phase<SAPQ_FP16, 2>, (const void *)k_bsap_phase<SAPQ_FP16, 4>,
-                         (const void *)k_bsap_phase<SAPQ_BF16, 1>, (const void *)k_bsap_phase<SAPQ_BF16, 2>,
-                         (const void *)k_bsap_phase<SAPQ_BF16, 4>};
+    const void *fns[] = {
+        (const void *)k_bsap_phase<SAPQ_FP32, 1>,    (const void *)k_bsap_phase<SAPQ_FP32, 2>,
+        (const void *)k_bsap_phase<SAPQ_FP32, 3>,    (const void *)k_bsap_phase<SAPQ_FP32, 4>,
+        (const void *)k_bsap_phase<SAPQ_FP16, 1>,    (const void *)k_bsap_phase<SAPQ_FP16, 2>,
+        (const void *)k_bsap_phase<SAPQ_FP16, 3>,    (const void *)k_bsap_phase<SAPQ_FP16, 4>,
+        (const void *)k_bsap_phase<SAPQ_BF16, 1>,    (const void *)k_bsap_phase<SAPQ_BF16, 2>,
+        (const void *)k_bsap_phase<SAPQ_BF16, 3>,    (const void *)k_bsap_phase<SAPQ_BF16, 4>,
+        (const void *)k_bsap_phase_2l<SAPQ_FP32, 1>, (const void *)k_bsap_phase_2l<SAPQ_FP32, 2>,
+        (const void *)k_bsap_phase_2l<SAPQ_FP32, 3>, (const void *)k_bsap_phase_2l<SAPQ_FP32, 4>,
+        (const void *)k_bsap_phase_2l<SAPQ_FP16, 1>, (const void *)k_bsap_phase_2l<SAPQ_FP16, 2>,
+        (const void *)k_bsap_phase_2l<SAPQ_FP16, 3>, (const void *)k_bsap_phase_2l<SAPQ_FP16, 4>,
+        (const void *)k_bsap_phase_2l<SAPQ_BF16, 1>, (const void *)k_bsap_phase_2l<SAPQ_BF16, 2>,
+        (const void *)k_bsap_phase_2l<SAPQ_BF16, 3>, (const void *)k_bsap_phase_2l<SAPQ_BF16, 4>};
     for (const void *f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    const void *fns2[] = {(const void *)k_bsap_phase_2l<SAPQ_FP32, 1>, (const void *)k_bsap_phase_2l<SAPQ_FP32, 2>,
-                          (const void *)k_bsap_phase_2l<SAPQ_FP32, 4>, (const void *)k_bsap_phase_2l<SAPQ_FP16, 1>,
-                          (const void *)k_bsap_phase_2l<SAPQ_FP16, 2>, (const void *)k_bsap_phase_2l<SAPQ_FP16, 4>,
-                          (const void *)k_bsap_phase_2l<SAPQ_BF16, 1>, (const void *)k_bsap_phase_2l<SAPQ_BF16, 2>,
-                          (const void *)k_bsap_phase_2l<SAPQ_BF16, 4>};
-    for (const void *f : fns2) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 // r_c += kappa F sum_{hops leaving the block} H x for every field and right-hand side
@@ -673,6 +675,7 @@ struct Batch {
     long max_V = 0;
     int prec = SAPQ_FP32, NR = 1;
     bool two_lane = false;  // k_bsap_phase_2l (else the four-lane k_bsap_phase)
+    bool use_nn = false;    // every context has the learned stage on
     int threads = 0;
     size_t lds = 0;
     hipStream_t stream = nullptr;
@@ -700,7 +703,8 @@ static size_t layout_batch(Batch &B, char *base) {
     B.active = (int *)take(sizeof(int) * 4);
     for (int f = 0; f < B.nf; ++f) {
         BField &F = B.host.f[f];
-        for (int s = 0; s < NIV; ++s) F.iv[s] = take(rhs_bytes(B.ctx[f], B.prec) * F.nrhs);
+        for (int s = 0; s < NIV; ++s)
+            F.iv[s] = (s == IV_Z || s == IV_RP) && !B.use_nn ? nullptr : take(rhs_bytes(B.ctx[f], B.prec) * F.nrhs);
         for (int s = 0; s < NDV; ++s) F.dv[s] = (double2 *)take(B.ctx[f]->nvec * 16 * F.nrhs);
     }
     return used + 256;
@@ -732,7 +736,9 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
     Ctx *c0 = B.ctx[0];
     B.prec = c0->prm.prec_inner;
     B.stream = c0->stream;
-    // right-hand sides per workgroup: as many as the LDS holds (1, 2 or 4)
+    B.use_nn = true;
+    for (Ctx *c : B.ctx) B.use_nn = B.use_nn && c->have_nn && (c->prm.flags & SAPQ_FLAG_NN);
+    // right-hand sides per workgroup: 1 to 4, as the LDS and the thread limit allow
     int max_lds = 65536, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     // two lanes per site when every context runs the one-workgroup two-lane kernel (same
@@ -742,11 +748,19 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
     const size_t per = B.two_lane ? (size_t)(c0->g.Vb + 1) * 6 * sizeof(float4) : (size_t)c0->g.Vb * 12 * sizeof(float2);
     const size_t extra = B.two_lane ? 0 : c0->lds_extra;
     const int tpr = B.two_lane ? c0->part_threads : c0->ssor_threads;
+    // right-hand sides per group: the size that leaves the fewest empty slots in the groups of
+    // all fields (ties to the larger group), among those whose iterates fit LDS
     B.NR = 0;
-    for (int nr : {4, 2, 1})
-        if (B.NR == 0 && nr <= std::max(1, B.max_rhs) && per * nr + extra <= (size_t)max_lds &&
-            (!B.two_lane || nr * tpr <= 768))
+    long best_slots = 0;
+    for (int nr : {4, 3, 2, 1}) {
+        if (nr > std::max(1, B.max_rhs) || per * nr + extra > (size_t)max_lds || (B.two_lane && nr * tpr > 768)) continue;
+        long slots = 0;
+        for (int f = 0; f < nctx; ++f) slots += (long)(nrhs[f] + nr - 1) / nr * nr;
+        if (B.NR == 0 || slots < best_slots) {
             B.NR = nr;
+            best_slots = slots;
+        }
+    }
     if (B.NR == 0) { why = "the SAP block is too large for the batched kernel's LDS"; return SAPQ_ESHAPE; }
     B.lds = per * B.NR + extra;
     B.threads = B.two_lane ? B.NR * tpr : c0->ssor_threads;
@@ -811,6 +825,7 @@ static void bmsap(Batch &B, int src, int y) {
         for (int colour = 0; colour < 2; ++colour) {
             BPREC(B.prec, ({
                       if (B.NR == 4) bphase<P_, 4>(B, colour, j == 0, s, IV_SAPR, IV_SAPX, y);
+                      else if (B.NR == 3) bphase<P_, 3>(B, colour, j == 0, s, IV_SAPR, IV_SAPX, y);
                       else if (B.NR == 2) bphase<P_, 2>(B, colour, j == 0, s, IV_SAPR, IV_SAPX, y);
                       else bphase<P_, 1>(B, colour, j == 0, s, IV_SAPR, IV_SAPX, y);
                   }));
@@ -835,16 +850,37 @@ static void bxpay(Batch &B, int z, int x, int which, int y, int masked) {
     BPREC(B.prec, (k_bxpay<P_><<<vgrid(B), 256, 0, B.stream>>>(B.dev, z, x, which, y, B.st, masked)));
 }
 
+// The inner preconditioner for every field and right-hand side: dst = M_SAP src, or with the
+// learned stage dst = z + M_SAP (src - D z), z = N src (the network runs per right-hand side
+// on its field's context, the SAP phases batched).  Either way the SAP recurrence leaves
+// D dst = src - r_N in IV_SAPR.
+static void bprecondition(Batch &B, int src, int dst) {
+    if (!B.use_nn) {
+        bmsap(B, src, dst);
+        return;
+    }
+    for (int f = 0; f < B.nf; ++f) {
+        Ctx *c = B.ctx[f];
+        const BField &F = B.host.f[f];
+        const size_t stride = rhs_bytes(c, B.prec);
+        for (int k = 0; k < F.nrhs; ++k)
+            nn_apply(c, (const char *)F.iv[src] + k * stride, (char *)F.iv[IV_Z] + k * stride,
+                     (char *)F.iv[IV_RP] + k * stride);
+    }
+    bmsap(B, IV_RP, dst);
+    bxpay(B, dst, dst, CF_ONE, IV_Z, 1);
+}
+
 // one inner BiCGStab iteration for every active right-hand side (captured in a graph)
 static void inner_iteration(Batch &B, double tol, int maxit) {
     bscalar(B, SC_BETA, tol, maxit);
     BPREC(B.prec, (k_bbicg_p<P_><<<vgrid(B), 256, 0, B.stream>>>(B.dev, B.st)));
-    bmsap(B, IV_P, IV_PH);
+    bprecondition(B, IV_P, IV_PH);
     bxpay(B, IV_V, IV_P, CF_MONE, IV_SAPR, 1);       // v = D p^ = p - r_N
     bdots(B, 1, IV_RT, IV_V, IV_RT, IV_V);
     bscalar(B, SC_ALPHA, tol, maxit);
     bxpay(B, IV_S, IV_R, CF_MALPHA, IV_V, 1);        // s = r - alpha v
-    bmsap(B, IV_S, IV_SH);
+    bprecondition(B, IV_S, IV_SH);
     bxpay(B, IV_T, IV_S, CF_MONE, IV_SAPR, 1);       // t = D s^
     bdots(B, 2, IV_T, IV_S, IV_T, IV_T);
     bscalar(B, SC_OMEGA, tol, maxit);

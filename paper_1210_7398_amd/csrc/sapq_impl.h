@@ -254,6 +254,8 @@ size_t nn_afrag_elems(int cin, int cout);
 void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A);
 void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *A);
 void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src);
+// learned stage on inner-precision vectors: z = N p, rp = p - D z
+void nn_apply(Ctx *c, const void *p, void *z, void *rp);
 
 // bracket a launch with HIP events when profiling is on
 int prof_begin(Ctx *c, int kind);

@@ -58,6 +58,42 @@ def test_solve_batch_two_fields(torch_cuda, orc, prec):
             q += 1
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_solve_batch_with_learned_stage(torch_cuda, orc, prec):
+    """The learned stage inside the batched inner solver (z = N r + M_SAP (r - D N r) per source):
+    every source reaches the true residual with the oracle's D, and the solutions agree with the
+    one-source solver using the same stage."""
+    from paper_1210_7398_amd import sapq
+
+    torch = torch_cuda
+    kappa = 0.125
+    B, S = (4, 4, 4, 4), (2, 2, 2, 2)
+    cfg = [((8, 8, 8, 8), 0.25, 41, 3), ((8, 8, 8, 16), 0.25, 42, 2)]
+    g = torch.Generator(device="cpu").manual_seed(5)
+    w = (0.02 * torch.randn(sapq.nn_param_count(), generator=g)).float().cuda()
+    solvers, srcs, fields = [], [], []
+    for L, eps, seed, n in cfg:
+        U, F = _field(L, eps, seed, kappa)
+        s = sapq.Solver(L, B, S, kappa, prec=prec, outer="defect", maxit_outer=100, nn=True)
+        s.load_gauge(to_dev(U))
+        s.load_clover(to_dev(F))
+        s.nn_set_weights(w)
+        s.use_nn(True)
+        b = np.stack([synth.gaussian_spinor(L, 100 * seed + k) for k in range(n)])
+        solvers.append(s)
+        srcs.append(to_dev(b))
+        fields.append((L, U, F, b))
+    xs, stats = sapq.solve_batch(solvers, srcs, tol=1e-10)
+    q = 0
+    for (L, U, F, b), x, s in zip(fields, xs, solvers):
+        x = to_host(x)
+        for k in range(b.shape[0]):
+            assert relerr(orc.dslash(L, U, F, kappa, x[k]), b[k]) <= 1e-10, (L, k, stats[q])
+            x1, _ = s.solve(to_dev(np.ascontiguousarray(b[k])), tol=1e-10)
+            assert relerr(x[k], to_host(x1)) < 1e-8
+            q += 1
+
+
 def test_autotune_picks_a_valid_subblock_and_caches(torch_cuda, orc, tmp_path):
     from paper_1210_7398_amd import sapq
 
