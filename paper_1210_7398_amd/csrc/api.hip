@@ -101,8 +101,10 @@ static void carve(Ctx *c, Arena &A, const HostTables &T, const PartTables &PT) {
     c->g.blk_nbr = ints(T.blk_nbr.size());
     c->g.plane_start = ints(MAX_PLANES + 1);  // room for any sub-block shape of this block
     c->g.slot_lex = ints(T.slot_lex.size());
+    c->slot_perm = ints(T.slot_lex.size());
     c->g.blk_lex = ints(T.blk_lex.size());
     c->g.lex_blk = ints(T.lex_blk.size());
+    c->g.zord_blk = ints(T.zord_blk.size());
     c->U64 = (double2 *)A.take((size_t)V * 24 * 16);
     c->F64 = (double2 *)A.take((size_t)V * 36 * 16);
     c->Uin = A.take((size_t)V * 24 * eb);
@@ -138,6 +140,7 @@ static void carve(Ctx *c, Arena &A, const HostTables &T, const PartTables &PT) {
         c->i_rp = A.take(nv * eb);
         for (int k = 0; k < 3; ++k) c->nn_afrag[k] = A.take(nn_afrag_elems(NN_CIN[k], NN_COUT[k]) * 2);
         c->nn_afrag_t = A.take(nn_afrag_elems(NN_C, NN_C) * 2);
+        c->nn_L = (float2 *)A.take(nn_link_elems(c) * sizeof(float2));
     }
     c->partials = (double2 *)A.take(RED_BLOCKS * 3 * sizeof(double2));
     c->dev_res = (double2 *)A.take(8 * sizeof(double2));
@@ -308,7 +311,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     if (rc) { delete h; return rc; }
     struct { const void *dst; const std::vector<int> *src; } cp[] = {
         {c->g.loc_nbr, &T.loc_nbr}, {c->g.nbr16, &T.nbr16}, {c->g.blk_nbr, &T.blk_nbr}, {c->g.plane_start, &T.plane_start},
-        {c->g.slot_lex, &T.slot_lex}, {c->g.blk_lex, &T.blk_lex}, {c->g.lex_blk, &T.lex_blk}};
+        {c->g.slot_lex, &T.slot_lex}, {c->g.blk_lex, &T.blk_lex}, {c->g.lex_blk, &T.lex_blk}, {c->g.zord_blk, &T.zord_blk}};
     for (auto &e : cp) {
         rc = hipcheck(hipMemcpyAsync((void *)e.dst, e.src->data(), e.src->size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
                       "hipMemcpyAsync(tables)");
@@ -373,6 +376,10 @@ int sapq_load_gauge(sapq_ctx *h, const double *U, double *max_dev) {
         return SAPQ_ENOTSU3;
     }
     c->have_U = true;
+    if (c->nn_alloc) {
+        launch_nn_links(c);
+        return hipcheck(hipGetLastError(), "k_nn_links");
+    }
     return SAPQ_OK;
 }
 
@@ -840,6 +847,35 @@ static int apply_subblock(Ctx *c, const int S[4]) {
         set_error("sub-block shape gives too large a hyperplane");
         return SAPQ_ESHAPE;
     }
+    // the packed fields are stored in slot order: re-lay them out for the new order (the
+    // device still holds the old slot -> in-block lexicographic map)
+    std::vector<int> perm;  // lives until the stream is synchronized below
+    if (c->have_U || c->have_F) {
+        const int Vb = c->g.Vb;
+        std::vector<int> old_lex(Vb), at(Vb);
+        perm.resize(Vb);
+        rc = hipcheck(hipMemcpyAsync(old_lex.data(), c->g.slot_lex, Vb * sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                      "hipMemcpyAsync(slot_lex)");
+        if (!rc) rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        if (rc) return rc;
+        for (int s = 0; s < Vb; ++s) at[old_lex[s]] = s;
+        bool same = true;
+        for (int s = 0; s < Vb; ++s) {
+            perm[s] = at[T.slot_lex[s]];
+            same = same && perm[s] == s;
+        }
+        if (!same) {
+            rc = hipcheck(hipMemcpyAsync(c->slot_perm, perm.data(), Vb * sizeof(int), hipMemcpyHostToDevice, c->stream),
+                          "hipMemcpyAsync(slot_perm)");
+            if (rc) return rc;
+            if (!launch_permute_fields(c, c->slot_perm)) {
+                set_error("block too large to re-order its sites in LDS");
+                return SAPQ_ESHAPE;
+            }
+            rc = hipcheck(hipGetLastError(), "k_permute_rows");
+            if (rc) return rc;
+        }
+    }
     struct { const void *dst; const std::vector<int> *src; } cp[] = {
         {c->g.loc_nbr, &T.loc_nbr}, {c->g.nbr16, &T.nbr16}, {c->g.plane_start, &T.plane_start}, {c->g.slot_lex, &T.slot_lex}};
     for (auto &e : cp) {
@@ -854,6 +890,10 @@ static int apply_subblock(Ctx *c, const int S[4]) {
     c->max_plane = T.max_plane;
     c->ssor_threads = std::min(512, ((4 * T.max_plane + 63) / 64) * 64);
     if (c->use_parts) c->part_threads = std::min(512, std::max(64, ((2 * PT.max_plane + 63) / 64) * 64));
+    if (c->nn_alloc && c->have_U) {
+        launch_nn_links(c);  // the layers' link table follows the slot order too
+        return hipcheck(hipGetLastError(), "k_nn_links");
+    }
     return SAPQ_OK;
 }
 

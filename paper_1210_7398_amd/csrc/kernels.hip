@@ -555,6 +555,48 @@ void launch_pack_clover(Ctx *c, const double *F) {
                                          c->g, (const double2 *)F, c->F64, (typename Prec<P_>::S2 *)c->Fin)));
 }
 
+// ================================================================ slot re-ordering
+// f is [rows][Vb]; each row becomes row[s] = old row[perm[s]] (one workgroup per row, the row
+// staged in LDS)
+template <typename T>
+__global__ void __launch_bounds__(256) k_permute_rows(T *__restrict__ f, int Vb, const int *__restrict__ perm) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char perm_lds[];
+    T *row = reinterpret_cast<T *>(perm_lds);
+    T *p = f + (size_t)blockIdx.x * Vb;
+    for (int s = threadIdx.x; s < Vb; s += blockDim.x) row[s] = p[s];
+    __syncthreads();
+    for (int s = threadIdx.x; s < Vb; s += blockDim.x) p[s] = row[perm[s]];
+}
+
+template <typename T>
+static bool permute_rows(Ctx *c, void *f, long rows, const int *perm) {
+    const size_t bytes = (size_t)c->g.Vb * sizeof(T);
+    if (bytes > 65536 &&
+        hipFuncSetAttribute((const void *)k_permute_rows<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) !=
+            hipSuccess)
+        return false;
+    k_permute_rows<T><<<(unsigned)rows, 256, bytes, c->stream>>>((T *)f, c->g.Vb, perm);
+    return true;
+}
+
+// The packed links and clover field (FP64 and inner precision) re-laid out for a new slot
+// order inside the blocks: new slot s holds what old slot perm[s] held.  False if a block row
+// does not fit the LDS.
+bool launch_permute_fields(Ctx *c, const int *perm) {
+    const long NB = c->g.NB;
+    const bool half = elem_bytes(c->prm.prec_inner) == 4;
+    bool ok = true;
+    if (c->have_U) {
+        ok = ok && permute_rows<uint4>(c, c->U64, NB * 24, perm);
+        ok = ok && (half ? permute_rows<unsigned>(c, c->Uin, NB * 24, perm) : permute_rows<uint2>(c, c->Uin, NB * 24, perm));
+    }
+    if (c->have_F) {
+        ok = ok && permute_rows<uint4>(c, c->F64, NB * 36, perm);
+        ok = ok && (half ? permute_rows<unsigned>(c, c->Fin, NB * 36, perm) : permute_rows<uint2>(c, c->Fin, NB * 36, perm));
+    }
+    return ok;
+}
+
 void launch_dslash(Ctx *c, int prec, void *out, const void *in) {
     const unsigned grid = (grid_for(4 * c->V, 256) + N_XCD - 1) / N_XCD * N_XCD;
     if (prec == SAPQ_FP64) {

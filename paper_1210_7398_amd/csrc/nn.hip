@@ -4,49 +4,52 @@
 // A layer maps c_in spinor channels to c_out:
 //   out[c'](n) = sum_{d=0..8} sum_c W[d][c'][c] (T_d in[c])(n),  W[d][c'][c] a 4x4 complex spin matrix,
 //   T_0 = 1, T_{1+2mu} psi(n) = U_mu(n) psi(n+mu), T_{2+2mu} psi(n) = U_mu(n-mu)^+ psi(n-mu),
-// with the fermion boundary sign on hops that wrap.  Activations are FP32 fields in the
-// internal layout, one [NB][12][Vb] spinor field per channel.  The forward pass uses the
-// weights rounded to BF16 (FP32 arithmetic); Adam keeps an FP32 master copy.
+// with the fermion boundary sign on hops that wrap.  Activations are FP32.  A one-channel
+// activation is a spinor field in the solver's layout ([NB][12][Vb]); an NN_C-channel one is
+// site-major, one record of NN_C x 12 complex per site i = ib Vb + s, so that a transport
+// reads all channels of a neighbour as one contiguous record.  The forward pass uses the
+// weights rounded to BF16; Adam keeps an FP32 master copy.
 #include "sitecore.h"
 
 namespace sapq {
 
-// (T_d psi)(ib, s) for one FP32 channel field; links in storage precision P
-template <int P>
-__device__ __forceinline__ void nn_transport(cx<float> t[12], const float2 *__restrict__ psi, const GeomDev &g,
-                                             const typename Prec<P>::S2 *__restrict__ U, int ib, int s, int d) {
-    if (d == 0) {
-        load_spinor(t, psi, g, ib, s);
-        return;
-    }
-    const int mu = (d - 1) >> 1;
-    const bool fwd = ((d - 1) & 1) == 0;
-    const unsigned w = g.nbr16[mu * g.Vb + s];
-    const unsigned half = fwd ? (w & 0xffffu) : (w >> 16);
-    const int ns = (int)(half & 0x7fffu);
-    const bool inside = (half & 0x8000u) != 0;
-    int nb = ib;
-    float ph = 1.f;
-    if (!inside) {
-        const int bl = g.blk_nbr[(2 * mu + (fwd ? 0 : 1)) * g.NB + ib];
-        nb = bl & BLK_MASK;
-        ph = (bl & WRAP_BIT) ? g.bc[mu] : 1.f;
-    }
-    cx<float> p[12], u[9];
-    load_spinor(p, psi, g, nb, ns);
-    if (fwd)
-        load_link(u, U, g, ib, s, mu);
-    else
-        load_link(u, U, g, nb, ns, mu);
+static_assert(NN_C == 8, "the layer kernels are written for 8 hidden channels");
+
+// ---------------------------------------------------------------- activations
+__device__ __forceinline__ void load_rec(cx<float> t[12], const float2 *__restrict__ f, long i, int nch, int c) {
+    const float4 *p = reinterpret_cast<const float4 *>(f + ((size_t)i * nch + c) * 12);
 #pragma unroll
-    for (int be = 0; be < 4; ++be) {
-        cx<float> h[3] = {p[3 * be], p[3 * be + 1], p[3 * be + 2]}, o[3];
-        su3_mul(o, u, h, !fwd);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) t[3 * be + a] = ph * o[a];
+    for (int k = 0; k < 6; ++k) {
+        const float4 v = p[k];
+        t[2 * k] = cx<float>{v.x, v.y};
+        t[2 * k + 1] = cx<float>{v.z, v.w};
     }
 }
 
+__device__ __forceinline__ void store_rec(float2 *__restrict__ f, long i, int nch, int c, const cx<float> t[12]) {
+    float4 *p = reinterpret_cast<float4 *>(f + ((size_t)i * nch + c) * 12);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = make_float4(t[2 * k].r, t[2 * k].i, t[2 * k + 1].r, t[2 * k + 1].i);
+}
+
+// channel c of an nch-channel activation at site (ib, s)
+__device__ __forceinline__ void load_chan(cx<float> t[12], const float2 *__restrict__ f, int nch, const GeomDev &g,
+                                          int ib, int s, int c) {
+    if (nch == 1)
+        load_spinor(t, f, g, ib, s);
+    else
+        load_rec(t, f, (long)ib * g.Vb + s, nch, c);
+}
+
+__device__ __forceinline__ void store_chan(float2 *__restrict__ f, int nch, const GeomDev &g, int ib, int s, int c,
+                                           const cx<float> t[12]) {
+    if (nch == 1)
+        store_spinor(f, g, ib, s, t);
+    else
+        store_rec(f, (long)ib * g.Vb + s, nch, c, t);
+}
+
+// ---------------------------------------------------------------- transports
 // Neighbour of (ib, s) for transport d (0: the site itself): block, slot and boundary sign.
 __device__ __forceinline__ void nn_neighbour(const GeomDev &g, int ib, int s, int d, int &nb, int &ns, float &ph) {
     nb = ib;
@@ -65,70 +68,85 @@ __device__ __forceinline__ void nn_neighbour(const GeomDev &g, int ib, int s, in
     }
 }
 
-// (T_d psi)(ib, s) with the neighbour (nb, ns, ph) already known
+// Transport links L[i][d - 1] (3x3 complex, FP32), with (T_d psi)(i) = L[i][d - 1] psi(nbr_d(i)):
+// U_mu(n) for d = 1 + 2 mu and U_mu(n - mu)^+ for d = 2 + 2 mu, times the boundary sign of the
+// hop.  Built once per gauge field from the links in storage precision, so a transport reads
+// one contiguous link of its own site instead of gathering the backward neighbour's.
 template <int P>
-__device__ __forceinline__ void nn_transport_at(cx<float> t[12], const float2 *__restrict__ psi, const GeomDev &g,
-                                                const typename Prec<P>::S2 *__restrict__ U, int ib, int s, int d, int nb,
-                                                int ns, float ph) {
-    if (d == 0) {
-        load_spinor(t, psi, g, ib, s);
-        return;
-    }
-    const int mu = (d - 1) >> 1;
+__global__ void k_nn_links(GeomDev g, const typename Prec<P>::S2 *__restrict__ U, float2 *__restrict__ L) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)g.V * 8) return;
+    const long i = t >> 3;
+    const int d = 1 + (int)(t & 7), mu = (d - 1) >> 1;
     const bool fwd = ((d - 1) & 1) == 0;
-    cx<float> p[12], u[9];
-    load_spinor(p, psi, g, nb, ns);
+    const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    int nb, ns;
+    float ph;
+    nn_neighbour(g, ib, s, d, nb, ns, ph);
+    cx<float> u[9];
     if (fwd)
         load_link(u, U, g, ib, s, mu);
     else
         load_link(u, U, g, nb, ns, mu);
+    float2 *o = L + (size_t)t * 9;
 #pragma unroll
-    for (int be = 0; be < 4; ++be) {
-        cx<float> h[3] = {p[3 * be], p[3 * be + 1], p[3 * be + 2]}, o[3];
-        su3_mul(o, u, h, !fwd);
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) t[3 * be + a] = ph * o[a];
+        for (int b = 0; b < 3; ++b) {
+            const cx<float> e = fwd ? u[3 * a + b] : conjx(u[3 * b + a]);
+            o[3 * a + b] = make_float2(ph * e.r, ph * e.i);
+        }
+}
+
+__device__ __forceinline__ void nn_link(cx<float> u[9], const float2 *__restrict__ L, long i, int d) {
+    const float2 *p = L + ((size_t)i * 8 + d - 1) * 9;
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const float2 v = p[e];
+        u[e] = cx<float>{v.x, v.y};
     }
 }
 
-// Tile of 16 sites of a layer workgroup.  Workgroups are dealt to the 8 XCDs in turn; with
-// a grid that is a multiple of 8, XCD x takes the x-th eighth of the tiles, and tiles run
-// through whole blocks in lexicographic block order, so that the neighbours a tile reads
-// (mostly in the same block or the next one) were fetched into the same L2.  ib < 0 marks a
-// workgroup past the last tile; n_valid sites of the tile exist (blocks need not hold a
-// multiple of 16 sites).
-__device__ __forceinline__ void nn_tile(const GeomDev &g, int &ib, int &s0, int &n_valid) {
-    const long vt = xcd_site_base(1);
-    const int tpb = (g.Vb + 15) / 16;
-    const long bl = vt / tpb;
-    ib = bl < g.NB ? g.lex_blk[bl] : -1;
-    s0 = (int)(vt - bl * tpb) * 16;
-    n_valid = min(16, g.Vb - s0);
+// (T_d f[c])(ib, s) for channel c of an nch-channel activation, the neighbour (nb, ns) of
+// (ib, s) for d already known
+__device__ __forceinline__ void nn_transport(cx<float> t[12], const float2 *__restrict__ f, int nch, const GeomDev &g,
+                                             const float2 *__restrict__ L, int ib, int s, int d, int c, int nb, int ns) {
+    if (d == 0) {
+        load_chan(t, f, nch, g, ib, s, c);
+        return;
+    }
+    cx<float> p[12], u[9];
+    load_chan(p, f, nch, g, nb, ns, c);
+    nn_link(u, L, (long)ib * g.Vb + s, d);
+#pragma unroll
+    for (int be = 0; be < 4; ++be) {
+        cx<float> h[3] = {p[3 * be], p[3 * be + 1], p[3 * be + 2]}, o[3];
+        su3_mul(o, u, h, false);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t[3 * be + a] = o[a];
+    }
 }
 
-unsigned nn_grid(const Ctx *c) {
-    const long tiles = (long)c->g.NB * ((c->g.Vb + 15) / 16);
-    return (unsigned)((tiles + N_XCD - 1) / N_XCD * N_XCD);
-}
-
+// ---------------------------------------------------------------- FP32 layer, weight gradient
 // out[c'] for one output channel c' = blockIdx.y; weights W[9][COUT][CIN][16] complex (float2)
-template <int P, int CIN, int COUT>
+template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_nn_layer(GeomDev g, const float2 *__restrict__ in, float2 *__restrict__ out,
-                                                 const float2 *__restrict__ W,
-                                                 const typename Prec<P>::S2 *__restrict__ U) {
+                                                 const float2 *__restrict__ W, const float2 *__restrict__ L) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const int co = blockIdx.y;
     if (i >= g.V) return;
     const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
-    const size_t chan = (size_t)g.V * 12;
     cx<float> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
     for (int d = 0; d < 9; ++d) {
+        int nb, ns;
+        float ph;
+        nn_neighbour(g, ib, s, d, nb, ns, ph);
 #pragma unroll 1
         for (int ci = 0; ci < CIN; ++ci) {
             cx<float> t[12];
-            nn_transport<P>(t, in + ci * chan, g, U, ib, s, d);
+            nn_transport(t, in, CIN, g, L, ib, s, d, ci, nb, ns);
             const float2 *w = W + (((size_t)d * COUT + co) * CIN + ci) * 16;
 #pragma unroll
             for (int al = 0; al < 4; ++al)
@@ -141,26 +159,27 @@ __global__ void __launch_bounds__(256) k_nn_layer(GeomDev g, const float2 *__res
                 }
         }
     }
-    store_spinor(out + co * chan, g, ib, s, acc);
+    store_chan(out, COUT, g, ib, s, co, acc);
 }
 
 // G[d][c'][c] (16 complex) = sum_n sum_a gout[c'](n)[al][a] conj((T_d in[c])(n)[be][a]), added to G.
 // One workgroup per (d, c', c); a fixed-order tree finishes the sum.
-template <int P>
 __global__ void __launch_bounds__(256) k_nn_wgrad(GeomDev g, int cin, int cout, const float2 *__restrict__ gout,
-                                                 const float2 *__restrict__ in, const typename Prec<P>::S2 *__restrict__ U,
+                                                 const float2 *__restrict__ in, const float2 *__restrict__ L,
                                                  float2 *__restrict__ G) {
     __shared__ float sm[32][257];
     const int d = blockIdx.x, co = blockIdx.y, ci = blockIdx.z;
-    const size_t chan = (size_t)g.V * 12;
     float acc[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) acc[k] = 0.f;
     for (long i = threadIdx.x; i < g.V; i += blockDim.x) {
         const int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+        int nb, ns;
+        float ph;
+        nn_neighbour(g, ib, s, d, nb, ns, ph);
         cx<float> t[12], go[12];
-        nn_transport<P>(t, in + ci * chan, g, U, ib, s, d);
-        load_spinor(go, gout + co * chan, g, ib, s);
+        nn_transport(t, in, cin, g, L, ib, s, d, ci, nb, ns);
+        load_chan(go, gout, cout, g, ib, s, co);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
 #pragma unroll
@@ -226,9 +245,9 @@ __global__ void k_nn_round(int n, const float *__restrict__ w, float *__restrict
     if (t < n) wq[t] = __bfloat162float(__float2bfloat16(w[t]));
 }
 
-// ---------------------------------------------------------------- MFMA layer
-// For a tile of 16 sites a layer is the real GEMM
-//   [out_r; out_i] (2M x 48) = [[W_r, -W_i], [W_i, W_r]] (2M x 2K) * [T_r; T_i] (2K x 48)
+// ---------------------------------------------------------------- MFMA layers
+// For a tile of NN_TILE sites a layer is the real GEMM
+//   [out_r; out_i] (2M x 3 NN_TILE) = [[W_r, -W_i], [W_i, W_r]] (2M x 2K) * [T_r; T_i] (2K x 3 NN_TILE)
 // with rows (re/im, c', alpha), M = 4 c_out; reduction index (re/im, d, c, beta), K = 36 c_in;
 // columns (site, colour).  The transported inputs T are written to LDS in BF16, the weights
 // are pre-arranged in MFMA fragment order (BF16), and v_mfma_f32_16x16x16bf16 accumulates in
@@ -261,160 +280,202 @@ __global__ void k_nn_afrag(int cin, int cout, const float2 *__restrict__ W, __hi
     A[t] = __float2bfloat16(v);
 }
 
-template <int P, int CIN, int COUT>
-__global__ void __launch_bounds__(256) k_nn_layer_mfma(GeomDev g, const float2 *__restrict__ in,
-                                                      float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
-                                                      const typename Prec<P>::S2 *__restrict__ U) {
-    constexpr int K = 36 * CIN, K2 = 2 * K, K2P = nn_k2p(CIN), M = 4 * COUT, M2P = nn_m2p(COUT);
-    constexpr int NS = 16, NC = 48, BPAD = K2P + 8, KS = K2P / 16, MT = M2P / 16, NT = 3;
+
+// Tile of NN_TILE sites of a layer workgroup.  Workgroups are dealt to the 8 XCDs in turn;
+// with a grid that is a multiple of 8, XCD x takes the x-th eighth of the tiles, and tiles
+// run through whole blocks in lexicographic block order, so that the neighbours a tile reads
+// (mostly in the same block or the next one) were fetched into the same L2.  ib < 0 marks a
+// workgroup past the last tile; n_valid sites of the tile exist (blocks need not hold a
+// multiple of NN_TILE sites).
+constexpr int NN_TILE = 32;
+
+__device__ __forceinline__ void nn_tile(const GeomDev &g, int &ib, int &s0, int &n_valid) {
+    const long vt = xcd_site_base(1);
+    const int tpb = (g.Vb + NN_TILE - 1) / NN_TILE;
+    const long bl = vt / tpb;
+    ib = bl < g.NB ? g.zord_blk[bl] : -1;
+    s0 = (int)(vt - bl * tpb) * NN_TILE;
+    n_valid = min(NN_TILE, g.Vb - s0);
+}
+
+unsigned nn_grid(const Ctx *c) {
+    const long tiles = (long)c->g.NB * ((c->g.Vb + NN_TILE - 1) / NN_TILE);
+    return (unsigned)((tiles + N_XCD - 1) / N_XCD * N_XCD);
+}
+
+// Output tiles of a wave: with four 16-row tiles (c_out = 8) wave w owns row tile w and all
+// column tiles, so it reads each A fragment once for all of them; with one row tile (c_out = 1)
+// the waves share it and take every fourth column tile.
+template <int MT, int NT> struct WaveTiles {
+    static_assert(MT == 4 || MT == 1, "four row tiles or one");
+    static constexpr int N = MT == 4 ? NT : (NT + 3) / 4;
+    __device__ static int mt(int wave) { return MT == 4 ? wave : 0; }
+    __device__ static int nt(int wave, int j) { return MT == 4 ? j : wave + 4 * j; }
+};
+
+// the tile of D (rows (re/im, c', alpha), columns (site, colour)) to the output activation
+template <int COUT>
+__device__ __forceinline__ void nn_store_tile(float2 *__restrict__ out, const GeomDev &g, int ib, int s0, int nv,
+                                              const float (*Dt)[3 * NN_TILE + 1]) {
+    constexpr int M = 4 * COUT;
+    if constexpr (COUT == 1) {
+        for (int w = threadIdx.x; w < NN_TILE * 12; w += blockDim.x) {
+            const int t = w % NN_TILE, comp = w / NN_TILE, r = comp / 3, col = 3 * t + comp % 3;
+            if (t < nv) out[((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
+        }
+    } else {
+        // the tile's records are contiguous: one coalesced sweep
+        float2 *o = out + ((size_t)ib * g.Vb + s0) * COUT * 12;
+        for (int w = threadIdx.x; w < nv * COUT * 12; w += blockDim.x) {
+            const int comp = w % 12, co = (w / 12) % COUT, t = w / (12 * COUT);
+            const int r = co * 4 + comp / 3, col = 3 * t + comp % 3;
+            o[w] = make_float2(Dt[r][col], Dt[M + r][col]);
+        }
+    }
+}
+
+// the transported spinor T (12 complex) of tile column group t, written as BF16 to rows
+// kre.. (real parts) and kim.. (imaginary parts) of the B tile: the four spins of one
+// (colour, re / im) are adjacent in k, one 8-byte store each
+template <int BPAD>
+__device__ __forceinline__ void nn_put_b(__hip_bfloat16 (*Bt)[BPAD], int t, int kre, int kim, const cx<float> T[12]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        bf16x4 re, im;
+#pragma unroll
+        for (int be = 0; be < 4; ++be) {
+            re.v[be] = __float2bfloat16(T[3 * be + a].r);
+            im.v[be] = __float2bfloat16(T[3 * be + a].i);
+        }
+        *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][kre]) = re;
+        *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][kim]) = im;
+    }
+}
+
+// One input channel (the first layer, and the adjoint of the last): the whole reduction
+// index (9 directions x 4 spins, re / im) is one LDS tile.
+template <int COUT>
+__global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 *__restrict__ in,
+                                                       float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
+                                                       const float2 *__restrict__ L) {
+    constexpr int K = 36, K2 = 2 * K, K2P = nn_k2p(1), M2P = nn_m2p(COUT);
+    constexpr int NS = NN_TILE, NC = 3 * NS, BPAD = K2P + 8, KS = K2P / 16, MT = M2P / 16, NT = NC / 16;
+    using WT = WaveTiles<MT, NT>;
     constexpr int B_BYTES = NC * BPAD * 2, D_BYTES = M2P * (NC + 1) * 4;
     __shared__ __attribute__((aligned(16))) unsigned char smem[B_BYTES > D_BYTES ? B_BYTES : D_BYTES];
     __shared__ int nb_blk[9][NS], nb_slot[9][NS];
-    __shared__ float nb_ph[9][NS];
     __hip_bfloat16 (*Bt)[BPAD] = reinterpret_cast<__hip_bfloat16 (*)[BPAD]>(smem);
     float (*Dt)[NC + 1] = reinterpret_cast<float (*)[NC + 1]>(smem);
     int ib, s0, nv;
     nn_tile(g, ib, s0, nv);
     if (ib < 0) return;
-    const size_t chan = (size_t)g.V * 12;
-    // 0. the neighbours of the tile's sites, once for all channels (missing sites of a short
-    // tile repeat the last one; their columns are not stored)
+    // 0. the neighbours of the tile's sites (missing sites of a short tile repeat the last
+    // one; their columns are not stored)
     for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
         const int t = w % NS, d = w / NS;
-        const int s = s0 + min(t, nv - 1);
-        nn_neighbour(g, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
+        float ph;
+        nn_neighbour(g, ib, s0 + min(t, nv - 1), d, nb_blk[d][t], nb_slot[d][t], ph);
     }
     __syncthreads();
-    // 1. transported inputs of the tile, BF16, column = 3 * site + colour
-    for (int w = threadIdx.x; w < NS * 9 * CIN; w += blockDim.x) {
-        const int t = w % NS, rest = w / NS, c = rest % CIN, d = rest / CIN;
-        const int s = s0 + min(t, nv - 1);
+    // 1. transported inputs, column = 3 * site + colour
+    for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
+        const int t = w % NS, d = w / NS;
         cx<float> T[12];
-        nn_transport_at<P>(T, in + c * chan, g, U, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
-        const int kb = (d * CIN + c) * 4;
-        // the four spins of one (colour, re / im) are adjacent in k: one 8-byte store each
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            bf16x4 re, im;
-#pragma unroll
-            for (int be = 0; be < 4; ++be) {
-                re.v[be] = __float2bfloat16(T[3 * be + a].r);
-                im.v[be] = __float2bfloat16(T[3 * be + a].i);
-            }
-            *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][kb]) = re;
-            *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][K + kb]) = im;
-        }
+        nn_transport(T, in, 1, g, L, ib, s0 + min(t, nv - 1), d, 0, nb_blk[d][t], nb_slot[d][t]);
+        nn_put_b<BPAD>(Bt, t, 4 * d, K + 4 * d, T);
     }
-    if constexpr (K2P > K2) {
-        for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
-            Bt[w / (K2P - K2)][K2 + w % (K2P - K2)] = __float2bfloat16(0.f);
-    }
+    for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
+        Bt[w / (K2P - K2)][K2 + w % (K2P - K2)] = __float2bfloat16(0.f);
     __syncthreads();
-    // 2. MFMA over the reduction index; each wave owns up to three 16x16 output tiles
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kq = 4 * (lane >> 4);
-    float4_t acc[3];
+    // 2. MFMA over the reduction index
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = 4 * (lane >> 4);
+    const short4_t *Ap = Afrag + (size_t)WT::mt(wave) * KS * 64 + lane;
+    float4_t acc[WT::N];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
-        const int tile = wave + 4 * j;
-        if (tile < MT * NT) {
-            const int mt = tile / NT, nt = tile % NT;
-            const short4_t *Ap = Afrag + (size_t)mt * KS * 64 + lane;
-            const int col = nt * 16 + (lane & 15);
-            for (int ks = 0; ks < KS; ++ks) {
-                const short4_t a = Ap[(size_t)ks * 64];
-                const short4_t b = *reinterpret_cast<const short4_t *>(&Bt[col][ks * 16 + kq]);
+    for (int j = 0; j < WT::N; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < KS; ++ks) {
+        const short4_t a = Ap[(size_t)ks * 64];
+#pragma unroll
+        for (int j = 0; j < WT::N; ++j) {
+            const int nt = WT::nt(wave, j);
+            if (nt < NT) {
+                const short4_t b = *reinterpret_cast<const short4_t *>(&Bt[nt * 16 + (lane & 15)][ks * 16 + kq]);
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
             }
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int tile = wave + 4 * j;
-        if (tile < MT * NT) {
-            const int mt = tile / NT, nt = tile % NT, col = nt * 16 + (lane & 15);
+    for (int j = 0; j < WT::N; ++j) {
+        const int nt = WT::nt(wave, j);
+        if (nt < NT)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Dt[mt * 16 + kq + q][col] = acc[j][q];
-        }
+            for (int q = 0; q < 4; ++q) Dt[WT::mt(wave) * 16 + kq + q][nt * 16 + (lane & 15)] = acc[j][q];
     }
     __syncthreads();
     // 3. complex outputs: out[c'](site)[alpha][a] = D[c' 4 + alpha][col] + i D[M + c' 4 + alpha][col]
-    for (int w = threadIdx.x; w < NS * COUT * 12; w += blockDim.x) {
-        const int t = w % NS, rest = w / NS, comp = rest % 12, co = rest / 12;
-        const int r = co * 4 + comp / 3, col = 3 * t + comp % 3;
-        if (t < nv) out[co * chan + ((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
-    }
+    nn_store_tile<COUT>(out, g, ib, s0, nv, Dt);
 }
 
-// The same layer for 8 input channels, with the reduction index taken in chunks of two
-// transport directions (128 rows: re and im of 2 directions x 8 channels x 4 spins).  A chunk
-// is one transport per thread, all loads in flight together, written to a 13 KB LDS tile
-// that the MFMA consumes before the next chunk; the accumulators stay in registers.  The
-// small LDS footprint lets about five workgroups share a CU.
-template <int P, int COUT>
+// Eight input channels: the reduction index is taken in chunks of two transport directions
+// (128 rows: re and im of 2 directions x 8 channels x 4 spins).  In a chunk each thread
+// transports one channel of one site along both directions; the eight threads of a site read
+// the neighbour's record as one contiguous 768-byte piece.  The MFMA consumes the chunk from
+// LDS before the next one; the accumulators stay in registers.
+template <int COUT>
 __global__ void __launch_bounds__(256) k_nn_layer8_mfma(GeomDev g, const float2 *__restrict__ in,
                                                        float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
-                                                       const typename Prec<P>::S2 *__restrict__ U) {
-    constexpr int CIN = 8, K = 36 * CIN, K2P = nn_k2p(CIN), M = 4 * COUT, M2P = nn_m2p(COUT);
-    constexpr int NS = 16, NC = 48, KS = K2P / 16, MT = M2P / 16, NT = 3;
+                                                       const float2 *__restrict__ L) {
+    constexpr int CIN = 8, K = 36 * CIN, K2P = nn_k2p(CIN), M2P = nn_m2p(COUT);
+    constexpr int NS = NN_TILE, NC = 3 * NS, KS = K2P / 16, MT = M2P / 16, NT = NC / 16;
     constexpr int CR = 128, BPAD = CR + 8;  // rows of a chunk (local: re 0..63, im 64..127)
     static_assert(K2P == 2 * K && K % 16 == 0, "8 input channels fill whole k-tiles");
-    __shared__ __attribute__((aligned(16))) __hip_bfloat16 Bt[NC][BPAD];
-    __shared__ float Dt[M2P][NC + 1];
+    static_assert(NS * CIN == 256, "one (site, channel) per thread");
+    using WT = WaveTiles<MT, NT>;
+    constexpr int B_BYTES = NC * BPAD * 2, D_BYTES = M2P * (NC + 1) * 4;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[B_BYTES > D_BYTES ? B_BYTES : D_BYTES];
     __shared__ int nb_blk[9][NS], nb_slot[9][NS];
-    __shared__ float nb_ph[9][NS];
+    __hip_bfloat16 (*Bt)[BPAD] = reinterpret_cast<__hip_bfloat16 (*)[BPAD]>(smem);
+    float (*Dt)[NC + 1] = reinterpret_cast<float (*)[NC + 1]>(smem);
     int ib, s0, nv;
     nn_tile(g, ib, s0, nv);
     if (ib < 0) return;
-    const size_t chan = (size_t)g.V * 12;
     for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
         const int t = w % NS, d = w / NS;
-        const int s = s0 + min(t, nv - 1);
-        nn_neighbour(g, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
+        float ph;
+        nn_neighbour(g, ib, s0 + min(t, nv - 1), d, nb_blk[d][t], nb_slot[d][t], ph);
     }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kq = 4 * (lane >> 4);
-    float4_t acc[3];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = 4 * (lane >> 4);
+    const int c = threadIdx.x % CIN, t = threadIdx.x / CIN, s = s0 + min(t, nv - 1);
+    const short4_t *Ap = Afrag + (size_t)WT::mt(wave) * KS * 64 + lane;
+    float4_t acc[WT::N];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WT::N; ++j) acc[j] = float4_t{0.f, 0.f, 0.f, 0.f};
     __syncthreads();
+    // unrolled, so that both transports of a chunk have their loads in flight together
+#pragma unroll
     for (int d0 = 0; d0 < 9; d0 += 2) {
         const int nd = d0 == 8 ? 1 : 2;
-        // transports of directions d0, d0 + 1 for all channels: one per thread
-        for (int w = threadIdx.x; w < NS * CIN * nd; w += blockDim.x) {
-            const int t = w % NS, c = (w / NS) % CIN, dd = w / (NS * CIN), d = d0 + dd;
-            const int s = s0 + min(t, nv - 1);
-            cx<float> T[12];
-            nn_transport_at<P>(T, in + c * chan, g, U, ib, s, d, nb_blk[d][t], nb_slot[d][t], nb_ph[d][t]);
-            const int lr = (dd * CIN + c) * 4;
+        cx<float> T[2][12];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                bf16x4 re, im;
+        for (int dd = 0; dd < 2; ++dd)
+            if (dd < nd) nn_transport(T[dd], in, CIN, g, L, ib, s, d0 + dd, c, nb_blk[d0 + dd][t], nb_slot[d0 + dd][t]);
 #pragma unroll
-                for (int be = 0; be < 4; ++be) {
-                    re.v[be] = __float2bfloat16(T[3 * be + a].r);
-                    im.v[be] = __float2bfloat16(T[3 * be + a].i);
-                }
-                *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][lr]) = re;
-                *reinterpret_cast<bf16x4 *>(&Bt[3 * t + a][64 + lr]) = im;
-            }
-        }
+        for (int dd = 0; dd < 2; ++dd)
+            if (dd < nd) nn_put_b<BPAD>(Bt, t, (dd * CIN + c) * 4, 64 + (dd * CIN + c) * 4, T[dd]);
         __syncthreads();
         // k-tiles of the chunk: re rows of d0 (global tile 2 d0 + lt), im rows (K / 16 + 2 d0 + lt)
-        const int ntile = 2 * nd;
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int tile = wave + 4 * j;
-            if (tile < MT * NT) {
-                const int mt = tile / NT, nt = tile % NT, col = nt * 16 + (lane & 15);
-                const short4_t *Ap = Afrag + (size_t)mt * KS * 64 + lane;
-                for (int lt = 0; lt < ntile; ++lt) {
-                    const short4_t a_re = Ap[(size_t)(2 * d0 + lt) * 64];
+        for (int lt = 0; lt < 2 * nd; ++lt) {
+            const short4_t a_re = Ap[(size_t)(2 * d0 + lt) * 64];
+            const short4_t a_im = Ap[(size_t)(K / 16 + 2 * d0 + lt) * 64];
+#pragma unroll
+            for (int j = 0; j < WT::N; ++j) {
+                const int nt = WT::nt(wave, j);
+                if (nt < NT) {
+                    const int col = nt * 16 + (lane & 15);
                     const short4_t b_re = *reinterpret_cast<const short4_t *>(&Bt[col][lt * 16 + kq]);
                     acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_re, b_re, acc[j], 0, 0, 0);
-                    const short4_t a_im = Ap[(size_t)(K / 16 + 2 * d0 + lt) * 64];
                     const short4_t b_im = *reinterpret_cast<const short4_t *>(&Bt[col][64 + lt * 16 + kq]);
                     acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a_im, b_im, acc[j], 0, 0, 0);
                 }
@@ -423,48 +484,29 @@ __global__ void __launch_bounds__(256) k_nn_layer8_mfma(GeomDev g, const float2 
         __syncthreads();
     }
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int tile = wave + 4 * j;
-        if (tile < MT * NT) {
-            const int mt = tile / NT, nt = tile % NT, col = nt * 16 + (lane & 15);
+    for (int j = 0; j < WT::N; ++j) {
+        const int nt = WT::nt(wave, j);
+        if (nt < NT)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Dt[mt * 16 + kq + q][col] = acc[j][q];
-        }
+            for (int q = 0; q < 4; ++q) Dt[WT::mt(wave) * 16 + kq + q][nt * 16 + (lane & 15)] = acc[j][q];
     }
     __syncthreads();
-    for (int w = threadIdx.x; w < NS * COUT * 12; w += blockDim.x) {
-        const int t = w % NS, rest = w / NS, comp = rest % 12, co = rest / 12;
-        const int r = co * 4 + comp / 3, col = 3 * t + comp % 3;
-        if (t < nv) out[co * chan + ((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
-    }
+    nn_store_tile<COUT>(out, g, ib, s0, nv, Dt);
 }
 
 // ---------------------------------------------------------------- launchers
-template <int P>
-static void nn_layer_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {
-    using S2 = typename Prec<P>::S2;
-    dim3 grid((unsigned)((c->V + 255) / 256), (unsigned)cout);
-    const S2 *U = (const S2 *)c->Uin;
-    if (cin == 1 && cout == 8)
-        k_nn_layer<P, 1, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
-    else if (cin == 8 && cout == 8)
-        k_nn_layer<P, 8, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
-    else if (cin == 8 && cout == 1)
-        k_nn_layer<P, 8, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, U);
-}
+size_t nn_link_elems(const Ctx *c) { return (size_t)c->V * 72; }
 
-template <int P>
-static void nn_layer_mfma_p(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *Af) {
-    using S2 = typename Prec<P>::S2;
-    const unsigned grid = nn_grid(c);
-    const S2 *U = (const S2 *)c->Uin;
-    const short4_t *A = (const short4_t *)Af;
-    if (cin == 1 && cout == 8)
-        k_nn_layer_mfma<P, 1, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
-    else if (cin == 8 && cout == 8)
-        k_nn_layer8_mfma<P, 8><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
-    else if (cin == 8 && cout == 1)
-        k_nn_layer8_mfma<P, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, U);
+void launch_nn_links(Ctx *c) {
+    const long n = (long)c->V * 8;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    switch (c->prm.prec_inner) {
+    case SAPQ_FP32: k_nn_links<SAPQ_FP32><<<grid, 256, 0, c->stream>>>(c->g, (const float2 *)c->Uin, c->nn_L); break;
+    case SAPQ_FP16: k_nn_links<SAPQ_FP16><<<grid, 256, 0, c->stream>>>(c->g, (const __half2 *)c->Uin, c->nn_L); break;
+    case SAPQ_BF16:
+        k_nn_links<SAPQ_BF16><<<grid, 256, 0, c->stream>>>(c->g, (const __hip_bfloat162 *)c->Uin, c->nn_L);
+        break;
+    }
 }
 
 size_t nn_afrag_elems(int cin, int cout) { return (size_t)nn_m2p(cout) * nn_k2p(cin); }
@@ -474,35 +516,30 @@ void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A) {
     k_nn_afrag<<<(n + 255) / 256, 256, 0, c->stream>>>(cin, cout, W, (__hip_bfloat16 *)A);
 }
 
-void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *A) {
-    switch (c->prm.prec_inner) {
-    case SAPQ_FP32: nn_layer_mfma_p<SAPQ_FP32>(c, cin, cout, in, out, A); break;
-    case SAPQ_FP16: nn_layer_mfma_p<SAPQ_FP16>(c, cin, cout, in, out, A); break;
-    case SAPQ_BF16: nn_layer_mfma_p<SAPQ_BF16>(c, cin, cout, in, out, A); break;
-    }
+void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *Af) {
+    const unsigned grid = nn_grid(c);
+    const short4_t *A = (const short4_t *)Af;
+    if (cin == 1 && cout == NN_C)
+        k_nn_layer1_mfma<NN_C><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
+    else if (cin == NN_C && cout == NN_C)
+        k_nn_layer8_mfma<NN_C><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
+    else if (cin == NN_C && cout == 1)
+        k_nn_layer8_mfma<1><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
 }
 
 void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {
-    switch (c->prm.prec_inner) {
-    case SAPQ_FP32: nn_layer_p<SAPQ_FP32>(c, cin, cout, in, out, W); break;
-    case SAPQ_FP16: nn_layer_p<SAPQ_FP16>(c, cin, cout, in, out, W); break;
-    case SAPQ_BF16: nn_layer_p<SAPQ_BF16>(c, cin, cout, in, out, W); break;
-    }
+    dim3 grid((unsigned)((c->V + 255) / 256), (unsigned)cout);
+    if (cin == 1 && cout == NN_C)
+        k_nn_layer<1, NN_C><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, c->nn_L);
+    else if (cin == NN_C && cout == NN_C)
+        k_nn_layer<NN_C, NN_C><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, c->nn_L);
+    else if (cin == NN_C && cout == 1)
+        k_nn_layer<NN_C, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, c->nn_L);
 }
 
 void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2 *in, float2 *G) {
     dim3 grid(9, (unsigned)cout, (unsigned)cin);
-    switch (c->prm.prec_inner) {
-    case SAPQ_FP32:
-        k_nn_wgrad<SAPQ_FP32><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, (const float2 *)c->Uin, G);
-        break;
-    case SAPQ_FP16:
-        k_nn_wgrad<SAPQ_FP16><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, (const __half2 *)c->Uin, G);
-        break;
-    case SAPQ_BF16:
-        k_nn_wgrad<SAPQ_BF16><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, (const __hip_bfloat162 *)c->Uin, G);
-        break;
-    }
+    k_nn_wgrad<<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, c->nn_L, G);
 }
 
 void launch_nn_adjoint_weights(Ctx *c, int cin, int cout, const float2 *W, float2 *Wt) {

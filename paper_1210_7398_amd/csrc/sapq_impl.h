@@ -43,6 +43,7 @@ struct GeomDev {
     const int *slot_lex;    // [Vb] block-local lexicographic index of each slot
     const int *blk_lex;     // [NB] lexicographic block index of each internal block id
     const int *lex_blk;     // [NB] internal block id of each lexicographic block index
+    const int *zord_blk;    // [NB] internal block ids in Z (Morton) order of the block coordinates
     int B[4];
     int nbk[4];             // blocks per direction
 };
@@ -155,6 +156,7 @@ void launch_pack_spinor(Ctx *c, int prec, void *dst, const double *src, double s
 void launch_unpack_spinor(Ctx *c, int prec, double *dst, const void *src, double scale);
 int launch_pack_links(Ctx *c, const double *U, double *max_dev);
 void launch_pack_clover(Ctx *c, const double *F);
+bool launch_permute_fields(Ctx *c, const int *perm);
 void launch_dslash(Ctx *c, int prec, void *out, const void *in);
 void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y);
 void launch_sap_face(Ctx *c, int colour, void *r, const void *x);
@@ -211,6 +213,7 @@ struct Ctx {
     size_t nvec;  // 12 V complex entries
     // fields
     double2 *U64, *F64;
+    int *slot_perm;   // [Vb] staging of a slot re-ordering (sub-block change)
     void *Uin, *Fin;  // inner storage precision
     bool have_U, have_F;
     // FP64 work vectors (internal layout)
@@ -237,6 +240,7 @@ struct Ctx {
     void *i_z, *i_rp;                    // N r and r - D N r in inner storage
     void *nn_afrag[3];                   // BF16 MFMA fragments of the three layers' weights
     void *nn_afrag_t;                    // fragments of an adjoint layer
+    float2 *nn_L;                        // transport links [V][8][9] of the layers (FP32)
 };
 
 constexpr int NN_C = SAPQ_NN_CHANNELS;
@@ -251,6 +255,8 @@ void launch_nn_adjoint_weights(Ctx *c, int cin, int cout, const float2 *W, float
 void launch_nn_adam(Ctx *c, int n, float *w, const float *grad, float gscale, float *m, float *v, float lr, int t, float *wq);
 void launch_nn_round(Ctx *c, int n, const float *w, float *wq);
 size_t nn_afrag_elems(int cin, int cout);
+size_t nn_link_elems(const Ctx *c);
+void launch_nn_links(Ctx *c);
 void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A);
 void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *A);
 void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src);

@@ -20,7 +20,7 @@ constexpr int MAX_PLANES = 64;
 struct HostTables {
     int Vb = 0, NB = 0, nplanes = 0, max_plane = 0;
     int nbk[4];
-    std::vector<int> loc_nbr, blk_nbr, plane_start, slot_lex, blk_lex, lex_blk;
+    std::vector<int> loc_nbr, blk_nbr, plane_start, slot_lex, blk_lex, lex_blk, zord_blk;
     std::vector<int> nbr16;  // packed forward/backward slots per direction (stored as unsigned)
 };
 
@@ -99,6 +99,22 @@ inline void build_tables(const sapq_geom *G, HostTables &T) {
     std::vector<int> ib_of(NB);
     for (int i = 0; i < NB; ++i) ib_of[T.blk_lex[i]] = i;
     T.lex_blk = ib_of;
+    // blocks in Z (Morton) order of their block coordinates: each aligned group of 2^k blocks
+    // per dimension is contiguous in it, so a run of it is a compact piece of the lattice
+    {
+        std::vector<std::pair<unsigned long long, int>> key(NB);
+        for (int b = 0; b < NB; ++b) {
+            int c[4], r = b;
+            for (int m = 0; m < 4; ++m) { c[m] = r % T.nbk[m]; r /= T.nbk[m]; }
+            unsigned long long k = 0;
+            for (int bit = 0; bit < 15; ++bit)
+                for (int m = 0; m < 4; ++m) k |= (unsigned long long)((c[m] >> bit) & 1) << (4 * bit + m);
+            key[b] = {k, b};
+        }
+        std::sort(key.begin(), key.end());
+        T.zord_blk.resize(NB);
+        for (int i = 0; i < NB; ++i) T.zord_blk[i] = ib_of[key[i].second];
+    }
     T.blk_nbr.resize(8 * NB);
     for (int i = 0; i < NB; ++i) {
         int c[4], r = T.blk_lex[i];

@@ -116,3 +116,48 @@ def test_autotune_picks_a_valid_subblock_and_caches(torch_cuda, orc, tmp_path):
     y_w, _ = orc.msap(L, B, S, U, F, orc.params(kappa), v)
     y, _ = s.sap_precondition(to_dev(v))
     assert relerr(to_host(y), y_w) < 2e-5
+
+
+def test_subblock_change_relays_out_the_fields(torch_cuda, orc, tmp_path):
+    """A tuning-cache hit with a sub-block shape other than the context's changes the slot
+    order inside every block; the packed links and clover field (and the learned stage's link
+    table) must follow it.  Checked after the change: the solve against the oracle's operator,
+    M_SAP against the oracle's M_SAP with the new ll order, the network against the oracle."""
+    import json
+
+    from paper_1210_7398_amd import sapq
+
+    torch = torch_cuda
+    L, B, kappa = (8, 8, 8, 8), (4, 4, 4, 4), 0.125
+    U, F = _field(L, 0.25, 36, kappa)
+    s = sapq.Solver(L, B, (2, 2, 2, 2), kappa)
+    s.load_gauge(to_dev(U))
+    s.load_clover(to_dev(F))
+    cache = tmp_path / "tune.jsonl"
+    first = s.autotune(str(cache))
+    s.close()
+    entry = json.loads(cache.read_text().splitlines()[0])
+    S_new = (4, 2, 2, 4) if tuple(first) != (4, 2, 2, 4) else (2, 4, 4, 2)
+    entry["subblock"] = list(S_new)
+    cache.write_text(json.dumps(entry) + "\n")
+
+    s = sapq.Solver(L, B, (2, 2, 2, 2), kappa, nn=True, nn_fp32=True)
+    s.load_gauge(to_dev(U))
+    s.load_clover(to_dev(F))
+    assert s.autotune(str(cache)) == S_new
+    b = synth.gaussian_spinor(L, 37)
+    x, st = s.solve(to_dev(b), tol=1e-10)
+    assert relerr(orc.dslash(L, U, F, kappa, to_host(x)), b) <= 1e-10
+    v = synth.gaussian_spinor(L, 38)
+    y_w, _ = orc.msap(L, B, S_new, U, F, orc.params(kappa), v)
+    y, _ = s.sap_precondition(to_dev(v))
+    assert relerr(to_host(y), y_w) < 2e-5
+    rng = np.random.default_rng(39)
+    w = (0.15 * rng.normal(size=orc.nn_param_count())).astype(np.float32)
+    w = w.view(np.uint32) & np.uint32(0xFFFF0000)  # BF16-exact weights (truncated)
+    w = w.view(np.float32)
+    s.nn_set_weights(torch.from_numpy(w).cuda())
+    r = synth.gaussian_spinor(L, 40)
+    z_w, _ = orc.nn_forward(L, U, orc.nn_unflatten(w), r)
+    assert relerr(to_host(s.nn_forward(to_dev(r))), z_w) < 1e-5
+    s.close()
