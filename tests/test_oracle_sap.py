@@ -199,3 +199,76 @@ def test_msap_converges_to_inverse(orc):
         errs.append(np.linalg.norm(y.reshape(-1) - xs) / np.linalg.norm(xs))
     assert all(errs[i + 1] < 0.7 * errs[i] for i in range(len(errs) - 1)), errs
     assert errs[-1] < 1e-6, errs
+
+
+EO = (0, 0, 0, 0)  # sub-block shape that selects the even-odd site ordering
+
+
+def _parity_order(B, seed=None):
+    """Block-local lexicographic indices: all even-parity sites, then all odd ones (shuffled
+    inside each parity when a seed is given)."""
+    lc = _local_coords(B)
+    par = lc.sum(axis=1) % 2
+    tie = np.arange(len(lc)) if seed is None else np.random.default_rng(seed).permutation(len(lc))
+    return np.lexsort((tie, par)).astype(np.int32)
+
+
+@pytest.mark.parametrize("L,B", [((8, 8, 4, 4), (4, 4, 2, 2)), ((8, 4, 4, 8), (4, 2, 2, 4))])
+@pytest.mark.parametrize("omega", [1.0, 1.3])
+def test_even_odd_ssor_equals_dense_ssor_in_parity_order(orc, L, B, omega):
+    """The even-odd site ordering (the alternative the paper measures the ll order against,
+    Sec. 3.2) is textbook SSOR on the block matrix with the even sites ordered first."""
+    kappa = 0.12
+    U, F = _fields(L, kappa, 41)
+    prm = orc.params(kappa, omega=omega, n_ssor=3)
+    Dense, loc, bid = H.dense_block_diagonal(lambda p: orc.dslash_part(L, B, U, F, kappa, p, 1), L, B)
+    order = _parity_order(B)
+    assert np.array_equal(orc.ll_order(B, EO), order)
+    perm = (order[:, None] * 12 + np.arange(12)[None, :]).reshape(-1)
+    v = synth.gaussian_spinor(L, 42)
+    col = H.block_colour(L, B)
+    x = orc.ssor(L, B, EO, U, F, prm, 1, v)
+    for blk in np.unique(bid[col == 1])[:3]:
+        sites = np.where(bid == blk)[0]
+        sites = sites[np.argsort(loc[sites])]
+        xd = _dense_ssor(Dense[blk][np.ix_(perm, perm)], v[sites].reshape(-1)[perm], omega, 3)
+        assert np.abs(x[sites].reshape(-1)[perm] - xd).max() < 1e-13 * np.abs(xd).max()
+
+
+def test_even_odd_ssor_first_half_sweep_closed_form(orc):
+    """With omega = 1 and one SSOR step from x = 0 on D_b = 1 - K (K = kappa F H inside the
+    block), the forward sweep leaves the even sites at v (no earlier neighbours) and the odd
+    ones at v + K x_even; the backward sweep repeats the odd update and then gives the even
+    sites v + K x_odd."""
+    L, B, kappa = (8, 4, 4, 4), (4, 2, 2, 2), 0.12
+    U, F = _fields(L, kappa, 43)
+    v = synth.gaussian_spinor(L, 44)
+    x = orc.ssor(L, B, EO, U, F, orc.params(kappa, n_ssor=1), 0, v)
+    Dense, loc, bid = H.dense_block_diagonal(lambda p: orc.dslash_part(L, B, U, F, kappa, p, 1), L, B)
+    col = H.block_colour(L, B)
+    par = _local_coords(B).sum(axis=1) % 2
+    for blk in np.unique(bid[col == 0])[:3]:
+        sites = np.where(bid == blk)[0]
+        sites = sites[np.argsort(loc[sites])]
+        n = len(sites)
+        K = (np.eye(n * 12) - Dense[blk]).reshape(n, 12, n, 12)
+        vb = v[sites].reshape(n, 12)
+        e, o = par == 0, par == 1
+        xo = vb[o] + np.einsum("iajb,jb->ia", K[np.ix_(o, np.arange(12), e, np.arange(12))], vb[e])
+        xe = vb[e] + np.einsum("iajb,jb->ia", K[np.ix_(e, np.arange(12), o, np.arange(12))], xo)
+        xb = x[sites].reshape(n, 12)
+        assert np.abs(xb[o] - xo).max() < 1e-13 * np.abs(xo).max()
+        assert np.abs(xb[e] - xe).max() < 1e-13 * np.abs(xe).max()
+
+
+def test_even_odd_order_invariance_and_difference(orc):
+    """Any order inside a parity gives bit-identical SSOR results; the even-odd ordering is a
+    different preconditioner from the ll ordering with 2^4 sub-blocks."""
+    L, B, kappa = (8, 8, 4, 4), (4, 4, 2, 2), 0.125
+    U, F = _fields(L, kappa, 45)
+    prm = orc.params(kappa, n_ssor=2)
+    v = synth.gaussian_spinor(L, 46)
+    ref = orc.ssor(L, B, EO, U, F, prm, 0, v)
+    for seed in (1, 2):
+        assert np.array_equal(ref, orc.ssor(L, B, EO, U, F, prm, 0, v, order=_parity_order(B, seed)))
+    assert not np.allclose(ref, orc.ssor(L, B, (2, 2, 2, 2), U, F, prm, 0, v))
