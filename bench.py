@@ -140,10 +140,12 @@ def _solve_stats(s, bd, steps):
 
 
 # SAP block and sub-block shapes of the block-shape study at 24^3x48 (sub-block = block is the
-# natural-order SSOR, the paper's reference point for the ll ordering)
+# natural-order SSOR; sub-block (0, 0, 0, 0) the even-odd site order that the paper measures
+# the ll ordering against)
 BLOCK_SHAPES = [((6, 6, 6, 12), (3, 3, 3, 6)), ((6, 6, 6, 12), (2, 2, 2, 4)), ((6, 6, 6, 12), (3, 3, 3, 3)),
                 ((6, 6, 6, 12), (6, 6, 6, 12)), ((6, 6, 6, 6), (3, 3, 3, 3)), ((6, 6, 6, 6), (2, 2, 2, 2)),
-                ((6, 6, 6, 6), (6, 6, 6, 6)), ((4, 4, 4, 4), (2, 2, 2, 2)), ((4, 4, 4, 4), (4, 4, 4, 4))]
+                ((6, 6, 6, 6), (6, 6, 6, 6)), ((6, 6, 6, 6), (0, 0, 0, 0)), ((4, 4, 4, 4), (2, 2, 2, 2)),
+                ((4, 4, 4, 4), (4, 4, 4, 4)), ((4, 4, 4, 4), (0, 0, 0, 0))]
 
 
 def blocks_study(args):

@@ -60,12 +60,15 @@ typedef enum { SAPQ_OUTER_FBICGSTAB = 0, SAPQ_OUTER_DEFECT = 1 } sapq_outer;
 /*
  * Geometry.  L: lattice extents (x,y,z,t).  block: SAP block extents; the blocks
  * are coloured like a checkerboard, E = colour 0 holds the origin (eq. 2.3).
- * subblock: sub-block extents of the locally-lexicographic ordering (section 3).
+ * subblock: sub-block extents of the locally-lexicographic ordering (section 3), or
+ * {0, 0, 0, 0} for the even-odd site ordering that section 3 compares it against: the
+ * sites of a block with an even sum of block-local coordinates first, then the odd ones
+ * (the SSOR then has two hyperplanes, the two parities).
  * bc_sign: +1 periodic, -1 antiperiodic fermion boundary per direction; the sign
  * multiplies the hops that cross the lattice boundary.
  * Constraints (else SAPQ_ESHAPE): block[mu] divides L[mu] and L[mu]/block[mu] is
  * even and >= 2 (so neighbouring blocks always have opposite colours);
- * subblock[mu] divides block[mu] and is >= 2 (so sites at the same sub-block-local
+ * unless all are 0, subblock[mu] divides block[mu] and is >= 2 (so sites at the same sub-block-local
  * position never couple); at most 1024 sites in one hyperplane of a block.
  */
 typedef struct {

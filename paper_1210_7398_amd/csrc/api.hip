@@ -64,14 +64,15 @@ void prof_harvest(Ctx *c) {
 }
 
 static int check_geom(const sapq_geom *g, std::string &why) {
+    const bool eo = eo_order(g);  // all-zero sub-block: even-odd site order
     for (int m = 0; m < 4; ++m) {
         int L = g->L[m], B = g->block[m], S = g->subblock[m];
-        if (L <= 0 || B <= 0 || S <= 0) { why = "non-positive extent"; return SAPQ_ESHAPE; }
+        if (L <= 0 || B <= 0 || (S <= 0 && !eo)) { why = "non-positive extent"; return SAPQ_ESHAPE; }
         if (L % B) { why = "block does not divide the lattice in direction " + std::to_string(m); return SAPQ_ESHAPE; }
         int nb = L / B;
         if (nb < 2 || nb % 2) { why = "blocks per direction must be even and >= 2 (direction " + std::to_string(m) + ")"; return SAPQ_ESHAPE; }
-        if (B % S) { why = "sub-block does not divide the block in direction " + std::to_string(m); return SAPQ_ESHAPE; }
-        if (S < 2) { why = "sub-block extent must be >= 2 (direction " + std::to_string(m) + ")"; return SAPQ_ESHAPE; }
+        if (!eo && B % S) { why = "sub-block does not divide the block in direction " + std::to_string(m); return SAPQ_ESHAPE; }
+        if (!eo && S < 2) { why = "sub-block extent must be >= 2 (direction " + std::to_string(m) + ")"; return SAPQ_ESHAPE; }
         if (g->bc_sign[m] != 1 && g->bc_sign[m] != -1) { why = "bc_sign must be +1 or -1"; return SAPQ_EINVAL; }
     }
     return SAPQ_OK;

@@ -24,21 +24,35 @@ struct HostTables {
     std::vector<int> nbr16;  // packed forward/backward slots per direction (stored as unsigned)
 };
 
-// Slots sorted by hyperplane h = sum_mu (x_mu mod S_mu); inside a plane first by the half
-// of the block in t that the site lies in (when the sub-block layers in t split evenly),
-// then by the ll key.  The order inside a hyperplane is free (its sites are independent);
-// this one gives each half of the block one contiguous slot range per hyperplane.
+// An all-zero sub-block shape asks for the even-odd site order instead of the ll order:
+// first the sites of the block whose block-local coordinates have an even sum, then the odd
+// ones, each in lexicographic order.  This is the ordering the paper compares the ll order
+// against (Sec. 3.2); its two hyperplanes are the two parities.
+inline bool eo_order(const sapq_geom *G) {
+    return G->subblock[0] == 0 && G->subblock[1] == 0 && G->subblock[2] == 0 && G->subblock[3] == 0;
+}
+
+// Slots sorted by hyperplane h = sum_mu (x_mu mod S_mu) (the site parity for the even-odd
+// order); inside a plane first by the half of the block in t that the site lies in (when
+// the sub-block layers in t split evenly), then by the ll key.  The order inside a
+// hyperplane is free (its sites are independent); this one gives each half of the block one
+// contiguous slot range per hyperplane.
 inline void build_tables(const sapq_geom *G, HostTables &T) {
     const int *B = G->block, *S = G->subblock;
+    const bool eo = eo_order(G);
     int Vb = B[0] * B[1] * B[2] * B[3];
     int ns[4];
-    for (int m = 0; m < 4; ++m) { ns[m] = B[m] / S[m]; T.nbk[m] = G->L[m] / B[m]; }
+    for (int m = 0; m < 4; ++m) { ns[m] = eo ? 1 : B[m] / S[m]; T.nbk[m] = G->L[m] / B[m]; }
     int Nsub = ns[0] * ns[1] * ns[2] * ns[3];
     struct Key { int h, half; long ll; int lex; };
     std::vector<Key> keys(Vb);
     for (int l = 0; l < Vb; ++l) {
         int c[4], r = l;
         for (int m = 0; m < 4; ++m) { c[m] = r % B[m]; r /= B[m]; }
+        if (eo) {
+            keys[l] = {(c[0] + c[1] + c[2] + c[3]) & 1, B[3] % 2 == 0 ? c[3] * 2 / B[3] : 0, l, l};
+            continue;
+        }
         int h = 0; long pos = 0, sub = 0, pm = 1, sm = 1;
         for (int m = 0; m < 4; ++m) {
             h += c[m] % S[m];
@@ -143,7 +157,9 @@ struct PartTables {
 
 inline bool build_parts(const sapq_geom *G, const HostTables &T, int NP, PartTables &P) {
     const int *B = G->block, *S = G->subblock;
-    const int Vb = T.Vb, nst = B[3] / S[3], H = T.nplanes;
+    // the split of a block in two is written for the ll order's sub-block layers in t
+    if (eo_order(G) && NP != 1) return false;
+    const int Vb = T.Vb, nst = eo_order(G) ? 1 : B[3] / S[3], H = T.nplanes;
     if (NP < 1 || NP > 2 || nst % NP) return false;
     const int Vp = Vb / NP, slab = B[0] * B[1] * B[2];
     std::vector<int> part_of(Vb), loc_of(Vb), plane_of(Vb), cnt(NP, 0);
@@ -155,7 +171,7 @@ inline bool build_parts(const sapq_geom *G, const HostTables &T, int NP, PartTab
     P.gslot.assign((size_t)NP * Vp, 0);
     for (int s = 0; s < Vb; ++s) {
         const int t = T.slot_lex[s] / slab;
-        const int p = (t / S[3]) * NP / nst;
+        const int p = eo_order(G) ? 0 : (t / S[3]) * NP / nst;
         if (cnt[p] >= Vp) return false;
         part_of[s] = p;
         loc_of[s] = cnt[p];

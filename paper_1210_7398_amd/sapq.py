@@ -264,9 +264,31 @@ class Solver:
         return loss.value
 
 
+# Work memory of solve_batch, kept per device between calls and grown when a call needs
+# more: a fresh multi-GB allocation per call (after the caching allocator has returned its
+# memory) can be mapped in a way that slows every kernel of the solve, and the batched
+# solver does not need the arena cleared.  release_batch_arena() hands it back.
+_BATCH_ARENA = {}
+
+
+def _batch_arena(device, nbytes):
+    a = _BATCH_ARENA.get(device)
+    if a is None or a.numel() < nbytes:
+        _BATCH_ARENA.pop(device, None)
+        a = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _BATCH_ARENA[device] = a
+    return a
+
+
+def release_batch_arena():
+    """Drop the work memory that solve_batch keeps between calls."""
+    _BATCH_ARENA.clear()
+
+
 def solve_batch(solvers, sources, tol=1e-10, check=True):
     """Solve every source of every solver's field together (sapq_solve_batch).  sources[i]:
-    complex128 GPU tensor [nrhs_i, V_i, 4, 3].  Returns (solutions, per-source stats dicts)."""
+    complex128 GPU tensor [nrhs_i, V_i, 4, 3].  Returns (solutions, per-source stats dicts).
+    The work memory stays allocated for the next call (release_batch_arena frees it)."""
     n = len(solvers)
     ctxs = (_P * n)(*[s.h for s in solvers])
     nrhs = (ctypes.c_int * n)(*[int(b.shape[0]) for b in sources])
@@ -279,7 +301,7 @@ def solve_batch(solvers, sources, tol=1e-10, check=True):
     nbytes = lib().sapq_batch_arena_bytes(ctxs, n, nrhs)
     if nbytes == 0:
         raise SapqError(-1, "batch not allowed (shapes, precisions or block size)")
-    arena = torch.empty(nbytes, dtype=torch.uint8, device=solvers[0].device)
+    arena = _batch_arena(solvers[0].device, nbytes)
     total = sum(int(b.shape[0]) for b in sources)
     st = (Stats * total)()
     rc = lib().sapq_solve_batch(ctxs, n, nrhs, xp, bp, tol, ctypes.c_void_p(arena.data_ptr()), nbytes, st)

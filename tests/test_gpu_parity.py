@@ -174,8 +174,8 @@ KERNELS = {"four-lane": "0", "two-lane": "1", "two-lane split": "2"}
 def _variant_applies(name, kernel):
     L, B, S, kappa, eps, bc = GEOMS[name]
     Vb = int(np.prod(B))
-    if kernel.startswith("two-lane split"):
-        return (B[3] // S[3]) % 2 == 0 and 96 * (Vb // 2 + Vb // B[3] + 1) <= 160 * 1024
+    if kernel.startswith("two-lane split"):  # the split follows the ll order's sub-block layers
+        return S[3] > 0 and (B[3] // S[3]) % 2 == 0 and 96 * (Vb // 2 + Vb // B[3] + 1) <= 160 * 1024
     if kernel.startswith("two-lane"):  # the whole iterate and a zero slot in LDS
         return 96 * (Vb + 1) <= 160 * 1024
     return True
