@@ -242,6 +242,12 @@ int sapq_nn_set_weights(sapq_ctx *ctx, const float *w);
 /* Copy the FP32 master weights out (device float array). */
 int sapq_nn_get_weights(sapq_ctx *ctx, float *w);
 
+/* Copy the training state of src (FP32 master weights and both Adam moments) into dst, so
+ * that training can go on with dst's field without restarting Adam; enables the stage in dst.
+ * Both contexts need SAPQ_FLAG_NN and set weights in src (else SAPQ_ESTATE) and must be on
+ * one device.  src's stream is synchronized first; the copy runs on dst's stream. */
+int sapq_nn_copy_state(sapq_ctx *dst, sapq_ctx *src);
+
 /* out = N in (spinor layout, FP64 at the boundary, FP32 inside). */
 int sapq_nn_forward(sapq_ctx *ctx, double *out, const double *in);
 

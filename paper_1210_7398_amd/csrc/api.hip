@@ -772,6 +772,28 @@ int sapq_nn_get_weights(sapq_ctx *h, float *w) {
     return hipcheck(hipGetLastError(), "sapq_nn_get_weights");
 }
 
+int sapq_nn_copy_state(sapq_ctx *dh, sapq_ctx *sh) {
+    if (!dh || !sh) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *d = &dh->c, *s = &sh->c;
+    int rc = nn_ready(s, true);
+    if (rc) return rc;
+    rc = nn_ready(d, false);
+    if (rc) return rc;
+    if (d == s) return SAPQ_OK;
+    rc = hipcheck(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (rc) return rc;
+    float *dst[] = {d->nn_w, d->nn_wq, d->nn_m, d->nn_v};
+    const float *src[] = {s->nn_w, s->nn_wq, s->nn_m, s->nn_v};
+    for (int k = 0; k < 4; ++k) {
+        rc = hipcheck(hipMemcpyAsync(dst[k], src[k], NN_PARAMS * sizeof(float), hipMemcpyDeviceToDevice, d->stream),
+                      "hipMemcpyAsync(nn state)");
+        if (rc) return rc;
+    }
+    nn_prepare(d);
+    d->have_nn = true;
+    return hipcheck(hipGetLastError(), "sapq_nn_copy_state");
+}
+
 int sapq_nn_forward(sapq_ctx *h, double *out, const double *in) {
     if (!h || !out || !in) { set_error("null argument"); return SAPQ_EINVAL; }
     Ctx *c = &h->c;

@@ -44,7 +44,7 @@ struct BField {
 
 struct BatchDev {
     int nf, total_rhs;
-    int work0[MAX_FIELDS + 1];  // prefix sums of NBc * ngroups over fields
+    int work0[MAX_FIELDS + 1];  // prefix sums of 8 ceil(NBc / 8) ngroups over fields (work_item)
     BField f[MAX_FIELDS];
 };
 
@@ -62,6 +62,21 @@ __device__ __forceinline__ int field_of_work(const BatchDev &B, int w) {
     return f;
 }
 
+// Work item w of a phase launch: its field fi, block ib of colour `colour` (-1: an idle
+// workgroup) and group index. Workgroups are dealt to the 8 XCDs in turn. A field's items
+// (8 ceil(NBc / 8) ngroups of them, from a multiple of 8) deal its blocks round robin to the
+// XCDs, and an XCD takes all groups of one block in a row. So the groups share the block's
+// links and clover rows in one L2, while the blocks, and with them the uneven work of
+// converged sources and differently sized fields, stay spread evenly over the XCDs.
+__device__ __forceinline__ int work_item(const BatchDev &B, int w, int colour, int &fi, int &group) {
+    fi = field_of_work(B, w);
+    const BField &F = B.f[fi];
+    const int local = w - B.work0[fi], pos = local / N_XCD;
+    const int b = (pos / F.ngroups) * N_XCD + local % N_XCD;
+    group = pos % F.ngroups;
+    return b < F.g.NBc ? colour * F.g.NBc + b : -1;
+}
+
 // ---------------------------------------------------------------- multi-RHS SAP phase
 // As the single-source phase kernel, for NR right-hand sides at once (iterates in LDS).
 template <int P, int NR>
@@ -71,13 +86,13 @@ __global__ void __launch_bounds__(512) k_bsap_phase(const BatchDev *__restrict__
     using C = float;
     extern __shared__ float2 lds[];
     const BatchDev &B = *Bd;
-    const int w = blockIdx.x;
-    const int fi = field_of_work(B, w);
+    if ((int)blockIdx.x >= B.work0[B.nf]) return;
+    int fi, grp;
+    const int ib = work_item(B, blockIdx.x, colour, fi, grp);
+    if (ib < 0) return;
     const BField &F = B.f[fi];
     const GeomDev &g = F.g;
-    const int local = w - B.work0[fi];
-    const int ib = colour * g.NBc + local / F.ngroups;
-    const int k0 = (local % F.ngroups) * NR;
+    const int k0 = grp * NR;
     // skip groups whose right-hand sides are all finished (uniform over the workgroup)
     bool any = false;
 #pragma unroll
@@ -212,13 +227,13 @@ __global__ void __launch_bounds__(768) k_bsap_phase_2l(const BatchDev *__restric
     using S2 = typename Prec<P>::S2;
     extern __shared__ float4 xb[];
     const BatchDev &B = *Bd;
-    const int w = blockIdx.x;
-    const int fi = field_of_work(B, w);
+    if ((int)blockIdx.x >= B.work0[B.nf]) return;
+    int fi, grp;
+    const int ib = work_item(B, blockIdx.x, colour, fi, grp);
+    if (ib < 0) return;
     const BField &F = B.f[fi];
     const GeomDev &g = F.g;
-    const int local = w - B.work0[fi];
-    const int ib = colour * g.NBc + local / F.ngroups;
-    const int k0 = (local % F.ngroups) * NR;
+    const int k0 = grp * NR;
     bool any = false;
 #pragma unroll
     for (int k = 0; k < NR; ++k)
@@ -370,6 +385,53 @@ __global__ void __launch_bounds__(256) k_bsap_face(const BatchDev *__restrict__ 
 #pragma unroll
     for (int c = 0; c < 3; ++c) v[c] = v[c] + F.kappa * fh[c];
     store_spin(r, g, ib, s, j, v);
+}
+
+// The same face update with two lanes per site (the single-source k_sap_face_2l), for every
+// field and right-hand side; sites with no hop out of their block leave at once.
+template <int P>
+__global__ void __launch_bounds__(256) k_bsap_face_2l(const BatchDev *__restrict__ Bd, int colour, int s_r, int s_x,
+                                                     const BState *__restrict__ bst) {
+    using S2 = typename Prec<P>::S2;
+    const BatchDev &B = *Bd;
+    const int fi = blockIdx.y, k = blockIdx.z;
+    if (fi >= B.nf) return;
+    const BField &F = B.f[fi];
+    if (k >= F.nrhs || bst[F.rhs0 + k].done) return;
+    const GeomDev &g = F.g;
+    const long i = xcd_site_base(128) + (threadIdx.x >> 1);
+    const int d = threadIdx.x & 1;
+    if (i >= (long)g.NBc * g.Vb) return;  // both lanes of a site together
+    const int ib = colour * g.NBc + (int)(i / g.Vb), s = (int)(i % g.Vb);
+    int outside = 0;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const unsigned w = g.nbr16[mu * g.Vb + s];
+        outside |= ((d ? (w >> 16) : w) & 0x8000u) ? 0 : 1;
+    }
+    outside |= __builtin_amdgcn_update_dpp(0, outside, QUAD_XOR1, 0xF, 0xF, true);
+    if (!outside) return;
+    const size_t ko = (size_t)k * F.nvec;
+    S2 *r = (S2 *)F.iv[s_r] + ko;
+    const S2 *x = (const S2 *)F.iv[s_x] + ko;
+    const S2 *U = (const S2 *)F.Uin;
+    const float sg = d ? -1.f : 1.f;
+    cx<float> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
+    gather_hop<0>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 0 + d) * g.NB + ib], sg);
+    gather_hop<1>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 1 + d) * g.NB + ib], sg);
+    gather_hop<2>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 2 + d) * g.NB + ib], sg);
+    gather_hop<3>(acc, g, x, U, ib, s, d, g.blk_nbr[(2 * 3 + d) * g.NB + ib], sg);
+    pair_reduce(acc);
+    cx<float> own[6], out[6], v[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) own[e] = sel(d != 0, acc[6 + e], acc[e]);
+    clover_block(out, own, (const S2 *)F.Fin + ((size_t)ib * 2 + d) * 18 * g.Vb + s, g.Vb);
+    load6(v, r, ib, s, d, g.Vb);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) v[e] = v[e] + F.kappa * out[e];
+    store6(r, ib, s, d, g.Vb, v);
 }
 
 // out = D in in FP64 for every field and right-hand side (outer slots)
@@ -738,7 +800,6 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
     B.stream = c0->stream;
     B.use_nn = true;
     for (Ctx *c : B.ctx) B.use_nn = B.use_nn && c->have_nn && (c->prm.flags & SAPQ_FLAG_NN);
-    // right-hand sides per workgroup: 1 to 4, as the LDS and the thread limit allow
     int max_lds = 65536, dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     // two lanes per site when every context runs the one-workgroup two-lane kernel (same
@@ -748,12 +809,21 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
     const size_t per = B.two_lane ? (size_t)(c0->g.Vb + 1) * 6 * sizeof(float4) : (size_t)c0->g.Vb * 12 * sizeof(float2);
     const size_t extra = B.two_lane ? 0 : c0->lds_extra;
     const int tpr = B.two_lane ? c0->part_threads : c0->ssor_threads;
-    // right-hand sides per group: the size that leaves the fewest empty slots in the groups of
-    // all fields (ties to the larger group), among those whose iterates fit LDS
+    // right-hand sides per workgroup: one by default.  Larger groups (up to 4, as the LDS and
+    // the thread limit allow; SAPQ_BATCH_NR=n, read here, permits them) load a site's links
+    // once for all their sources, but their slices wait for each other at every barrier.
+    // With the groups of a block consecutive on one XCD (work_item) the links are shared
+    // through its L2 anyway, and one source per workgroup measured fastest.  Among the
+    // permitted sizes the one that leaves the fewest empty slots in the groups of all fields
+    // wins (ties to the larger).
+    int nr_cap = 1;
+    if (const char *e = getenv("SAPQ_BATCH_NR")) nr_cap = std::max(1, std::min(4, atoi(e)));
     B.NR = 0;
     long best_slots = 0;
     for (int nr : {4, 3, 2, 1}) {
-        if (nr > std::max(1, B.max_rhs) || per * nr + extra > (size_t)max_lds || (B.two_lane && nr * tpr > 768)) continue;
+        if (nr > nr_cap || nr > std::max(1, B.max_rhs) || per * nr + extra > (size_t)max_lds ||
+            (B.two_lane && nr * tpr > 768))
+            continue;
         long slots = 0;
         for (int f = 0; f < nctx; ++f) slots += (long)(nrhs[f] + nr - 1) / nr * nr;
         if (B.NR == 0 || slots < best_slots) {
@@ -791,7 +861,7 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
         F.pst = c->part_pstart;
         F.tpr = c->part_threads;
         B.host.work0[f] = work;
-        work += c->g.NBc * F.ngroups;
+        work += (c->g.NBc + N_XCD - 1) / N_XCD * N_XCD * F.ngroups;  // a multiple of 8 (work_item)
         B.total += nrhs[f];
     }
     B.host.work0[nctx] = work;
@@ -833,8 +903,14 @@ static void bmsap(Batch &B, int src, int y) {
     }
     long maxc = 0;
     for (Ctx *c : B.ctx) maxc = std::max(maxc, (long)c->g.NBc * c->g.Vb);
-    dim3 g((unsigned)((4 * maxc + 255) / 256), (unsigned)B.nf, (unsigned)B.max_rhs);
-    BPREC(B.prec, (k_bsap_face<P_><<<g, 256, 0, B.stream>>>(B.dev, 0, IV_SAPR, IV_SAPX, B.st)));
+    if (B.two_lane) {
+        const unsigned gx = (unsigned)((2 * maxc + 255) / 256 + N_XCD - 1) / N_XCD * N_XCD;
+        dim3 g(gx, (unsigned)B.nf, (unsigned)B.max_rhs);
+        BPREC(B.prec, (k_bsap_face_2l<P_><<<g, 256, 0, B.stream>>>(B.dev, 0, IV_SAPR, IV_SAPX, B.st)));
+    } else {
+        dim3 g((unsigned)((4 * maxc + 255) / 256), (unsigned)B.nf, (unsigned)B.max_rhs);
+        BPREC(B.prec, (k_bsap_face<P_><<<g, 256, 0, B.stream>>>(B.dev, 0, IV_SAPR, IV_SAPX, B.st)));
+    }
 }
 
 static void bdots(Batch &B, int nd, int a0, int b0, int a1, int b1) {

@@ -73,6 +73,7 @@ _SIGS = {
     "sapq_nn_param_count": (ctypes.c_size_t, []),
     "sapq_nn_set_weights": (ctypes.c_int, [_P, _P]),
     "sapq_nn_get_weights": (ctypes.c_int, [_P, _P]),
+    "sapq_nn_copy_state": (ctypes.c_int, [_P, _P]),
     "sapq_nn_forward": (ctypes.c_int, [_P, _P, _P]),
     "sapq_nn_backward": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sapq_nn_train_step": (ctypes.c_int, [_P, _P, ctypes.c_long, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -120,7 +121,7 @@ def _ptr(t, V=None, shape_tail=None):
 class Solver:
     """One lattice + parameter set (one sapq context) with its own device arena."""
 
-    def __init__(self, L, block, subblock, kappa, bc=(1, 1, 1, 1), omega=1.0, n_ssor=4, n_sap=4, tol_inner=1e-2,
+    def __init__(self, L, block, subblock, kappa, bc=(1, 1, 1, 1), omega=1.0, n_ssor=4, n_sap=4, tol_inner=0.1,
                  maxit_inner=50, maxit_outer=100, prec="fp32", outer="fbicgstab", device=None, nn=False,
                  nn_fp32=False):
         self.L = tuple(L)
@@ -241,6 +242,10 @@ class Solver:
         _check(lib().sapq_nn_get_weights(self.h, ctypes.c_void_p(w.data_ptr())))
         return w
 
+    def nn_copy_state_from(self, other):
+        """Take over other's training state (weights and Adam moments; sapq_nn_copy_state)."""
+        _check(lib().sapq_nn_copy_state(self.h, other.h))
+
     def nn_forward(self, psi):
         out = self._spinor()
         _check(lib().sapq_nn_forward(self.h, _ptr(out), _ptr(psi, self.V, (4, 3))))
@@ -273,10 +278,12 @@ _BATCH_ARENA = {}
 
 def _batch_arena(device, nbytes):
     a = _BATCH_ARENA.get(device)
-    if a is None or a.numel() < nbytes:
-        _BATCH_ARENA.pop(device, None)
-        a = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        _BATCH_ARENA[device] = a
+    if a is not None and a.numel() >= nbytes:
+        return a
+    del a
+    _BATCH_ARENA.pop(device, None)  # the old one is freed before the larger one is taken
+    a = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    _BATCH_ARENA[device] = a
     return a
 
 

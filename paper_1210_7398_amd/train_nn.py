@@ -7,6 +7,8 @@ Only e_k is stored (float32, interchange layout); the library forms r_k = D e_k 
 FP32 inside sapq_nn_train_step.  The loss is the batch mean of |N r - e|^2 / |e|^2
 and the update is Adam; forward, backward and the update run in the library's kernels.
 """
+import sys
+
 import numpy as np
 import torch
 
@@ -47,21 +49,21 @@ def make_pairs(solver, sources, n_iter=5, tol=1e-12):
 
 
 def train(solvers_and_pairs, steps, batch=8, lr=1e-3, seed=0, log=None):
-    """Adam on mini-batches drawn in turn from each (solver, e) entry; the solvers share one
-    set of weights, carried from one to the next.  Returns the per-step losses."""
+    """Adam on mini-batches drawn in turn from each (solver, e) entry (one solver per field);
+    the training state (weights and Adam moments) passes from each solver to the next, so the
+    solvers run one Adam.  Returns the per-step losses; log=n prints every n-th to stderr."""
     rng = np.random.default_rng(seed)
     losses = []
-    w = None
+    prev = None
     for t in range(1, steps + 1):
         solver, e = solvers_and_pairs[(t - 1) % len(solvers_and_pairs)]
-        if w is not None and len(solvers_and_pairs) > 1:
-            solver.nn_set_weights(w)  # only one solver per field; moments restart per field
+        if prev is not None and prev is not solver:
+            solver.nn_copy_state_from(prev)
         idx = rng.integers(0, e.shape[0], size=batch)
         losses.append(solver.nn_train_step(e, idx, lr, t))
-        if len(solvers_and_pairs) > 1:
-            w = solver.nn_get_weights()
+        prev = solver
         if log and (t % log == 0 or t == 1):
-            print(f"# nn step {t}: loss {np.mean(losses[-log:]):.4f}", flush=True)
+            print(f"# nn step {t}: loss {np.mean(losses[-log:]):.4f}", file=sys.stderr, flush=True)
     return losses
 
 

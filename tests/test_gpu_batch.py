@@ -26,10 +26,14 @@ def point_sources(L, n):
     return np.stack([synth.point_source(L, k % 4, (k // 4) % 3) for k in range(n)])
 
 
+# group size 1 is the default; 4 (with 5 and 2 sources: groups of 4 + 1 and 2) and 3 run the
+# multi-source workgroups, whose slices each hold one source's iterate
+@pytest.mark.parametrize("group", ["1", "3", "4"])
 @pytest.mark.parametrize("prec", ["fp32", "fp16"])
-def test_solve_batch_two_fields(torch_cuda, orc, prec):
+def test_solve_batch_two_fields(torch_cuda, orc, prec, group, monkeypatch):
     from paper_1210_7398_amd import sapq
 
+    monkeypatch.setenv("SAPQ_BATCH_NR", group)
     torch = torch_cuda
     kappa = 0.125
     B, S = (4, 4, 4, 4), (2, 2, 2, 2)

@@ -187,6 +187,9 @@ def test_nn_training_gain(torch_cuda, orc):
     s.load_gauge(to_dev(U))
     s.load_clover(to_dev(F))
     s.nn_set_weights(w)
+    # held-out pairs from the plain solver, as the training pairs are made (with the stage on,
+    # the iterates would keep only the error that the network does not remove)
+    s.use_nn(False)
     held = train_nn.make_pairs(s, [to_dev(synth.gaussian_spinor(L, 25001))], n_iter=4)
     gains = []
     for k in range(1, held.shape[0]):
@@ -201,3 +204,31 @@ def test_nn_training_gain(torch_cuda, orc):
     b = synth.gaussian_spinor(L, 25002)
     x, st = s.solve(to_dev(b), tol=1e-10)
     assert relerr(orc.dslash(L, U, F, kappa, to_host(x)), b) <= 1e-10
+
+
+def test_nn_copy_state_continues_adam(torch_cuda, orc):
+    """Training that hands its state (weights and both Adam moments) to another context goes
+    on as if uninterrupted: two Adam steps split over two contexts of the same field give the
+    same weights, bit for bit, as two steps on one context.  Restarting the second step from
+    the weights alone (moments reset) does not."""
+    torch = torch_cuda
+    L, B, S, kappa, eps, bc = GEOMS[NAME]
+    V = int(np.prod(L))
+    a, b, c, d = (make(torch) for _ in range(4))
+    w0 = torch.from_numpy(rand_weights(orc, 7)).cuda()
+    g = torch.Generator().manual_seed(8)
+    e = torch.randn((4, V, 4, 3, 2), generator=g, dtype=torch.float32).cuda()
+    for s in (a, c, d):
+        s.nn_set_weights(w0)
+    c.nn_train_step(e, [0, 1], 1e-3, 1)
+    c.nn_train_step(e, [2, 3], 1e-3, 2)
+    a.nn_train_step(e, [0, 1], 1e-3, 1)
+    b.nn_copy_state_from(a)
+    b.nn_train_step(e, [2, 3], 1e-3, 2)
+    assert torch.equal(b.nn_get_weights(), c.nn_get_weights())
+    d.nn_train_step(e, [0, 1], 1e-3, 1)
+    d.nn_set_weights(d.nn_get_weights())
+    d.nn_train_step(e, [2, 3], 1e-3, 2)
+    assert not torch.equal(d.nn_get_weights(), c.nn_get_weights())
+    for s in (a, b, c, d):
+        s.close()
