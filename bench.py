@@ -490,8 +490,8 @@ def main():
     ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a domain-decomposed "
+              "multi-GPU solver is not built.", file=sys.stderr)
         sys.exit(2)
     if args.mode == "copy":
         copy_calibration()

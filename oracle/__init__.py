@@ -11,8 +11,8 @@ Every array is numpy complex128 in the interchange layout:
   clover  [V, 2, 6, 6]   two chiral 6x6 blocks, row 3*(alpha-2k)+a
 
 Each wrapper names the passage of the paper its C routine follows.  The NN
-routines (``nn_*``) follow the linear parallel-transport convolution defined
-in the design doc; they have no passage in the paper.
+routines (``nn_*``) follow the linear parallel-transport convolution stated in
+nn_oracle.c; they have no passage in the paper.
 """
 import ctypes
 import os

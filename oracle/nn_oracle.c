@@ -2,8 +2,8 @@
  * nn_oracle.c -- plain FP64 CPU oracle of the learned gauge-covariant preconditioner stage
  * (test infrastructure only; shares no code with the GPU library).
  *
- * The paper has no learned part; the stage is defined as a linear parallel-transport
- * convolution ("Learned stage").  One layer maps c_in spinor channels to c_out:
+ * The paper has no learned part; the stage is defined here as a linear parallel-transport
+ * convolution.  One layer maps c_in spinor channels to c_out:
  *
  *   out[c'](n) = sum_{d=0..8} sum_c W[d][c'][c] (T_d in[c])(n)
  *

@@ -8,8 +8,8 @@
  * header, table or helper with the GPU library; it is written for a reader who
  * checks it against the paper by eye, not for speed.
  *
- * Conventions (one spin basis everywhere; see the design doc for every reading of
- * the paper that this file takes):
+ * Conventions (one chiral spin basis everywhere; where the paper is silent or
+ * garbled, the reading taken is stated at the routine that depends on it):
  *   site      n = x + Lx*(y + Ly*(z + Lz*t)); mu = 0..3 stands for x,y,z,t
  *   spinor    psi[n][alpha][a]  complex128, spin alpha = 0..3, colour a = 0..2
  *   links     U[n][mu][a][b]    U_mu(n), the link from n to n+mu
