@@ -6,6 +6,7 @@
 // from 0) once on the whole block and once by two emulated workgroups advancing in a
 // random interleaving; the results must agree bit for bit and no interleaving may leave
 // both workgroups waiting.
+#include <array>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -175,6 +176,34 @@ int main() {
         build_tables(&G, T);
         PartTables P;
         if (build_parts(&G, T, 2, P)) { printf("FAIL: split accepted 3 sub-block layers in t\n"); ++fails; }
+    }
+    // even-odd site order (all-zero sub-block): two hyperplanes, the even and the odd sites of
+    // the block, no coupled pair inside a plane, one-workgroup tables only
+    for (const auto &Bv : {std::array<int, 4>{4, 4, 4, 4}, std::array<int, 4>{6, 6, 6, 6}, std::array<int, 4>{3, 4, 5, 6}}) {
+        sapq_geom G;
+        for (int m = 0; m < 4; ++m) { G.L[m] = 2 * Bv[m]; G.block[m] = Bv[m]; G.subblock[m] = 0; G.bc_sign[m] = 1; }
+        HostTables T;
+        build_tables(&G, T);
+        const int Vb = T.Vb;
+        bool ok = T.nplanes == 2 && T.plane_start[0] == 0 && T.plane_start[2] == Vb;
+        std::vector<int> plane(Vb);
+        for (int s = 0; s < Vb && ok; ++s) {
+            plane[s] = s < T.plane_start[1] ? 0 : 1;
+            int l = T.slot_lex[s], sum = 0;
+            for (int m = 0; m < 4; ++m) { sum += l % Bv[m]; l /= Bv[m]; }
+            ok = ok && (sum & 1) == plane[s];
+        }
+        for (int k = 0; k < 8 && ok; ++k)
+            for (int s = 0; s < Vb && ok; ++s) {
+                const int t = T.loc_nbr[(size_t)k * Vb + s];
+                if (t >= 0) ok = plane[t] != plane[s];
+            }
+        PartTables P1, P2;
+        ok = ok && build_parts(&G, T, 1, P1) && !build_parts(&G, T, 2, P2);
+        if (!ok) {
+            printf("FAIL: even-odd tables for B=%dx%dx%dx%d\n", Bv[0], Bv[1], Bv[2], Bv[3]);
+            ++fails;
+        }
     }
     printf(fails ? "%d failures\n" : "all protocol cases agree\n", fails);
     return fails ? 1 : 0;
