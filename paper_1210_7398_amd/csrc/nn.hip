@@ -8,7 +8,10 @@
 // activation is a spinor field in the solver's layout ([NB][12][Vb]); an NN_C-channel one is
 // site-major, one record of NN_C x 12 complex per site i = ib Vb + s, so that a transport
 // reads all channels of a neighbour as one contiguous record.  The forward pass uses the
-// weights rounded to BF16; Adam keeps an FP32 master copy.
+// weights rounded to BF16; Adam keeps an FP32 master copy.  Inside a record the channels are
+// interleaved per pair of components: float4 k of channel c (components 2k and 2k + 1) sits at
+// float4 index (6 i + k) NN_C + c, so the 8 channel threads of a site read 128 contiguous
+// bytes per load instruction.
 #include "sitecore.h"
 
 namespace sapq {
@@ -17,19 +20,19 @@ static_assert(NN_C == 8, "the layer kernels are written for 8 hidden channels");
 
 // ---------------------------------------------------------------- activations
 __device__ __forceinline__ void load_rec(cx<float> t[12], const float2 *__restrict__ f, long i, int nch, int c) {
-    const float4 *p = reinterpret_cast<const float4 *>(f + ((size_t)i * nch + c) * 12);
+    const float4 *p = reinterpret_cast<const float4 *>(f) + (size_t)i * 6 * nch + c;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const float4 v = p[k];
+        const float4 v = p[k * nch];
         t[2 * k] = cx<float>{v.x, v.y};
         t[2 * k + 1] = cx<float>{v.z, v.w};
     }
 }
 
 __device__ __forceinline__ void store_rec(float2 *__restrict__ f, long i, int nch, int c, const cx<float> t[12]) {
-    float4 *p = reinterpret_cast<float4 *>(f + ((size_t)i * nch + c) * 12);
+    float4 *p = reinterpret_cast<float4 *>(f) + (size_t)i * 6 * nch + c;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) p[k] = make_float4(t[2 * k].r, t[2 * k].i, t[2 * k + 1].r, t[2 * k + 1].i);
+    for (int k = 0; k < 6; ++k) p[k * nch] = make_float4(t[2 * k].r, t[2 * k].i, t[2 * k + 1].r, t[2 * k + 1].i);
 }
 
 // channel c of an nch-channel activation at site (ib, s)
@@ -324,12 +327,14 @@ __device__ __forceinline__ void nn_store_tile(float2 *__restrict__ out, const Ge
             if (t < nv) out[((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
         }
     } else {
-        // the tile's records are contiguous: one coalesced sweep
-        float2 *o = out + ((size_t)ib * g.Vb + s0) * COUT * 12;
-        for (int w = threadIdx.x; w < nv * COUT * 12; w += blockDim.x) {
-            const int comp = w % 12, co = (w / 12) % COUT, t = w / (12 * COUT);
-            const int r = co * 4 + comp / 3, col = 3 * t + comp % 3;
-            o[w] = make_float2(Dt[r][col], Dt[M + r][col]);
+        // the tile's records are contiguous: one coalesced sweep of float4 (two components of
+        // one channel each, in the record's interleaved order)
+        float4 *o = reinterpret_cast<float4 *>(out) + ((size_t)ib * g.Vb + s0) * 6 * COUT;
+        for (int w = threadIdx.x; w < nv * 6 * COUT; w += blockDim.x) {
+            const int co = w % COUT, k = (w / COUT) % 6, t = w / (6 * COUT);
+            const int r0 = co * 4 + (2 * k) / 3, c0 = 3 * t + (2 * k) % 3;
+            const int r1 = co * 4 + (2 * k + 1) / 3, c1 = 3 * t + (2 * k + 1) % 3;
+            o[w] = make_float4(Dt[r0][c0], Dt[M + r0][c0], Dt[r1][c1], Dt[M + r1][c1]);
         }
     }
 }
