@@ -177,6 +177,36 @@ def blocks_study(args):
           flush=True)
 
 
+def nsap_study(args):
+    """N_SAP (SAP cycles per M_SAP application, which the paper leaves open) at 24^3x48 with
+    the workload's fields, source and blocks: time to 1e-10, M_SAP applications and phase
+    launches for N_SAP = 1, 2, 3, 4, 6, 8."""
+    import torch
+
+    from paper_1210_7398_amd import sapq
+
+    w = WORKLOADS["24^3x48"]
+    U, F, b = make_inputs(w)
+    dev = torch.device("cuda:0")
+    Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
+    del U, F
+    res = []
+    for n_sap in (1, 2, 3, 4, 6, 8):
+        s = sapq.Solver(w["L"], w["B"], w["S"], w["kappa"], n_sap=n_sap, maxit_outer=400, device=dev)
+        s.load_gauge(Ud)
+        s.load_clover(Fd)
+        t, st, ph_us = _solve_stats(s, bd, args.steps)
+        res.append(dict(n_sap=n_sap, time_s=t, n_msap=st["n_msap"], phase_launches=2 * n_sap * st["n_msap"],
+                        inner_its=st["inner_its"], outer_its=st["outer_its"], true_relres=st["true_relres"],
+                        sap_phase_avg_us=ph_us))
+        print(f"# {res[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "nsap", "lattice": list(w["L"]), "block": list(w["B"]), "subblock": list(w["S"]),
+                      "kappa": w["kappa"], "tol": 1e-10, "results": res}), flush=True)
+
+
 def msap_flops(B, V, n_ssor=4, n_sap=4):
     """Algorithmic flops of one M_SAP application on V sites (phase model, Table 1 counts)."""
     face = sum(2.0 / b for b in B)
@@ -486,7 +516,7 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision", "batch", "nn", "blocks",
-                                                        "sustained"])
+                                                        "sustained", "nsap"])
     ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -507,6 +537,9 @@ def main():
         return
     if args.mode == "blocks":
         blocks_study(args)
+        return
+    if args.mode == "nsap":
+        nsap_study(args)
         return
     if args.mode == "sustained":
         sustained_study(args)
