@@ -79,7 +79,8 @@ typedef struct {
 } sapq_geom;
 
 /*
- * Parameters.  kappa: hopping parameter of D (eq. 2.2).  omega: SSOR relaxation;
+ * Parameters (else SAPQ_EINVAL).  kappa: hopping parameter of D (eq. 2.2), > 0.  omega:
+ * SSOR relaxation, 0 < omega < 2;
  * n_ssor: symmetric (forward + backward) SSOR sweeps from x = 0 per block inverse;
  * n_sap: N_SAP of eq. (2.4).  tol_inner / maxit_inner: relative residual target and
  * iteration cap of the inner BiCGStab.  maxit_outer: outer iteration cap.

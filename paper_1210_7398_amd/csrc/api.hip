@@ -221,6 +221,16 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
     // ask for one / two workgroups per block wherever they fit.
     int mode = -1;
     if (const char *e = getenv("SAPQ_PARTS")) mode = atoi(e);
+    // SAPQ_HALO_TIMEOUT_TEST=1 (read here) makes every wait of a split block on its partner's
+    // halo words time out after 64 polls, so that the time-out path (error flag, SAPQ_EHIP)
+    // can be tested with every kernel still running to its end
+    c->halo_spin_limit = 1 << 20;
+    c->halo_wait_xor = 0;
+    if (const char *e = getenv("SAPQ_HALO_TIMEOUT_TEST"))
+        if (atoi(e) == 1) {
+            c->halo_spin_limit = 64;
+            c->halo_wait_xor = 0x80000000u;
+        }
     c->use_parts = false;
     c->sap_np = 1;
     for (int np = 1; np <= 2 && !c->use_parts; ++np) {

@@ -41,10 +41,13 @@ struct PartArgs {
     const int *imp_start;     // [NP][MAX_PLANES + 1]
     unsigned long long *xch;  // [NBc][NP][3][24][Hp]
     unsigned *sync;           // [0] ticket, [1] done, [2] epoch, [3] error
+    int spin_limit;           // bounded wait on a halo word, in polls
+    unsigned wait_xor;        // 0; nonzero only where a test forces the time-out path (no
+                              // written word then carries the awaited tag)
 };
 
 constexpr int IMP_REGS = 4;          // halo words a thread keeps in flight during a step
-constexpr int SPIN_LIMIT = 1 << 20;  // bounded wait on a halo word (about a second)
+constexpr int SPIN_LIMIT = 1 << 20;  // default bounded wait on a halo word (about a second)
 
 __device__ __forceinline__ unsigned xch_tag(unsigned epoch, int sweep) {
     return 0x80000000u | ((epoch & 0x1ffffffu) << 6) | (unsigned)(sweep & 63);
@@ -59,16 +62,17 @@ __device__ __forceinline__ unsigned long long xch_get(unsigned long long *p) {
 // the word at p once it carries `tag`; on time-out the error flag is raised and the caller
 // stops waiting for the rest of the launch (the result is then discarded by the host)
 __device__ __forceinline__ float xch_wait(unsigned long long w, unsigned long long *p, unsigned tag, bool &gave_up,
-                                          unsigned *sync) {
+                                          const PartArgs &a) {
+    tag ^= a.wait_xor;
     if ((unsigned)(w >> 32) != tag && !gave_up) {
         int it = 0;
         do {
             __builtin_amdgcn_s_sleep(2);
             w = xch_get(p);
-        } while ((unsigned)(w >> 32) != tag && ++it < SPIN_LIMIT);
+        } while ((unsigned)(w >> 32) != tag && ++it < a.spin_limit);
         if ((unsigned)(w >> 32) != tag) {
             gave_up = true;
-            __hip_atomic_store(&sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.sync[3], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     return __uint_as_float((unsigned)w);
@@ -229,13 +233,13 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     if (t < nw) {
                         const int c = t / ne, e = t - c * ne, k = imp[e0 + e];
                         unsigned long long *p = src + (size_t)c * Hp + k;
-                        xsf[(((c >> 2) * NS) + Vp + k) * 4 + (c & 3)] = xch_wait(pre[u], p, tag, gave_up, a.sync);
+                        xsf[(((c >> 2) * NS) + Vp + k) * 4 + (c & 3)] = xch_wait(pre[u], p, tag, gave_up, a);
                     }
                 }
                 for (int t = threadIdx.x + IMP_REGS * blockDim.x; t < nw; t += blockDim.x) {
                     const int c = t / ne, e = t - c * ne, k = imp[e0 + e];
                     unsigned long long *p = src + (size_t)c * Hp + k;
-                    xsf[(((c >> 2) * NS) + Vp + k) * 4 + (c & 3)] = xch_wait(xch_get(p), p, tag, gave_up, a.sync);
+                    xsf[(((c >> 2) * NS) + Vp + k) * 4 + (c & 3)] = xch_wait(xch_get(p), p, tag, gave_up, a);
                 }
             }
             lds_barrier();
@@ -249,7 +253,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
         for (int t = threadIdx.x; t < 24 * Hp; t += blockDim.x) {
             const int c = t / Hp, k = t - c * Hp;
             unsigned long long *p = src + (size_t)c * Hp + k;
-            xsf[(((c >> 2) * NS) + Vp + k) * 4 + (c & 3)] = xch_wait(xch_get(p), p, tag, gave_up, a.sync);
+            xsf[(((c >> 2) * NS) + Vp + k) * 4 + (c & 3)] = xch_wait(xch_get(p), p, tag, gave_up, a);
         }
         __syncthreads();
     }
@@ -366,6 +370,8 @@ void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_
     a.imp_start = c->part_imps;
     a.xch = c->xch;
     a.sync = c->xsync;
+    a.spin_limit = c->halo_spin_limit;
+    a.wait_xor = c->halo_wait_xor;
     const dim3 grid(c->g.NBc * c->sap_np), block(c->part_threads);
     INNER_SWITCH(c->prm.prec_inner, ({
                      using S2 = typename Prec<P_>::S2;

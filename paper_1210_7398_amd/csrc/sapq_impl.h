@@ -214,6 +214,8 @@ struct Ctx {
     // fields
     double2 *U64, *F64;
     int *slot_perm;   // [Vb] staging of a slot re-ordering (sub-block change)
+    int halo_spin_limit = 1 << 20;  // polls of a split block's bounded wait on a halo word
+    unsigned halo_wait_xor = 0;     // nonzero: every such wait times out (failure-path tests)
     void *Uin, *Fin;  // inner storage precision
     bool have_U, have_F;
     // FP64 work vectors (internal layout)
