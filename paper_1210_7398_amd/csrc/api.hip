@@ -490,7 +490,7 @@ static void nn_backward(Ctx *c) {
     float2 *gin[3] = {c->nn_gin, c->nn_g1, c->nn_g2};
     const float2 *gout = c->nn_gz;
     for (int k = 2; k >= 0; --k) {
-        launch_nn_wgrad(c, NN_CIN[k], NN_COUT[k], gout, acts[k], G + NN_OFF[k] / 2);
+        launch_nn_wgrad(c, NN_CIN[k], NN_COUT[k], gout, acts[k], G + NN_OFF[k] / 2, nn_use_mfma(c));
         launch_nn_adjoint_weights(c, NN_CIN[k], NN_COUT[k], W + NN_OFF[k] / 2, c->nn_wt);
         if (nn_use_mfma(c)) {
             launch_nn_afrag(c, NN_COUT[k], NN_CIN[k], c->nn_wt, c->nn_afrag_t);

@@ -8,10 +8,12 @@
 // activation is a spinor field in the solver's layout ([NB][12][Vb]); an NN_C-channel one is
 // site-major, one record of NN_C x 12 complex per site i = ib Vb + s, so that a transport
 // reads all channels of a neighbour as one contiguous record.  The forward pass uses the
-// weights rounded to BF16; Adam keeps an FP32 master copy.  Inside a record the channels are
-// interleaved per pair of components: float4 k of channel c (components 2k and 2k + 1) sits at
-// float4 index (6 i + k) NN_C + c, so the 8 channel threads of a site read 128 contiguous
-// bytes per load instruction.
+// weights rounded to BF16; Adam keeps an FP32 master copy.  Records hold FP32 values on the
+// FP32 path and BF16 values on the MFMA path, whose contraction rounds its inputs to BF16
+// anyway (the transports and sums stay FP32).  Inside a record the channels are interleaved
+// per 16-byte piece: piece k of channel c (components 2k, 2k + 1 in FP32, 4k .. 4k + 3 in
+// BF16) sits at piece index (K i + k) NN_C + c (K = 6 or 3), so the 8 channel threads of a
+// site read 128 contiguous bytes per load instruction.
 #include "sitecore.h"
 
 namespace sapq {
@@ -19,37 +21,71 @@ namespace sapq {
 static_assert(NN_C == 8, "the layer kernels are written for 8 hidden channels");
 
 // ---------------------------------------------------------------- activations
-__device__ __forceinline__ void load_rec(cx<float> t[12], const float2 *__restrict__ f, long i, int nch, int c) {
-    const float4 *p = reinterpret_cast<const float4 *>(f) + (size_t)i * 6 * nch + c;
+enum { REC_F32 = 0, REC_BF16 = 1 };  // value type of the 8-channel activation records
+
+__device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ __forceinline__ unsigned bf16_pack(float lo, float hi) {
+    const __hip_bfloat16 a = __float2bfloat16(lo), b = __float2bfloat16(hi);  // round to nearest even
+    return (unsigned)*reinterpret_cast<const unsigned short *>(&a) |
+           ((unsigned)*reinterpret_cast<const unsigned short *>(&b) << 16);
+}
+
+template <int RT>
+__device__ __forceinline__ void load_rec(cx<float> t[12], const void *__restrict__ f, long i, int nch, int c) {
+    if constexpr (RT == REC_F32) {
+        const float4 *p = reinterpret_cast<const float4 *>(f) + (size_t)i * 6 * nch + c;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const float4 v = p[k * nch];
-        t[2 * k] = cx<float>{v.x, v.y};
-        t[2 * k + 1] = cx<float>{v.z, v.w};
+        for (int k = 0; k < 6; ++k) {
+            const float4 v = p[k * nch];
+            t[2 * k] = cx<float>{v.x, v.y};
+            t[2 * k + 1] = cx<float>{v.z, v.w};
+        }
+    } else {
+        const uint4 *p = reinterpret_cast<const uint4 *>(f) + (size_t)i * 3 * nch + c;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint4 v = p[k * nch];
+            t[4 * k] = cx<float>{bf16_lo(v.x), bf16_hi(v.x)};
+            t[4 * k + 1] = cx<float>{bf16_lo(v.y), bf16_hi(v.y)};
+            t[4 * k + 2] = cx<float>{bf16_lo(v.z), bf16_hi(v.z)};
+            t[4 * k + 3] = cx<float>{bf16_lo(v.w), bf16_hi(v.w)};
+        }
     }
 }
 
-__device__ __forceinline__ void store_rec(float2 *__restrict__ f, long i, int nch, int c, const cx<float> t[12]) {
-    float4 *p = reinterpret_cast<float4 *>(f) + (size_t)i * 6 * nch + c;
+template <int RT>
+__device__ __forceinline__ void store_rec(void *__restrict__ f, long i, int nch, int c, const cx<float> t[12]) {
+    if constexpr (RT == REC_F32) {
+        float4 *p = reinterpret_cast<float4 *>(f) + (size_t)i * 6 * nch + c;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) p[k * nch] = make_float4(t[2 * k].r, t[2 * k].i, t[2 * k + 1].r, t[2 * k + 1].i);
+        for (int k = 0; k < 6; ++k) p[k * nch] = make_float4(t[2 * k].r, t[2 * k].i, t[2 * k + 1].r, t[2 * k + 1].i);
+    } else {
+        uint4 *p = reinterpret_cast<uint4 *>(f) + (size_t)i * 3 * nch + c;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            p[k * nch] = make_uint4(bf16_pack(t[4 * k].r, t[4 * k].i), bf16_pack(t[4 * k + 1].r, t[4 * k + 1].i),
+                                    bf16_pack(t[4 * k + 2].r, t[4 * k + 2].i), bf16_pack(t[4 * k + 3].r, t[4 * k + 3].i));
+    }
 }
 
 // channel c of an nch-channel activation at site (ib, s)
+template <int RT>
 __device__ __forceinline__ void load_chan(cx<float> t[12], const float2 *__restrict__ f, int nch, const GeomDev &g,
                                           int ib, int s, int c) {
     if (nch == 1)
         load_spinor(t, f, g, ib, s);
     else
-        load_rec(t, f, (long)ib * g.Vb + s, nch, c);
+        load_rec<RT>(t, f, (long)ib * g.Vb + s, nch, c);
 }
 
+template <int RT>
 __device__ __forceinline__ void store_chan(float2 *__restrict__ f, int nch, const GeomDev &g, int ib, int s, int c,
                                            const cx<float> t[12]) {
     if (nch == 1)
         store_spinor(f, g, ib, s, t);
     else
-        store_rec(f, (long)ib * g.Vb + s, nch, c, t);
+        store_rec<RT>(f, (long)ib * g.Vb + s, nch, c, t);
 }
 
 // ---------------------------------------------------------------- transports
@@ -112,14 +148,15 @@ __device__ __forceinline__ void nn_link(cx<float> u[9], const float2 *__restrict
 
 // (T_d f[c])(ib, s) for channel c of an nch-channel activation, the neighbour (nb, ns) of
 // (ib, s) for d already known
+template <int RT>
 __device__ __forceinline__ void nn_transport(cx<float> t[12], const float2 *__restrict__ f, int nch, const GeomDev &g,
                                              const float2 *__restrict__ L, int ib, int s, int d, int c, int nb, int ns) {
     if (d == 0) {
-        load_chan(t, f, nch, g, ib, s, c);
+        load_chan<RT>(t, f, nch, g, ib, s, c);
         return;
     }
     cx<float> p[12], u[9];
-    load_chan(p, f, nch, g, nb, ns, c);
+    load_chan<RT>(p, f, nch, g, nb, ns, c);
     nn_link(u, L, (long)ib * g.Vb + s, d);
 #pragma unroll
     for (int be = 0; be < 4; ++be) {
@@ -149,7 +186,7 @@ __global__ void __launch_bounds__(256) k_nn_layer(GeomDev g, const float2 *__res
 #pragma unroll 1
         for (int ci = 0; ci < CIN; ++ci) {
             cx<float> t[12];
-            nn_transport(t, in, CIN, g, L, ib, s, d, ci, nb, ns);
+            nn_transport<REC_F32>(t, in, CIN, g, L, ib, s, d, ci, nb, ns);
             const float2 *w = W + (((size_t)d * COUT + co) * CIN + ci) * 16;
 #pragma unroll
             for (int al = 0; al < 4; ++al)
@@ -162,11 +199,12 @@ __global__ void __launch_bounds__(256) k_nn_layer(GeomDev g, const float2 *__res
                 }
         }
     }
-    store_chan(out, COUT, g, ib, s, co, acc);
+    store_chan<REC_F32>(out, COUT, g, ib, s, co, acc);
 }
 
 // G[d][c'][c] (16 complex) = sum_n sum_a gout[c'](n)[al][a] conj((T_d in[c])(n)[be][a]), added to G.
 // One workgroup per (d, c', c); a fixed-order tree finishes the sum.
+template <int RT>
 __global__ void __launch_bounds__(256) k_nn_wgrad(GeomDev g, int cin, int cout, const float2 *__restrict__ gout,
                                                  const float2 *__restrict__ in, const float2 *__restrict__ L,
                                                  float2 *__restrict__ G) {
@@ -181,8 +219,8 @@ __global__ void __launch_bounds__(256) k_nn_wgrad(GeomDev g, int cin, int cout, 
         float ph;
         nn_neighbour(g, ib, s, d, nb, ns, ph);
         cx<float> t[12], go[12];
-        nn_transport(t, in, cin, g, L, ib, s, d, ci, nb, ns);
-        load_chan(go, gout, cout, g, ib, s, co);
+        nn_transport<RT>(t, in, cin, g, L, ib, s, d, ci, nb, ns);
+        load_chan<RT>(go, gout, cout, g, ib, s, co);
 #pragma unroll
         for (int al = 0; al < 4; ++al)
 #pragma unroll
@@ -317,7 +355,7 @@ template <int MT, int NT> struct WaveTiles {
 };
 
 // the tile of D (rows (re/im, c', alpha), columns (site, colour)) to the output activation
-template <int COUT>
+template <int COUT, int RT>
 __device__ __forceinline__ void nn_store_tile(float2 *__restrict__ out, const GeomDev &g, int ib, int s0, int nv,
                                               const float (*Dt)[3 * NN_TILE + 1]) {
     constexpr int M = 4 * COUT;
@@ -326,15 +364,28 @@ __device__ __forceinline__ void nn_store_tile(float2 *__restrict__ out, const Ge
             const int t = w % NN_TILE, comp = w / NN_TILE, r = comp / 3, col = 3 * t + comp % 3;
             if (t < nv) out[((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
         }
-    } else {
-        // the tile's records are contiguous: one coalesced sweep of float4 (two components of
-        // one channel each, in the record's interleaved order)
+    } else if constexpr (RT == REC_F32) {
+        // the tile's records are contiguous: one coalesced sweep of 16-byte pieces (two
+        // components of one channel each, in the record's interleaved order)
         float4 *o = reinterpret_cast<float4 *>(out) + ((size_t)ib * g.Vb + s0) * 6 * COUT;
         for (int w = threadIdx.x; w < nv * 6 * COUT; w += blockDim.x) {
             const int co = w % COUT, k = (w / COUT) % 6, t = w / (6 * COUT);
             const int r0 = co * 4 + (2 * k) / 3, c0 = 3 * t + (2 * k) % 3;
             const int r1 = co * 4 + (2 * k + 1) / 3, c1 = 3 * t + (2 * k + 1) % 3;
             o[w] = make_float4(Dt[r0][c0], Dt[M + r0][c0], Dt[r1][c1], Dt[M + r1][c1]);
+        }
+    } else {
+        // BF16 records: pieces of four components of one channel
+        uint4 *o = reinterpret_cast<uint4 *>(out) + ((size_t)ib * g.Vb + s0) * 3 * COUT;
+        for (int w = threadIdx.x; w < nv * 3 * COUT; w += blockDim.x) {
+            const int co = w % COUT, k = (w / COUT) % 3, t = w / (3 * COUT);
+            unsigned q[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int comp = 4 * k + j, r = co * 4 + comp / 3, col = 3 * t + comp % 3;
+                q[j] = bf16_pack(Dt[r][col], Dt[M + r][col]);
+            }
+            o[w] = make_uint4(q[0], q[1], q[2], q[3]);
         }
     }
 }
@@ -359,7 +410,7 @@ __device__ __forceinline__ void nn_put_b(__hip_bfloat16 (*Bt)[BPAD], int t, int 
 
 // One input channel (the first layer, and the adjoint of the last): the whole reduction
 // index (9 directions x 4 spins, re / im) is one LDS tile.
-template <int COUT>
+template <int COUT, int RT>
 __global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 *__restrict__ in,
                                                        float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
                                                        const float2 *__restrict__ L) {
@@ -386,7 +437,7 @@ __global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 
     for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
         const int t = w % NS, d = w / NS;
         cx<float> T[12];
-        nn_transport(T, in, 1, g, L, ib, s0 + min(t, nv - 1), d, 0, nb_blk[d][t], nb_slot[d][t]);
+        nn_transport<RT>(T, in, 1, g, L, ib, s0 + min(t, nv - 1), d, 0, nb_blk[d][t], nb_slot[d][t]);
         nn_put_b<BPAD>(Bt, t, 4 * d, K + 4 * d, T);
     }
     for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
@@ -419,7 +470,7 @@ __global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 
     }
     __syncthreads();
     // 3. complex outputs: out[c'](site)[alpha][a] = D[c' 4 + alpha][col] + i D[M + c' 4 + alpha][col]
-    nn_store_tile<COUT>(out, g, ib, s0, nv, Dt);
+    nn_store_tile<COUT, RT>(out, g, ib, s0, nv, Dt);
 }
 
 // Eight input channels: the reduction index is taken in chunks of two transport directions
@@ -427,8 +478,8 @@ __global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 
 // transports one channel of one site along both directions; the eight threads of a site read
 // the neighbour's record as one contiguous 768-byte piece.  The MFMA consumes the chunk from
 // LDS before the next one; the accumulators stay in registers.
-template <int COUT>
-__global__ void __launch_bounds__(256) k_nn_layer8_mfma(GeomDev g, const float2 *__restrict__ in,
+template <int COUT, int RT>
+__global__ void __launch_bounds__(256, 4) k_nn_layer8_mfma(GeomDev g, const float2 *__restrict__ in,
                                                        float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
                                                        const float2 *__restrict__ L) {
     constexpr int CIN = 8, K = 36 * CIN, K2P = nn_k2p(CIN), M2P = nn_m2p(COUT);
@@ -464,7 +515,7 @@ __global__ void __launch_bounds__(256) k_nn_layer8_mfma(GeomDev g, const float2 
         cx<float> T[2][12];
 #pragma unroll
         for (int dd = 0; dd < 2; ++dd)
-            if (dd < nd) nn_transport(T[dd], in, CIN, g, L, ib, s, d0 + dd, c, nb_blk[d0 + dd][t], nb_slot[d0 + dd][t]);
+            if (dd < nd) nn_transport<RT>(T[dd], in, CIN, g, L, ib, s, d0 + dd, c, nb_blk[d0 + dd][t], nb_slot[d0 + dd][t]);
 #pragma unroll
         for (int dd = 0; dd < 2; ++dd)
             if (dd < nd) nn_put_b<BPAD>(Bt, t, (dd * CIN + c) * 4, 64 + (dd * CIN + c) * 4, T[dd]);
@@ -496,7 +547,7 @@ __global__ void __launch_bounds__(256) k_nn_layer8_mfma(GeomDev g, const float2 
             for (int q = 0; q < 4; ++q) Dt[WT::mt(wave) * 16 + kq + q][nt * 16 + (lane & 15)] = acc[j][q];
     }
     __syncthreads();
-    nn_store_tile<COUT>(out, g, ib, s0, nv, Dt);
+    nn_store_tile<COUT, RT>(out, g, ib, s0, nv, Dt);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -525,11 +576,11 @@ void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *o
     const unsigned grid = nn_grid(c);
     const short4_t *A = (const short4_t *)Af;
     if (cin == 1 && cout == NN_C)
-        k_nn_layer1_mfma<NN_C><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
+        k_nn_layer1_mfma<NN_C, REC_BF16><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
     else if (cin == NN_C && cout == NN_C)
-        k_nn_layer8_mfma<NN_C><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
+        k_nn_layer8_mfma<NN_C, REC_BF16><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
     else if (cin == NN_C && cout == 1)
-        k_nn_layer8_mfma<1><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
+        k_nn_layer8_mfma<1, REC_BF16><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
 }
 
 void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {
@@ -542,9 +593,12 @@ void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, c
         k_nn_layer<NN_C, 1><<<grid, 256, 0, c->stream>>>(c->g, in, out, W, c->nn_L);
 }
 
-void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2 *in, float2 *G) {
+void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2 *in, float2 *G, bool bf16_records) {
     dim3 grid(9, (unsigned)cout, (unsigned)cin);
-    k_nn_wgrad<<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, c->nn_L, G);
+    if (bf16_records)
+        k_nn_wgrad<REC_BF16><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, c->nn_L, G);
+    else
+        k_nn_wgrad<REC_F32><<<grid, 256, 0, c->stream>>>(c->g, cin, cout, gout, in, c->nn_L, G);
 }
 
 void launch_nn_adjoint_weights(Ctx *c, int cin, int cout, const float2 *W, float2 *Wt) {

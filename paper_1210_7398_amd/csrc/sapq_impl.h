@@ -252,7 +252,7 @@ constexpr int NN_CIN[3] = {1, NN_C, NN_C};
 constexpr int NN_COUT[3] = {NN_C, NN_C, 1};
 
 void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W);
-void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2 *in, float2 *G);
+void launch_nn_wgrad(Ctx *c, int cin, int cout, const float2 *gout, const float2 *in, float2 *G, bool bf16_records);
 void launch_nn_adjoint_weights(Ctx *c, int cin, int cout, const float2 *W, float2 *Wt);
 void launch_nn_adam(Ctx *c, int n, float *w, const float *grad, float gscale, float *m, float *v, float lr, int t, float *wq);
 void launch_nn_round(Ctx *c, int n, const float *w, float *wq);
