@@ -470,7 +470,7 @@ static void nn_prepare(Ctx *c) {
 static void nn_layer(Ctx *c, int k, const float2 *in, float2 *out) {
     const float2 *W = (const float2 *)c->nn_wq;
     if (nn_use_mfma(c))
-        launch_nn_layer_mfma(c, NN_CIN[k], NN_COUT[k], in, out, c->nn_afrag[k]);
+        launch_nn_layer_mfma(c, NN_CIN[k], NN_COUT[k], in, out, c->nn_afrag[k], SAPQ_FP32, SAPQ_FP32, nullptr);
     else
         launch_nn_layer(c, NN_CIN[k], NN_COUT[k], in, out, W + NN_OFF[k] / 2);
 }
@@ -494,7 +494,7 @@ static void nn_backward(Ctx *c) {
         launch_nn_adjoint_weights(c, NN_CIN[k], NN_COUT[k], W + NN_OFF[k] / 2, c->nn_wt);
         if (nn_use_mfma(c)) {
             launch_nn_afrag(c, NN_COUT[k], NN_CIN[k], c->nn_wt, c->nn_afrag_t);
-            launch_nn_layer_mfma(c, NN_COUT[k], NN_CIN[k], gout, gin[k], c->nn_afrag_t);
+            launch_nn_layer_mfma(c, NN_COUT[k], NN_CIN[k], gout, gin[k], c->nn_afrag_t, SAPQ_FP32, SAPQ_FP32, nullptr);
         } else {
             launch_nn_layer(c, NN_COUT[k], NN_CIN[k], gout, gin[k], c->nn_wt);
         }
@@ -556,11 +556,18 @@ static double2 dot1(Ctx *c, int prec, const void *a, const void *b) {
 }
 
 // z = N p and rp = p - D z, on inner-precision vectors of the context's lattice
-void nn_apply(Ctx *c, const void *p, void *z, void *rp) {
+void nn_apply(Ctx *c, const void *p, void *z, void *rp, const int *skip) {
     const int pi = c->prm.prec_inner;
-    blas_convert(c, SAPQ_FP32, c->nn_a0, pi, p, 1.0);
-    nn_forward(c);
-    blas_convert(c, pi, z, SAPQ_FP32, c->nn_z, 1.0);
+    if (nn_use_mfma(c)) {
+        // the first layer reads p and the last writes z in the inner precision directly
+        launch_nn_layer_mfma(c, NN_CIN[0], NN_COUT[0], p, c->nn_a1, c->nn_afrag[0], pi, SAPQ_FP32, skip);
+        launch_nn_layer_mfma(c, NN_CIN[1], NN_COUT[1], c->nn_a1, c->nn_a2, c->nn_afrag[1], SAPQ_FP32, SAPQ_FP32, skip);
+        launch_nn_layer_mfma(c, NN_CIN[2], NN_COUT[2], c->nn_a2, z, c->nn_afrag[2], SAPQ_FP32, pi, skip);
+    } else {
+        blas_convert(c, SAPQ_FP32, c->nn_a0, pi, p, 1.0);
+        nn_forward(c);
+        blas_convert(c, pi, z, SAPQ_FP32, c->nn_z, 1.0);
+    }
     launch_dslash(c, pi, rp, z);
     blas_xpay(c, pi, rp, p, make_double2(-1, 0), rp);  // rp = p - D z
 }

@@ -939,9 +939,10 @@ static void bprecondition(Batch &B, int src, int dst) {
         Ctx *c = B.ctx[f];
         const BField &F = B.host.f[f];
         const size_t stride = rhs_bytes(c, B.prec);
+        // the network skips sources that have finished (their done flag, read on the device)
         for (int k = 0; k < F.nrhs; ++k)
             nn_apply(c, (const char *)F.iv[src] + k * stride, (char *)F.iv[IV_Z] + k * stride,
-                     (char *)F.iv[IV_RP] + k * stride);
+                     (char *)F.iv[IV_RP] + k * stride, &B.st[F.rhs0 + k].done);
     }
     bmsap(B, IV_RP, dst);
     bxpay(B, dst, dst, CF_ONE, IV_Z, 1);

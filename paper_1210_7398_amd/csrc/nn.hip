@@ -167,6 +167,26 @@ __device__ __forceinline__ void nn_transport(cx<float> t[12], const float2 *__re
     }
 }
 
+// (T_d in)(ib, s) for a one-channel input in the solver's layout and storage type S2
+template <typename S2>
+__device__ __forceinline__ void nn_transport1(cx<float> t[12], const S2 *__restrict__ in, const GeomDev &g,
+                                              const float2 *__restrict__ L, int ib, int s, int d, int nb, int ns) {
+    if (d == 0) {
+        load_spinor(t, in, g, ib, s);
+        return;
+    }
+    cx<float> p[12], u[9];
+    load_spinor(p, in, g, nb, ns);
+    nn_link(u, L, (long)ib * g.Vb + s, d);
+#pragma unroll
+    for (int be = 0; be < 4; ++be) {
+        cx<float> h[3] = {p[3 * be], p[3 * be + 1], p[3 * be + 2]}, o[3];
+        su3_mul(o, u, h, false);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) t[3 * be + a] = o[a];
+    }
+}
+
 // ---------------------------------------------------------------- FP32 layer, weight gradient
 // out[c'] for one output channel c' = blockIdx.y; weights W[9][COUT][CIN][16] complex (float2)
 template <int CIN, int COUT>
@@ -355,14 +375,18 @@ template <int MT, int NT> struct WaveTiles {
 };
 
 // the tile of D (rows (re/im, c', alpha), columns (site, colour)) to the output activation
-template <int COUT, int RT>
-__device__ __forceinline__ void nn_store_tile(float2 *__restrict__ out, const GeomDev &g, int ib, int s0, int nv,
+template <int COUT, int RT, int POUT>
+__device__ __forceinline__ void nn_store_tile(void *__restrict__ out_, const GeomDev &g, int ib, int s0, int nv,
                                               const float (*Dt)[3 * NN_TILE + 1]) {
     constexpr int M = 4 * COUT;
+    float2 *out = reinterpret_cast<float2 *>(out_);
     if constexpr (COUT == 1) {
+        // one channel: the solver's spinor layout in storage precision POUT
+        using S2 = typename Prec<POUT>::S2;
+        S2 *o = reinterpret_cast<S2 *>(out_);
         for (int w = threadIdx.x; w < NN_TILE * 12; w += blockDim.x) {
             const int t = w % NN_TILE, comp = w / NN_TILE, r = comp / 3, col = 3 * t + comp % 3;
-            if (t < nv) out[((size_t)ib * 12 + comp) * g.Vb + s0 + t] = make_float2(Dt[r][col], Dt[M + r][col]);
+            if (t < nv) st(o + ((size_t)ib * 12 + comp) * g.Vb + s0 + t, cx<float>{Dt[r][col], Dt[M + r][col]});
         }
     } else if constexpr (RT == REC_F32) {
         // the tile's records are contiguous: one coalesced sweep of 16-byte pieces (two
@@ -410,10 +434,13 @@ __device__ __forceinline__ void nn_put_b(__hip_bfloat16 (*Bt)[BPAD], int t, int 
 
 // One input channel (the first layer, and the adjoint of the last): the whole reduction
 // index (9 directions x 4 spins, re / im) is one LDS tile.
-template <int COUT, int RT>
-__global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 *__restrict__ in,
+// (skip: nullable flag read at the start; nonzero leaves the output untouched, for sources a
+// batched solve has finished)
+template <int COUT, int RT, int PIN>
+__global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const typename Prec<PIN>::S2 *__restrict__ in,
                                                        float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
-                                                       const float2 *__restrict__ L) {
+                                                       const float2 *__restrict__ L, const int *__restrict__ skip) {
+    if (skip && *skip) return;
     constexpr int K = 36, K2 = 2 * K, K2P = nn_k2p(1), M2P = nn_m2p(COUT);
     constexpr int NS = NN_TILE, NC = 3 * NS, BPAD = K2P + 8, KS = K2P / 16, MT = M2P / 16, NT = NC / 16;
     using WT = WaveTiles<MT, NT>;
@@ -437,7 +464,7 @@ __global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 
     for (int w = threadIdx.x; w < NS * 9; w += blockDim.x) {
         const int t = w % NS, d = w / NS;
         cx<float> T[12];
-        nn_transport<RT>(T, in, 1, g, L, ib, s0 + min(t, nv - 1), d, 0, nb_blk[d][t], nb_slot[d][t]);
+        nn_transport1(T, in, g, L, ib, s0 + min(t, nv - 1), d, nb_blk[d][t], nb_slot[d][t]);
         nn_put_b<BPAD>(Bt, t, 4 * d, K + 4 * d, T);
     }
     for (int w = threadIdx.x; w < NC * (K2P - K2); w += blockDim.x)
@@ -470,7 +497,7 @@ __global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 
     }
     __syncthreads();
     // 3. complex outputs: out[c'](site)[alpha][a] = D[c' 4 + alpha][col] + i D[M + c' 4 + alpha][col]
-    nn_store_tile<COUT, RT>(out, g, ib, s0, nv, Dt);
+    nn_store_tile<COUT, RT, SAPQ_FP32>(out, g, ib, s0, nv, Dt);
 }
 
 // Eight input channels: the reduction index is taken in chunks of two transport directions
@@ -478,10 +505,11 @@ __global__ void __launch_bounds__(256) k_nn_layer1_mfma(GeomDev g, const float2 
 // transports one channel of one site along both directions; the eight threads of a site read
 // the neighbour's record as one contiguous 768-byte piece.  The MFMA consumes the chunk from
 // LDS before the next one; the accumulators stay in registers.
-template <int COUT, int RT>
+template <int COUT, int RT, int POUT>
 __global__ void __launch_bounds__(256, 4) k_nn_layer8_mfma(GeomDev g, const float2 *__restrict__ in,
-                                                       float2 *__restrict__ out, const short4_t *__restrict__ Afrag,
-                                                       const float2 *__restrict__ L) {
+                                                       void *__restrict__ out, const short4_t *__restrict__ Afrag,
+                                                       const float2 *__restrict__ L, const int *__restrict__ skip) {
+    if (skip && *skip) return;
     constexpr int CIN = 8, K = 36 * CIN, K2P = nn_k2p(CIN), M2P = nn_m2p(COUT);
     constexpr int NS = NN_TILE, NC = 3 * NS, KS = K2P / 16, MT = M2P / 16, NT = NC / 16;
     constexpr int CR = 128, BPAD = CR + 8;  // rows of a chunk (local: re 0..63, im 64..127)
@@ -547,7 +575,7 @@ __global__ void __launch_bounds__(256, 4) k_nn_layer8_mfma(GeomDev g, const floa
             for (int q = 0; q < 4; ++q) Dt[WT::mt(wave) * 16 + kq + q][nt * 16 + (lane & 15)] = acc[j][q];
     }
     __syncthreads();
-    nn_store_tile<COUT, RT>(out, g, ib, s0, nv, Dt);
+    nn_store_tile<COUT, RT, POUT>(out, g, ib, s0, nv, Dt);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -572,15 +600,39 @@ void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A) {
     k_nn_afrag<<<(n + 255) / 256, 256, 0, c->stream>>>(cin, cout, W, (__hip_bfloat16 *)A);
 }
 
-void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *Af) {
+void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const void *in, void *out, const void *Af, int p_in, int p_out,
+                          const int *skip) {
     const unsigned grid = nn_grid(c);
     const short4_t *A = (const short4_t *)Af;
-    if (cin == 1 && cout == NN_C)
-        k_nn_layer1_mfma<NN_C, REC_BF16><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
-    else if (cin == NN_C && cout == NN_C)
-        k_nn_layer8_mfma<NN_C, REC_BF16><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
-    else if (cin == NN_C && cout == 1)
-        k_nn_layer8_mfma<1, REC_BF16><<<grid, 256, 0, c->stream>>>(c->g, in, out, A, c->nn_L);
+    const float2 *L = c->nn_L;
+    if (cin == 1 && cout == NN_C) {
+        switch (p_in) {
+        case SAPQ_FP32:
+            k_nn_layer1_mfma<NN_C, REC_BF16, SAPQ_FP32><<<grid, 256, 0, c->stream>>>(c->g, (const float2 *)in, (float2 *)out, A, L, skip);
+            break;
+        case SAPQ_FP16:
+            k_nn_layer1_mfma<NN_C, REC_BF16, SAPQ_FP16><<<grid, 256, 0, c->stream>>>(c->g, (const __half2 *)in, (float2 *)out, A, L, skip);
+            break;
+        case SAPQ_BF16:
+            k_nn_layer1_mfma<NN_C, REC_BF16, SAPQ_BF16><<<grid, 256, 0, c->stream>>>(
+                c->g, (const __hip_bfloat162 *)in, (float2 *)out, A, L, skip);
+            break;
+        }
+    } else if (cin == NN_C && cout == NN_C) {
+        k_nn_layer8_mfma<NN_C, REC_BF16, SAPQ_FP32><<<grid, 256, 0, c->stream>>>(c->g, (const float2 *)in, out, A, L, skip);
+    } else if (cin == NN_C && cout == 1) {
+        switch (p_out) {
+        case SAPQ_FP32:
+            k_nn_layer8_mfma<1, REC_BF16, SAPQ_FP32><<<grid, 256, 0, c->stream>>>(c->g, (const float2 *)in, out, A, L, skip);
+            break;
+        case SAPQ_FP16:
+            k_nn_layer8_mfma<1, REC_BF16, SAPQ_FP16><<<grid, 256, 0, c->stream>>>(c->g, (const float2 *)in, out, A, L, skip);
+            break;
+        case SAPQ_BF16:
+            k_nn_layer8_mfma<1, REC_BF16, SAPQ_BF16><<<grid, 256, 0, c->stream>>>(c->g, (const float2 *)in, out, A, L, skip);
+            break;
+        }
+    }
 }
 
 void launch_nn_layer(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const float2 *W) {

@@ -260,10 +260,13 @@ size_t nn_afrag_elems(int cin, int cout);
 size_t nn_link_elems(const Ctx *c);
 void launch_nn_links(Ctx *c);
 void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A);
-void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const float2 *in, float2 *out, const void *A);
+// p_in / p_out: storage precision of a one-channel input / output (spinor layout); skip:
+// nullable device flag, nonzero leaves the output untouched
+void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const void *in, void *out, const void *A, int p_in, int p_out,
+                          const int *skip);
 void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src);
 // learned stage on inner-precision vectors: z = N p, rp = p - D z
-void nn_apply(Ctx *c, const void *p, void *z, void *rp);
+void nn_apply(Ctx *c, const void *p, void *z, void *rp, const int *skip = nullptr);
 
 // bracket a launch with HIP events when profiling is on
 int prof_begin(Ctx *c, int kind);
