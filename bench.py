@@ -335,17 +335,27 @@ def nn_study(args):
     """The learned-preconditioner workload: the network is trained on the GPU on 2000
     residual->error pairs from the plain SAP solver on four 16^3x32 fields (eps 0.25, seeds
     21-24), then 12 spin-colour point sources are solved at 48^3x96 (seed 31), kappa 0.125, 4^4
-    blocks / 2^4 sub-blocks, with plain SAP and with the learned stage ahead of SAP, each with
-    FP32 and FP16 storage inside an FP64 outer iteration.  Prints one JSON line."""
+    blocks with the autotuned sub-block shape, with plain SAP and with the learned stage ahead
+    of SAP, each with FP32 and FP16 storage inside an FP64 outer iteration.  Prints one JSON
+    line."""
     import torch
 
     from paper_1210_7398_amd import sapq, synth, train_nn
 
-    kappa, B, S = 0.125, (4, 4, 4, 4), (2, 2, 2, 2)
+    kappa, B = 0.125, (4, 4, 4, 4)
     dev = torch.device("cuda:0")
     Lt = (16, 16, 16, 32)
     n_src = int(os.environ.get("SAPQ_NN_SOURCES_PER_FIELD", "100"))
     steps = int(os.environ.get("SAPQ_NN_STEPS", "600"))
+    # the sub-block shape (or the even-odd site order) that the autotuner picks on the first
+    # training field serves the training pairs and every application below
+    U = synth.gauge_field(Lt, 0.25, 21, device=dev)
+    tuner = sapq.Solver(Lt, B, (2, 2, 2, 2), kappa, device=dev)
+    tuner.load_gauge(U)
+    tuner.load_clover(synth.clover_inverse(Lt, U, 1.0, kappa, device=dev))
+    S = tuner.autotune()
+    tuner.close()
+    print(f"# autotuned sub-block {S}", file=sys.stderr, flush=True)
     t0 = time.time()
     sets = []
     for seed in (21, 22, 23, 24):

@@ -209,8 +209,9 @@ int sapq_solve_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *c
 
 /*
  * Autotune the sub-block shape of a context: every sub-block shape whose extents are 2 or more
- * and divide the block is timed on a solve of the point source at the origin (spin 0, colour 0)
- * to 1e-10, and the fastest is kept (the ll ordering, hence the preconditioner, changes with it).
+ * and divide the block, and the even-odd site order {0, 0, 0, 0} where the context's phase
+ * kernel takes it, is timed on a solve of the point source at the origin (spin 0, colour 0)
+ * to 1e-10, and the fastest is kept (the ordering, hence the preconditioner, changes with it).
  * cache_json_path (host, nullable): a JSON file of earlier choices, keyed by lattice, block,
  * kappa and prec_inner; a hit skips the timing, a miss appends the result.  *subblock_out
  * (host, nullable, 4 ints) receives the choice.
