@@ -165,3 +165,31 @@ def test_subblock_change_relays_out_the_fields(torch_cuda, orc, tmp_path):
     z_w, _ = orc.nn_forward(L, U, orc.nn_unflatten(w), r)
     assert relerr(to_host(s.nn_forward(to_dev(r))), z_w) < 1e-5
     s.close()
+
+
+def test_solve_batch_even_odd_order(torch_cuda, orc):
+    """The batched solver with SSOR in even-odd site order (sub-block (0, 0, 0, 0)): every source
+    reaches the true residual with the oracle's D and equals the one-source solve."""
+    from paper_1210_7398_amd import sapq
+
+    kappa, B, S = 0.125, (4, 4, 4, 4), (0, 0, 0, 0)
+    cfg = [((8, 8, 8, 8), 0.25, 51, 3), ((8, 8, 8, 16), 0.2, 52, 2)]
+    solvers, srcs, fields = [], [], []
+    for L, eps, seed, n in cfg:
+        U, F = _field(L, eps, seed, kappa)
+        s = sapq.Solver(L, B, S, kappa, outer="defect", maxit_outer=100)
+        s.load_gauge(to_dev(U))
+        s.load_clover(to_dev(F))
+        b = point_sources(L, n)
+        solvers.append(s)
+        srcs.append(to_dev(b))
+        fields.append((L, U, F, b))
+    xs, stats = sapq.solve_batch(solvers, srcs, tol=1e-10)
+    for (L, U, F, b), x, s in zip(fields, xs, solvers):
+        x = to_host(x)
+        for k in range(b.shape[0]):
+            assert relerr(orc.dslash(L, U, F, kappa, x[k]), b[k]) <= 1e-10
+            x1, _ = s.solve(to_dev(np.ascontiguousarray(b[k])), tol=1e-10)
+            assert relerr(x[k], to_host(x1)) < 1e-8
+    for s in solvers:
+        s.close()
