@@ -128,6 +128,14 @@ size_t sapq_arena_bytes(const sapq_geom *geom, const sapq_params *params);
  * Create a context.  arena: device memory of >= sapq_arena_bytes() bytes, 256-byte
  * aligned, owned by the caller.  stream: hipStream_t (NULL = default stream).
  * Builds the block/sub-block/hyperplane tables on the device.
+ * Environment switches read here (all optional; for study and testing only):
+ *   SAPQ_PARTS=0|1|2        0: four-lane SAP kernels; 1 / 2: one / two workgroups per block
+ *                           for the two-lane phase kernel wherever they fit (default: choose).
+ *   SAPQ_SSOR_THREADS=n     cap on the four-lane kernels' workgroup size (64..1024; default 512).
+ *   SAPQ_NO_STAGING=1       four-lane kernels keep the block's links in HBM instead of LDS.
+ *   SAPQ_HALO_TIMEOUT_TEST=1  every halo wait of a split block times out after 64 polls,
+ *                           so that the SAPQ_EHIP path can be tested.
+ * sapq_solve_batch reads SAPQ_BATCH_NR=1..4 (sources per workgroup; default 1).
  */
 int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, size_t arena_bytes,
                 void *stream, sapq_ctx **out);
