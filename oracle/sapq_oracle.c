@@ -25,6 +25,8 @@
  *                       D_EO/D_OE (pairs in different blocks)
  *   orc_ssor            section 3, "Inverse of block operator": SSOR forward and backward
  *                       substitution in locally-lexicographic (ll) order
+ *   orc_eomr            section 3, the even-odd site-preconditioned block solve the SSOR is
+ *                       measured against (minimal residual on the even-odd reduced block system)
  *   orc_dk              Algorithm 1 (w = D K v), with K of eq. (2.4)
  *   orc_msap            eq. (2.4): M_SAP = K sum_{j<N_SAP} (1 - D K)^j
  *   orc_inner_bicgstab  section 2: BiCGStab preconditioned by M_SAP (textbook van der Vorst)
@@ -40,6 +42,7 @@ typedef double complex dc;
 typedef struct {
     double kappa, omega, tol_inner;
     int n_ssor, n_sap, maxit_inner, maxit_outer, outer_kind;
+    int block_solver; /* 0: SSOR (orc_ssor); 1: even-odd minimal residual (orc_eomr) */
 } orc_params;
 
 typedef struct {
@@ -604,6 +607,106 @@ void orc_ssor(const int *g, const dc *U, const dc *F, const orc_params *p, int c
     free(ord);
 }
 
+/* parity of the block-local coordinate sum of site n (0 = even) */
+static int local_parity(const geom_t *G, long n)
+{
+    int c[4], s = 0;
+    coords(G, n, c);
+    for (int m = 0; m < 4; ++m) s += c[m] % G->B[m];
+    return s & 1;
+}
+
+/* out_n = kappa F(n) sum_{m in block(n)} H_nm in_m on the sites of block colour `colour` and
+ * parity `par`; every other site of out is set to 0 */
+static void k_block(const geom_t *G, const dc *U, const dc *F, double kappa, int colour, int par, const dc *in,
+                    dc *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < G->V; ++n) {
+        dc h[12], fh[12];
+        if (colour_of(G, n) != colour || local_parity(G, n) != par) {
+            for (int i = 0; i < 12; ++i) out[12 * n + i] = 0;
+            continue;
+        }
+        hop_at(G, U, in, n, 1, h);
+        clover_site(F + 72 * n, h, fh);
+        for (int i = 0; i < 12; ++i) out[12 * n + i] = kappa * fh[i];
+    }
+}
+
+/*
+ * x = A_cc v by the even-odd site-preconditioned block solve, on every block of colour
+ * `colour` (the block solver of the cited Luscher SAP, which section 3 compares the SSOR
+ * against at equal cost).  Inside a block, A = 1 - K with K = kappa F H restricted to the
+ * block; a hop changes the parity of the block-local coordinate sum, so with e / o the two
+ * parities A x = v reads x_e - K_eo x_o = v_e, x_o - K_oe x_e = v_o.  Eliminating x_o:
+ *     (1 - K_eo K_oe) x_e = v_e + K_eo v_o,      x_o = v_o + K_oe x_e.
+ * The reduced system is solved by n_mr minimal-residual steps from x_e = 0 (r = rhs):
+ *     p = (1 - K_eo K_oe) r,  alpha = <p, r> / <p, p>,  x_e += alpha r,  r -= alpha p,
+ * alpha taken per block.  n_mr = 2 n_ssor: a step applies K to the odd and then to the even
+ * sites, one application of the block operator, as one SSOR half-sweep does.
+ * Readings: the paper names this solver and the equal-cost comparison only; the reduced
+ * system, the minimal-residual steps and their count are taken from the cited SAP.
+ * Sites of the other colour get x = 0.
+ */
+void orc_eomr(const int *g, const dc *U, const dc *F, const orc_params *p, int colour, const dc *v, dc *x)
+{
+    geom_t G;
+    geom_from(g, &G);
+    init_gamma();
+    const long N = 12 * G.V;
+    long NB = 1;
+    for (int m = 0; m < 4; ++m) NB *= G.L[m] / G.B[m];
+    dc *ve = calloc(N, sizeof(dc)), *vo = calloc(N, sizeof(dc)), *r = calloc(N, sizeof(dc));
+    dc *t = calloc(N, sizeof(dc)), *q = calloc(N, sizeof(dc)), *xe = calloc(N, sizeof(dc));
+    dc *num = calloc(NB, sizeof(dc));
+    double *den = calloc(NB, sizeof(double));
+    for (long n = 0; n < G.V; ++n) {
+        if (colour_of(&G, n) != colour) continue;
+        dc *dst = local_parity(&G, n) == 0 ? ve : vo;
+        for (int i = 0; i < 12; ++i) dst[12 * n + i] = v[12 * n + i];
+    }
+    k_block(&G, U, F, p->kappa, colour, 0, vo, t); /* t_e = K_eo v_o */
+    for (long i = 0; i < N; ++i) r[i] = ve[i] + t[i];
+    const int n_mr = 2 * p->n_ssor;
+    for (int k = 0; k < n_mr; ++k) {
+        k_block(&G, U, F, p->kappa, colour, 1, r, t); /* t_o = K_oe r_e */
+        k_block(&G, U, F, p->kappa, colour, 0, t, q); /* q_e = K_eo t_o */
+        for (long i = 0; i < N; ++i) q[i] = r[i] - q[i]; /* p = (1 - K_eo K_oe) r (zero off the even sites) */
+        for (long b = 0; b < NB; ++b) {
+            num[b] = 0;
+            den[b] = 0;
+        }
+        for (long n = 0; n < G.V; ++n) {
+            const long b = block_of(&G, n);
+            for (int i = 0; i < 12; ++i) {
+                num[b] += conj(q[12 * n + i]) * r[12 * n + i];
+                den[b] += creal(conj(q[12 * n + i]) * q[12 * n + i]);
+            }
+        }
+        for (long n = 0; n < G.V; ++n) {
+            const long b = block_of(&G, n);
+            const dc alpha = den[b] > 0 ? num[b] / den[b] : 0;
+            for (int i = 0; i < 12; ++i) {
+                xe[12 * n + i] += alpha * r[12 * n + i];
+                r[12 * n + i] -= alpha * q[12 * n + i];
+            }
+        }
+    }
+    k_block(&G, U, F, p->kappa, colour, 1, xe, t); /* t_o = K_oe x_e */
+    for (long i = 0; i < N; ++i) x[i] = xe[i] + vo[i] + t[i];
+    free(ve); free(vo); free(r); free(t); free(q); free(xe); free(num); free(den);
+}
+
+/* the block inverse the parameters select: SSOR in ll order, or the even-odd MR solve */
+static void block_solve(const int *g, const dc *U, const dc *F, const orc_params *p, int colour, const dc *v, dc *x)
+{
+    if (p->block_solver == 1)
+        orc_eomr(g, U, F, p, colour, v, x);
+    else
+        orc_ssor(g, U, F, p, colour, NULL, v, x);
+}
+
 /* ------------------------------------------------------------------ SAP: Algorithm 1 and M_SAP */
 
 static void vzero(dc *a, long n) { memset(a, 0, sizeof(dc) * n); }
@@ -622,14 +725,14 @@ void orc_dk(const int *g, const dc *U, const dc *F, const orc_params *p, const d
     dc *xE = malloc(sizeof(dc) * N), *xO = malloc(sizeof(dc) * N);
     dc *wE = malloc(sizeof(dc) * N), *wO = malloc(sizeof(dc) * N);
     dc *fE = malloc(sizeof(dc) * N), *fO = malloc(sizeof(dc) * N);
-    orc_ssor(g, U, F, p, 0, NULL, v, xE);                      /* x_E = A_EE v_E */
+    block_solve(g, U, F, p, 0, v, xE);                         /* x_E = A_EE v_E */
     orc_dslash_part(g, U, F, p->kappa, xE, wO, 2, 1);          /* w_O = D_OE x_E */
     orc_dslash_part(g, U, F, p->kappa, xE, wE, 1, 0);          /* w_E = D_EE x_E */
     for (long n = 0; n < G.V; ++n) {                            /* f_O = v_O - w_O */
         int c = colour_of(&G, n);
         for (int i = 0; i < 12; ++i) fO[12 * n + i] = (c == 1) ? v[12 * n + i] - wO[12 * n + i] : 0;
     }
-    orc_ssor(g, U, F, p, 1, NULL, fO, xO);                     /* x_O = A_OO f_O */
+    block_solve(g, U, F, p, 1, fO, xO);                        /* x_O = A_OO f_O */
     orc_dslash_part(g, U, F, p->kappa, xO, fE, 2, 0);          /* f_E = D_EO x_O */
     orc_dslash_part(g, U, F, p->kappa, xO, fO, 1, 1);          /* f_O = D_OO x_O */
     for (long i = 0; i < N; ++i) {

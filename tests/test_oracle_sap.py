@@ -272,3 +272,103 @@ def test_even_odd_order_invariance_and_difference(orc):
     for seed in (1, 2):
         assert np.array_equal(ref, orc.ssor(L, B, EO, U, F, prm, 0, v, order=_parity_order(B, seed)))
     assert not np.allclose(ref, orc.ssor(L, B, (2, 2, 2, 2), U, F, prm, 0, v))
+
+
+# ----------------------------------------------------------------------------- even-odd MR block solve
+
+
+def _dense_eo_mr(Db, par, v, n_mr):
+    """Textbook even-odd reduction of D_b x = v (Schur complement on the even sites, with a
+    general D_oo^-1), n_mr minimal-residual steps on it from 0, then the odd sites by
+    back-substitution.  Rows of Db in block-local lexicographic order; par per site."""
+    e = np.repeat(par == 0, 12)
+    o = ~e
+    Dee, Deo, Doe, Doo = Db[np.ix_(e, e)], Db[np.ix_(e, o)], Db[np.ix_(o, e)], Db[np.ix_(o, o)]
+    S = Dee - Deo @ np.linalg.solve(Doo, Doe)
+    r = v[e] - Deo @ np.linalg.solve(Doo, v[o])
+    x = np.zeros_like(r)
+    for _ in range(n_mr):
+        p = S @ r
+        a = np.vdot(p, r) / np.vdot(p, p)
+        x = x + a * r
+        r = r - a * p
+    out = np.zeros(len(v), complex)
+    out[e] = x
+    out[o] = np.linalg.solve(Doo, v[o] - Doe @ x)
+    return out
+
+
+@pytest.mark.parametrize("L,B", [((8, 8, 4, 4), (4, 4, 2, 2)), ((8, 4, 4, 8), (4, 2, 2, 4))])
+@pytest.mark.parametrize("n_ssor", [1, 3])
+def test_eomr_equals_dense_even_odd_minimal_residual(orc, L, B, n_ssor):
+    """The even-odd site-preconditioned block solve (the block solver section 3 compares the
+    SSOR against) is textbook minimal residual with 2 n_ssor steps on the Schur complement of
+    the dense block matrix, for both block colours; other-colour sites stay zero."""
+    kappa = 0.12
+    U, F = _fields(L, kappa, 61)
+    prm = orc.params(kappa, n_ssor=n_ssor, block_solver=1)
+    Dense, loc, bid = H.dense_block_diagonal(lambda p: orc.dslash_part(L, B, U, F, kappa, p, 1), L, B)
+    par = _local_coords(B).sum(axis=1) % 2
+    v = synth.gaussian_spinor(L, 62)
+    col = H.block_colour(L, B)
+    for colour in (0, 1):
+        x = orc.eomr(L, B, U, F, prm, colour, v)
+        assert np.abs(x[col != colour]).max() == 0
+        for blk in np.unique(bid[col == colour])[:3]:
+            sites = np.where(bid == blk)[0]
+            sites = sites[np.argsort(loc[sites])]
+            xd = _dense_eo_mr(Dense[blk], par, v[sites].reshape(-1), 2 * n_ssor)
+            assert np.abs(x[sites].reshape(-1) - xd).max() < 1e-12 * np.abs(xd).max()
+
+
+def test_eomr_converges_to_block_inverse_and_residual_decreases(orc):
+    """Many MR steps reach the exact block inverse (dense LU); the block residual of the
+    returned x never grows with the step count (minimal residual on the reduced system, and
+    the odd rows of A x - v vanish by construction)."""
+    L, B = (8, 8, 4, 4), (4, 4, 2, 2)
+    kappa = 0.12
+    U, F = _fields(L, kappa, 63)
+    Dense, loc, bid = H.dense_block_diagonal(lambda p: orc.dslash_part(L, B, U, F, kappa, p, 1), L, B)
+    v = synth.gaussian_spinor(L, 64)
+    col = H.block_colour(L, B)
+    blocks = np.unique(bid[col == 1])[:3]
+    res = []
+    for n_ssor in (1, 2, 4, 8, 40):
+        x = orc.eomr(L, B, U, F, orc.params(kappa, n_ssor=n_ssor, block_solver=1), 1, v)
+        rb = []
+        for blk in blocks:
+            sites = np.where(bid == blk)[0]
+            sites = sites[np.argsort(loc[sites])]
+            vb = v[sites].reshape(-1)
+            rb.append(np.linalg.norm(Dense[blk] @ x[sites].reshape(-1) - vb) / np.linalg.norm(vb))
+            if n_ssor == 40:
+                xl = np.linalg.solve(Dense[blk], vb)
+                assert np.abs(x[sites].reshape(-1) - xl).max() < 1e-10 * np.abs(xl).max()
+        res.append(max(rb))
+    assert all(res[i + 1] <= res[i] * (1 + 1e-12) for i in range(len(res) - 1)), res
+    assert res[0] < 0.5 and res[-1] < 1e-10, res
+
+
+def test_eomr_in_msap(orc):
+    """With block_solver = 1, Algorithm 1 uses the MR block inverse for A_EE and A_OO: x_E of
+    DK equals the MR solve of v_E; D K v = D x; and M_SAP still converges to D^-1 (dense LU)
+    while differing from the SSOR-preconditioned M_SAP."""
+    L, B, S = GEOMS[0]
+    kappa = 0.12
+    U, F = _fields(L, kappa, 65)
+    col = H.block_colour(L, B)
+    v = synth.gaussian_spinor(L, 66)
+    prm = orc.params(kappa, n_ssor=2, block_solver=1)
+    x, w = orc.dk(L, B, S, U, F, prm, v)
+    assert np.array_equal(x[col == 0], orc.eomr(L, B, U, F, prm, 0, v)[col == 0])
+    assert np.abs(w - orc.dslash(L, U, F, kappa, x)).max() < 1e-13 * np.abs(w).max()
+    y_s, _ = orc.msap(L, B, S, U, F, orc.params(kappa, n_ssor=2), v)
+    y_m, _ = orc.msap(L, B, S, U, F, prm, v)
+    assert not np.allclose(y_s, y_m)
+    L2, B2 = (4, 4, 4, 4), (2, 2, 2, 2)
+    U2, F2 = _fields(L2, kappa, 67)
+    D = H.dense_operator(lambda p: orc.dslash(L2, U2, F2, kappa, p), 256)
+    v2 = synth.gaussian_spinor(L2, 68)
+    xs = np.linalg.solve(D, v2.reshape(-1))
+    y, _ = orc.msap(L2, B2, B2, U2, F2, orc.params(kappa, n_ssor=4, n_sap=64, block_solver=1), v2)
+    assert np.linalg.norm(y.reshape(-1) - xs) < 1e-6 * np.linalg.norm(xs)
