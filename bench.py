@@ -139,18 +139,22 @@ def _solve_stats(s, bd, steps):
     return sorted(times)[len(times) // 2], st, (1e3 * (ph[0].get("ms", 0) + ph[1].get("ms", 0)) / n_ph) if n_ph else None
 
 
-# SAP block and sub-block shapes of the block-shape study at 24^3x48 (sub-block = block is the
-# natural-order SSOR; sub-block (0, 0, 0, 0) the even-odd site order that the paper measures
-# the ll ordering against)
-BLOCK_SHAPES = [((6, 6, 6, 12), (3, 3, 3, 6)), ((6, 6, 6, 12), (2, 2, 2, 4)), ((6, 6, 6, 12), (3, 3, 3, 3)),
-                ((6, 6, 6, 12), (6, 6, 6, 12)), ((6, 6, 6, 6), (3, 3, 3, 3)), ((6, 6, 6, 6), (2, 2, 2, 2)),
-                ((6, 6, 6, 6), (6, 6, 6, 6)), ((6, 6, 6, 6), (0, 0, 0, 0)), ((4, 4, 4, 4), (2, 2, 2, 2)),
-                ((4, 4, 4, 4), (4, 4, 4, 4)), ((4, 4, 4, 4), (0, 0, 0, 0))]
+# (block, sub-block, block solver) of the block study at 24^3x48: sub-block = block is the
+# natural-order SSOR, sub-block (0, 0, 0, 0) the even-odd site order; "eomr" replaces the SSOR
+# by the even-odd site-preconditioned minimal-residual block solve at the same cost (the block
+# solvers the paper measures the ll-ordered SSOR against)
+BLOCK_SHAPES = [((6, 6, 6, 12), (3, 3, 3, 6), "ssor"), ((6, 6, 6, 12), (2, 2, 2, 4), "ssor"),
+                ((6, 6, 6, 12), (3, 3, 3, 3), "ssor"), ((6, 6, 6, 12), (6, 6, 6, 12), "ssor"),
+                ((6, 6, 6, 6), (3, 3, 3, 3), "ssor"), ((6, 6, 6, 6), (2, 2, 2, 2), "ssor"),
+                ((6, 6, 6, 6), (6, 6, 6, 6), "ssor"), ((6, 6, 6, 6), (0, 0, 0, 0), "ssor"),
+                ((6, 6, 6, 6), (0, 0, 0, 0), "eomr"), ((4, 4, 4, 4), (2, 2, 2, 2), "ssor"),
+                ((4, 4, 4, 4), (4, 4, 4, 4), "ssor"), ((4, 4, 4, 4), (0, 0, 0, 0), "ssor"),
+                ((4, 4, 4, 4), (0, 0, 0, 0), "eomr")]
 
 
 def blocks_study(args):
-    """Block and sub-block shapes at 24^3x48 (the default workload's fields and source): M_SAP
-    applications and time to 1e-10 for each shape, with the phase kernel each one runs."""
+    """Block and sub-block shapes and block solvers at 24^3x48 (the default workload's fields and
+    source): M_SAP applications and time to 1e-10 for each, with the phase kernel each runs."""
     import torch
 
     from paper_1210_7398_amd import sapq
@@ -161,12 +165,13 @@ def blocks_study(args):
     Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
     del U, F
     res = []
-    for B, S in BLOCK_SHAPES:
-        s = sapq.Solver(w["L"], B, S, w["kappa"], device=dev)
+    for B, S, solver in BLOCK_SHAPES:
+        s = sapq.Solver(w["L"], B, S, w["kappa"], device=dev, block_solver=solver)
         s.load_gauge(Ud)
         s.load_clover(Fd)
         t, st, ph_us = _solve_stats(s, bd, args.steps)
-        res.append(dict(block=list(B), subblock=list(S), phase_kernel=s.phase_kernel, time_s=t, n_msap=st["n_msap"],
+        res.append(dict(block=list(B), subblock=list(S), block_solver=solver, phase_kernel=s.phase_kernel, time_s=t,
+                        n_msap=st["n_msap"],
                         inner_its=st["inner_its"], outer_its=st["outer_its"], true_relres=st["true_relres"],
                         sap_phase_avg_us=ph_us))
         print(f"# {res[-1]}", file=sys.stderr, flush=True)

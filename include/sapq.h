@@ -85,7 +85,7 @@ typedef struct {
  * n_sap: N_SAP of eq. (2.4).  tol_inner / maxit_inner: relative residual target and
  * iteration cap of the inner BiCGStab.  maxit_outer: outer iteration cap.
  * prec_inner: storage precision of SAP + inner solver (SAPQ_FP32, _FP16, _BF16).
- * outer: sapq_outer.  flags: SAPQ_FLAG_GUESS | SAPQ_FLAG_PROFILE.
+ * outer: sapq_outer.  flags: SAPQ_FLAG_* below.
  */
 typedef struct {
     double kappa, omega, tol_inner;
@@ -100,6 +100,16 @@ typedef struct {
 #define SAPQ_FLAG_NN 4      /* reserve the learned stage (at sapq_create) and use it in the inner
                                solver once weights are set (see sapq_nn_*) */
 #define SAPQ_FLAG_NN_FP32 8 /* learned-stage layers in FP32 FMAs instead of BF16 MFMA */
+/* Block inverses A_EE, A_OO by the even-odd site-preconditioned block solve that section 3
+ * measures the SSOR against, instead of the SSOR: inside a block, the system reduced to the
+ * even sites, (1 - K_eo K_oe) x_e = v_e + K_eo v_o with K = kappa F H in the block, gets
+ * 2 n_ssor minimal-residual steps from 0 (the cost of n_ssor symmetric SSOR sweeps), then
+ * x_o = v_o + K_oe x_e.  Needs the even-odd site order (subblock {0, 0, 0, 0}), an even
+ * number of sites per block and a block whose vector fits one workgroup's LDS (96 bytes per
+ * site: at most 1700 sites in gfx950's 160 KiB) (sapq_create: SAPQ_ESHAPE; sapq_set_params:
+ * SAPQ_EINVAL).  omega is unused.  sapq_autotune and sapq_solve_batch refuse such a context
+ * (SAPQ_EINVAL). */
+#define SAPQ_FLAG_EOMR 16
 
 /* Per-solve statistics (host struct). */
 typedef struct {
@@ -165,8 +175,9 @@ int sapq_dslash(sapq_ctx *ctx, double *out, const double *in, int prec);
 /*
  * x = A_cc v: the SSOR approximate inverse of the block operator on every block of
  * colour `colour` (0 = E, 1 = O), section 3 "Inverse of block operator": from x = 0,
- * n_ssor forward+backward substitution sweeps in locally-lexicographic order.  Runs in
- * the inner precision.  Sites of the other colour get x = 0.
+ * n_ssor forward+backward substitution sweeps in locally-lexicographic order (with
+ * SAPQ_FLAG_EOMR: the even-odd minimal-residual block solve instead).  Runs in the inner
+ * precision.  Sites of the other colour get x = 0.
  */
 int sapq_ssor(sapq_ctx *ctx, double *x, const double *v, int colour);
 

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsapq.so")
-SOURCES = ["api.hip", "kernels.hip", "sap_parts.hip", "nn.hip", "batch.hip"]
+SOURCES = ["api.hip", "kernels.hip", "sap_parts.hip", "sap_eomr.hip", "nn.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -296,6 +296,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     if ((long)c->lds_extra > (long)device_max_lds()) { delete h; set_error("block too large for LDS tables"); return SAPQ_ESHAPE; }
     if (T.nplanes > MAX_PLANES) { delete h; set_error("too many hyperplanes"); return SAPQ_ESHAPE; }
     if (c->ssor_threads > 512 && !getenv("SAPQ_SSOR_THREADS")) { delete h; set_error("hyperplane too large"); return SAPQ_ESHAPE; }
+    if ((params->flags & SAPQ_FLAG_EOMR) && !eomr_supported(c, why)) { delete h; set_error(why); return SAPQ_ESHAPE; }
     if (arena_bytes < need) {
         delete h;
         set_error("arena too small: need " + std::to_string(need) + " bytes");
@@ -338,7 +339,7 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     }
     rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (rc) { hipHostFree(c->host_res); delete h; return rc; }
-    if (set_sap_lds_limits(c) || set_parts_lds_limit(c)) {
+    if (set_sap_lds_limits(c) || set_parts_lds_limit(c) || set_eomr_lds_limit(c)) {
         hipHostFree(c->host_res);
         delete h;
         set_error("hipFuncSetAttribute refused the LDS size of the SAP kernel");
@@ -354,6 +355,7 @@ int sapq_set_params(sapq_ctx *h, const sapq_params *p) {
     int rc = check_params(p, why);
     if (rc) { set_error(why); return rc; }
     if (p->prec_inner != h->c.prm.prec_inner) { set_error("prec_inner is fixed at creation"); return SAPQ_EINVAL; }
+    if ((p->flags & SAPQ_FLAG_EOMR) && !eomr_supported(&h->c, why)) { set_error(why); return SAPQ_EINVAL; }
     h->c.prm = *p;
     return SAPQ_OK;
 }
@@ -950,6 +952,10 @@ int sapq_autotune(sapq_ctx *h, const char *cache_json_path, int *subblock_out) {
     Ctx *c = &h->c;
     int rc = ready(c);
     if (rc) return rc;
+    if (c->prm.flags & SAPQ_FLAG_EOMR) {
+        set_error("autotune chooses the SSOR site ordering; the even-odd MR block solver has none to choose");
+        return SAPQ_EINVAL;
+    }
     const std::string key = tune_key(c);
     // cache: one JSON object per line, {"key": "...", "subblock": [a, b, c, d], "time_s": t}
     if (cache_json_path) {

@@ -792,6 +792,7 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
             if (c->prm.prec_inner != c0->prm.prec_inner) { why = "all contexts need the same prec_inner"; return SAPQ_EINVAL; }
         }
         if (!c->have_U || !c->have_F) { why = "fields must be loaded in every context"; return SAPQ_ESTATE; }
+        if (c->prm.flags & SAPQ_FLAG_EOMR) { why = "the batched solver runs the SSOR block inverses only"; return SAPQ_EINVAL; }
         B.max_rhs = std::max(B.max_rhs, nrhs[f]);
         B.max_V = std::max(B.max_V, c->V);
     }

@@ -667,6 +667,10 @@ int set_sap_lds_limits(Ctx *c) {
 }
 
 void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r, void *x, void *y) {
+    if (c->prm.flags & SAPQ_FLAG_EOMR) {
+        launch_sap_phase_eomr(c, colour, (colour == 1 || !first) ? 1 : 0, first ? 1 : 0, 0, rsrc, r, x, y);
+        return;
+    }
     if (c->use_parts) {
         launch_sap_phase_parts(c, colour, (colour == 1 || !first) ? 1 : 0, first ? 1 : 0, 0, rsrc, r, x, y);
         return;
@@ -683,6 +687,10 @@ void launch_sap_phase(Ctx *c, int colour, bool first, const void *rsrc, void *r,
 }
 
 void launch_ssor_only(Ctx *c, int colour, const void *v, void *x) {
+    if (c->prm.flags & SAPQ_FLAG_EOMR) {
+        launch_sap_phase_eomr(c, colour, 0, 1, 1, v, nullptr, x, nullptr);
+        return;
+    }
     if (c->use_parts) {
         launch_sap_phase_parts(c, colour, 0, 1, 1, v, nullptr, x, nullptr);
         return;

@@ -163,6 +163,11 @@ void launch_sap_face(Ctx *c, int colour, void *r, const void *x);
 void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_only, const void *rsrc, void *r,
                             void *x, void *y);
 int set_parts_lds_limit(Ctx *c);
+// the even-odd minimal-residual block solve (SAPQ_FLAG_EOMR) in place of the SSOR
+bool eomr_supported(const Ctx *c, std::string &why);
+void launch_sap_phase_eomr(Ctx *c, int colour, int gather, int first, int ssor_only, const void *rsrc, void *r,
+                           void *x, void *y);
+int set_eomr_lds_limit(Ctx *c);
 void launch_sap_face_2l(Ctx *c, int colour, void *r, const void *x);
 void launch_ssor_only(Ctx *c, int colour, const void *v, void *x);
 

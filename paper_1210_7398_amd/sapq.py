@@ -16,7 +16,7 @@ _LIB = None
 
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 OUTER_FBICGSTAB, OUTER_DEFECT = 0, 1
-FLAG_GUESS, FLAG_PROFILE, FLAG_NN, FLAG_NN_FP32 = 1, 2, 4, 8
+FLAG_GUESS, FLAG_PROFILE, FLAG_NN, FLAG_NN_FP32, FLAG_EOMR = 1, 2, 4, 8, 16
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOTSU3", -4: "ENOTCONV", -5: "EBREAKDOWN", -6: "EHIP",
           -7: "ENOMEM", -8: "ESTATE"}
@@ -123,12 +123,15 @@ class Solver:
 
     def __init__(self, L, block, subblock, kappa, bc=(1, 1, 1, 1), omega=1.0, n_ssor=4, n_sap=4, tol_inner=0.1,
                  maxit_inner=50, maxit_outer=100, prec="fp32", outer="fbicgstab", device=None, nn=False,
-                 nn_fp32=False):
+                 nn_fp32=False, block_solver="ssor"):
         self.L = tuple(L)
         self.V = int(L[0] * L[1] * L[2] * L[3])
         self.geom = Geom((ctypes.c_int * 4)(*L), (ctypes.c_int * 4)(*block), (ctypes.c_int * 4)(*subblock),
                          (ctypes.c_int * 4)(*bc))
-        self.base_flags = (FLAG_NN if nn else 0) | (FLAG_NN_FP32 if nn_fp32 else 0)
+        if block_solver not in ("ssor", "eomr"):
+            raise ValueError("block_solver must be 'ssor' or 'eomr'")
+        self.base_flags = ((FLAG_NN if nn else 0) | (FLAG_NN_FP32 if nn_fp32 else 0) |
+                           (FLAG_EOMR if block_solver == "eomr" else 0))
         self.params = Params(kappa, omega, tol_inner, n_ssor, n_sap, maxit_inner, maxit_outer, PREC[prec],
                              OUTER_FBICGSTAB if outer == "fbicgstab" else OUTER_DEFECT, self.base_flags)
         self.prec = prec
