@@ -68,14 +68,19 @@ def test_sap_precondition(torch_cuda, orc, name):
     s.close()
 
 
-def test_sap_precondition_fp16(torch_cuda, orc):
-    name = "8^4/4^4"
-    s, L, B, kappa, bc, U, F = _setup(name, prec="fp16")
+# M_SAP tolerances of the low-precision storage parity tests (unit roundoff 2^-11 / 2^-8)
+MSAP_TOL = {"fp16": 1e-2, "bf16": 8e-2}
+
+
+@pytest.mark.parametrize("prec", ["fp16", "bf16"])
+@pytest.mark.parametrize("name", ["8^4/4^4", "12^4/6^4 antiperiodic"])
+def test_sap_precondition_low_precision(torch_cuda, orc, name, prec):
+    s, L, B, kappa, bc, U, F = _setup(name, prec=prec)
     v = synth.gaussian_spinor(L, 14)
     y_w, dy_w = orc.msap(L, B, EO, U, F, orc.params(kappa, block_solver=1), v, bc=bc)
     y, dy = s.sap_precondition(to_dev(v))
-    assert relerr(to_host(y), y_w) < 1e-2
-    assert relerr(to_host(dy), dy_w) < 1e-2
+    assert relerr(to_host(y), y_w) < MSAP_TOL[prec]
+    assert relerr(to_host(dy), dy_w) < MSAP_TOL[prec]
     s.close()
 
 
@@ -89,6 +94,23 @@ def test_solve_true_residual(torch_cuda, orc, name, prec):
     assert relerr(orc.dslash(L, U, F, kappa, x, bc=bc), b) <= 1e-10, st
     xo, _, ok = orc.solve(L, B, EO, U, F, orc.params(kappa, block_solver=1), b, tol=1e-12, bc=bc)
     assert ok and relerr(x, xo) < 1e-8
+    s.close()
+
+
+def test_solve_with_learned_stage(torch_cuda, orc):
+    """The learned stage ahead of the MR-preconditioned M_SAP (z = N r + M_SAP (r - D N r)):
+    the solve still reaches the FP64 true residual with the oracle's operator."""
+    import torch
+
+    from paper_1210_7398_amd import sapq
+
+    s, L, B, kappa, bc, U, F = _setup("8^4/4^4", nn=True)
+    g = torch.Generator(device="cpu").manual_seed(19)
+    s.nn_set_weights((0.02 * torch.randn(sapq.nn_param_count(), generator=g)).float().cuda())
+    s.use_nn(True)
+    b = synth.gaussian_spinor(L, 20)
+    x, st = s.solve(to_dev(b), tol=1e-10)
+    assert relerr(orc.dslash(L, U, F, kappa, to_host(x), bc=bc), b) <= 1e-10, st
     s.close()
 
 
