@@ -212,6 +212,38 @@ def nsap_study(args):
                       "kappa": w["kappa"], "tol": 1e-10, "results": res}), flush=True)
 
 
+def omega_study(args):
+    """SSOR relaxation omega (the paper gives none; the workload uses 1) at 24^3x48 with the
+    workload's fields and blocks: time to 1e-10 and M_SAP applications of the workload's source
+    for omega from 0.8 to 1.4, and the M_SAP applications of three more Gaussian sources."""
+    import torch
+
+    from paper_1210_7398_amd import sapq, synth
+
+    w = WORKLOADS["24^3x48"]
+    U, F, b = make_inputs(w)
+    dev = torch.device("cuda:0")
+    Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
+    extra = [torch.from_numpy(synth.gaussian_spinor(w["L"], w["seed_b"] + k)).to(dev) for k in (1, 2, 3)]
+    del U, F
+    res = []
+    for omega in (0.8, 0.9, 1.0, 1.1, 1.2, 1.3, 1.4):
+        s = sapq.Solver(w["L"], w["B"], w["S"], w["kappa"], omega=omega, maxit_outer=400, device=dev)
+        s.load_gauge(Ud)
+        s.load_clover(Fd)
+        t, st, ph_us = _solve_stats(s, bd, args.steps)
+        n_extra = [s.solve(e, tol=1e-10)[1]["n_msap"] for e in extra]
+        res.append(dict(omega=omega, time_s=t, n_msap=st["n_msap"], inner_its=st["inner_its"],
+                        outer_its=st["outer_its"], true_relres=st["true_relres"], sap_phase_avg_us=ph_us,
+                        n_msap_more_sources=n_extra))
+        print(f"# {res[-1]}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    print(json.dumps({"mode": "omega", "lattice": list(w["L"]), "block": list(w["B"]), "subblock": list(w["S"]),
+                      "kappa": w["kappa"], "tol": 1e-10, "results": res}), flush=True)
+
+
 def msap_flops(B, V, n_ssor=4, n_sap=4):
     """Algorithmic flops of one M_SAP application on V sites (phase model, Table 1 counts)."""
     face = sum(2.0 / b for b in B)
@@ -531,7 +563,7 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision", "batch", "nn", "blocks",
-                                                        "sustained", "nsap"])
+                                                        "sustained", "nsap", "omega"])
     ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -555,6 +587,9 @@ def main():
         return
     if args.mode == "nsap":
         nsap_study(args)
+        return
+    if args.mode == "omega":
+        omega_study(args)
         return
     if args.mode == "sustained":
         sustained_study(args)
