@@ -265,7 +265,6 @@ bool eomr_supported(const Ctx *c, std::string &why) {
         why = "the even-odd MR block solver needs a block whose vector fits one workgroup's LDS";
         return false;
     }
-    // the block vector (dynamic LDS) and the reduction slots (static) within gfx950's 160 KiB
     if (c->part_threads > 64 * EOMR_WAVES || c->part_threads % 64 || eomr_k(c) > EOMR_MAXK ||
         c->parts_lds + 3 * EOMR_WAVES * sizeof(double) > 160 * 1024) {
         why = "block too large for the even-odd MR block solver";
