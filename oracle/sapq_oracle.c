@@ -493,7 +493,7 @@ double orc_plaquette(const int *g, const dc *U)
  * index of the sub-block.  order[k] is the block-local lexicographic index of
  * the k-th site.
  *
- * A sub-block shape of all zeros selects the even-odd site ordering that Sec. 3.2
+ * A sub-block shape of all zeros selects the even-odd site ordering that section 3 ("Inverse of block operator")
  * compares the ll ordering against: the sites whose block-local coordinates have an
  * even sum, in lexicographic order, then the odd ones.  (Reading: the parity is taken
  * inside the block; the paper does not say, and for SSOR on one block only the

@@ -1,19 +1,24 @@
-"""Build libsapq.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libsapq.so (HIP, gfx950) in-tree with hipcc.
+
+Every source is compiled to an object of its own, in parallel, and the objects are linked
+into one shared library; kernels are launched from the file that defines them, so no
+relocatable device code is needed."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libsapq.so")
-SOURCES = ["api.hip", "kernels.hip", "sap_parts.hip", "sap_eomr.hip", "nn.hip", "batch.hip"]
+OBJ = os.path.join(HERE, "_build")
+SOURCES = ["api.hip", "kernels.hip", "sap_parts.hip", "sap_eomr.hip", "nn.hip", "batch.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -22,8 +27,21 @@ HIPCC_FLAGS = [
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-o", OUT + ".tmp", *srcs]
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+
+    def compile_one(s):
+        obj = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
+        cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-c", "-o", obj, os.path.join(CSRC, s)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, srcs))
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", OUT + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -187,12 +187,16 @@ static int upload_parts(Ctx *c, const PartTables &PT) {
 // ticket counter out of step) is recorded on the device and turned into an error here.
 static int parts_status(Ctx *c) {
     if (!c->use_parts || c->sap_np < 2) return SAPQ_OK;
-    unsigned flag = 0;
-    int rc = hipcheck(hipMemcpyAsync(&flag, c->xsync + 3, sizeof flag, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync(sync)");
+    unsigned sync[4] = {0, 0, 0, 0};
+    int rc = hipcheck(hipMemcpyAsync(sync, c->xsync, sizeof sync, hipMemcpyDeviceToHost, c->stream), "hipMemcpyAsync(sync)");
     if (rc == SAPQ_OK) rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (rc) return rc;
+    const unsigned flag = sync[3];
     if (flag == 0) return SAPQ_OK;
-    (void)hipMemsetAsync(c->xsync, 0, 4 * sizeof(unsigned), c->stream);
+    // counters restart, the epoch moves past every epoch the exchange array may still hold
+    unsigned next[4];
+    parts_sync_after_error(sync, next);
+    (void)hipMemcpyAsync(c->xsync, next, sizeof next, hipMemcpyHostToDevice, c->stream);
     (void)hipStreamSynchronize(c->stream);
     set_error(flag == 1 ? "SAP phase: a workgroup timed out waiting for the other half of its block"
                         : "SAP phase: workgroup ticket counter out of step");

@@ -2,7 +2,7 @@
 // LDS as a whole: the block is split along t into two workgroups ("parts"), each holding
 // the iterate of its own half in LDS.  It computes exactly what k_sap_phase computes
 // (Algorithm 1 fused with the M_SAP update, the locally-lexicographic SSOR in hyperplane
-// order of the sub-block-local coordinates, Sec. 3.2 and Fig. 2):
+// order of the sub-block-local coordinates, section 3 "Inverse of block operator" and Fig. 1):
 //   v_c = r_c + kappa F sum_{hops leaving the block} H x_other
 //   x_c = n_ssor forward + backward sweeps from 0,  y_c += x_c,  r_c = v_c - D_cc x_c.
 //

@@ -1,5 +1,5 @@
 // Host-side geometry tables of libsapq (no HIP dependency): the slot order of a block
-// (hyperplanes of the locally-lexicographic SSOR, Sec. 3.2), neighbour tables, the block
+// (hyperplanes of the locally-lexicographic SSOR, section 3 "Inverse of block operator", Fig. 1), neighbour tables, the block
 // colouring, and the split of a block into two workgroups for the two-lanes-per-site
 // phase kernel.  Used by api.hip and compiled on its own by the host-logic tests.
 #pragma once
@@ -27,7 +27,7 @@ struct HostTables {
 // An all-zero sub-block shape asks for the even-odd site order instead of the ll order:
 // first the sites of the block whose block-local coordinates have an even sum, then the odd
 // ones, each in lexicographic order.  This is the ordering the paper compares the ll order
-// against (Sec. 3.2); its two hyperplanes are the two parities.
+// against (section 3, "Inverse of block operator"); its two hyperplanes are the two parities.
 inline bool eo_order(const sapq_geom *G) {
     return G->subblock[0] == 0 && G->subblock[1] == 0 && G->subblock[2] == 0 && G->subblock[3] == 0;
 }
@@ -272,6 +272,19 @@ inline bool build_parts(const sapq_geom *G, const HostTables &T, int NP, PartTab
         if (s0[1] != s0[0] || s1[H] != s1[H - 1]) return false;
     }
     return true;
+}
+
+// Sync words of the split phase kernel ([0] ticket, [1] done, [2] epoch, [3] error) to use
+// after a launch that raised the error word.  The halo words that launch left in the
+// exchange array carry its epoch (or an earlier one), so the epoch only moves forward: the
+// next launch must never tag its words like the failed one, or a part could take a stale
+// word for a current one.  Ticket and done counts restart from zero (a workgroup that found
+// the ticket counter out of step returned without counting itself done).
+inline void parts_sync_after_error(const unsigned in[4], unsigned out[4]) {
+    out[0] = 0u;
+    out[1] = 0u;
+    out[2] = in[2] + 1u;
+    out[3] = 0u;
 }
 
 }  // namespace sapq

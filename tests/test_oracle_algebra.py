@@ -69,3 +69,48 @@ def test_clover_gauge_covariance(orc):
     F = orc.clover_inv(L, U, 1.0, 0.13)
     Fg = orc.clover_inv(L, H.gauge_transform(L, U, g), 1.0, 0.13)
     assert np.abs(Fg - H.transform_clover(F, g)).max() < 1e-13
+
+
+def _abelian_flux_links(L, mu, nu, k):
+    """U_nu(n) = exp(i phi n_mu T), T = diag(1, -1, 0), phi = 2 pi k / L_mu; all other links 1.
+    Every mu-nu plaquette leaf around any site is then exp(i phi T) (the flux closes
+    periodically because phi L_mu is a multiple of 2 pi and T has integer eigenvalues)."""
+    V = int(np.prod(L))
+    U = synth.unit_gauge(L).copy()
+    phi = 2 * np.pi * k / L[mu]
+    nmu = H.coords(L)[:, mu]
+    ph = np.exp(1j * phi * np.outer(nmu, [1.0, -1.0, 0.0]))  # [V, 3] diagonal of exp(i phi n_mu T)
+    U[:, nu] = 0
+    for a in range(3):
+        U[:, nu, a, a] = ph[:, a]
+    assert U.shape == (V, 4, 3, 3)
+    return U, phi
+
+
+@pytest.mark.parametrize("mu,nu", [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)])
+def test_clover_uniform_abelian_flux_closed_form(orc, mu, nu):
+    """Eq. (2.2)'s clover term for a uniform abelian flux through the mu-nu planes.  The four
+    leaves are exp(i phi T), so the clover field strength is exactly F_mu_nu = sin(phi) T, every
+    other plane carries none, and A = 1 - (c_SW kappa / 2) sum_{rho != sigma} sigma_rho_sigma
+    F_rho_sigma = 1 - c_SW kappa sigma_mu_nu (x) sin(phi) T.  sigma_mu_nu squares to 1, so A has
+    eigenvalues 1 - c_SW kappa sin(phi) (4 times), 1 + c_SW kappa sin(phi) (4 times) and 1 (4
+    times), and on sigma_mu_nu = +1 spinors of colour 0 it is 1 - c_SW kappa sin(phi).  A wrong
+    normalisation (kappa/2 over mu < nu, 1/(4i)) moves the eigenvalues; a flipped sign or a
+    reversed leaf orientation swaps the last eigenvalue with 1 + c_SW kappa sin(phi)."""
+    L = (6, 4, 8, 4)
+    csw, kappa = 1.3, 0.11
+    U, phi = _abelian_flux_links(L, mu, nu, 1)
+    A = orc.clover_A(L, U, csw, kappa)
+    s = np.sin(phi)
+    want = np.sort(np.r_[np.full(4, 1 - csw * kappa * s), np.full(4, 1 + csw * kappa * s), np.ones(4)])
+    g = [orc.gamma(m) for m in range(4)]
+    sig = 0.5j * (g[mu] @ g[nu] - g[nu] @ g[mu])
+    assert np.abs(sig @ sig - np.eye(4)).max() < 1e-15
+    w, X = np.linalg.eigh(sig)
+    plus = X[:, w > 0]  # the two spinors with sigma_mu_nu = +1
+    for n in (0, 17, 100, int(np.prod(L)) - 1):
+        An = A[n]
+        assert np.abs(np.sort(np.linalg.eigvalsh(An)) - want).max() < 1e-14
+        for j in range(2):
+            chi = np.kron(plus[:, j], np.array([1.0, 0.0, 0.0]))  # index 3*alpha + a
+            assert np.abs(An @ chi - (1 - csw * kappa * s) * chi).max() < 1e-14

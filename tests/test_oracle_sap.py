@@ -217,7 +217,7 @@ def _parity_order(B, seed=None):
 @pytest.mark.parametrize("omega", [1.0, 1.3])
 def test_even_odd_ssor_equals_dense_ssor_in_parity_order(orc, L, B, omega):
     """The even-odd site ordering (the alternative the paper measures the ll order against,
-    Sec. 3.2) is textbook SSOR on the block matrix with the even sites ordered first."""
+    section 3, "Inverse of block operator") is textbook SSOR on the block matrix with the even sites ordered first."""
     kappa = 0.12
     U, F = _fields(L, kappa, 41)
     prm = orc.params(kappa, omega=omega, n_ssor=3)

@@ -1,7 +1,8 @@
 """Host logic of the two-workgroup SAP phase kernel: the split tables and the halo
 exchange protocol, emulated on the CPU (tests/host/parts_protocol.cpp) against an
 unsplit hyperplane-order SSOR of a scalar toy operator, bit for bit, under random
-interleavings of the two workgroups (no GPU)."""
+interleavings of the two workgroups, including a launch after one whose waits timed out
+(no GPU)."""
 import os
 import shutil
 import subprocess
