@@ -8,9 +8,12 @@ Fields and source are resident in HBM before the timed region starts.
 
 Prints ONE JSON line.  The roofline object describes the dominant kernel (the
 fused SAP phase kernel: gather, SSOR sweeps, block hop), timed with HIP events
-on the library's stream during the timed solves.  The cpu_baseline object times
-the FP64 oracle on a bounded sample (one M_SAP application and three operator
-applications at the full lattice) and scales it by the solve's operation counts.
+on the library's stream during the timed solves.  The cpu_baseline object is the
+FP64 oracle's own full solve of the same system, timed on the host's threads; the
+accuracy object gives the GPU solution's error against the oracle's 1e-12 solve and
+its true residual with the oracle's operator.  The learned_stage object is the
+NN-augmented FP16 batched solver against the plain FP32 solver at 48^3x96 (12
+point sources), with the network trained on the GPU in the same run.
 """
 import argparse
 import hashlib
@@ -77,6 +80,70 @@ def make_inputs(w):
     return U, F, b
 
 
+def omp_threads(n=None):
+    """Threads the oracle's OpenMP loops use (set to n first if given)."""
+    import ctypes
+
+    import oracle
+
+    oracle.lib()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
+def oracle_reference(w, U, F, b, x_gpu, tol=1e-10, tol_inner=0.1, one_thread_sample=True):
+    """The FP64 CPU oracle beside the GPU solve of the same system (fields, source, blocks,
+    sweeps and inner tolerance).  Returns (cpu_baseline, accuracy):
+    - cpu_baseline: the oracle's full solve to tol, timed at all the threads OpenMP gives it;
+      with one_thread_sample, one DK application (Algorithm 1) and one operator application
+      timed at 1 thread, scaled by the solve's counts as a labelled single-thread estimate;
+    - accuracy: the oracle's solve continued to 1e-12 (x_oracle), the GPU solution's error
+      |x - x_oracle| / |x_oracle|, and its true residual |b - D x| / |b| with the oracle's D."""
+    import oracle
+
+    L, B, S, kappa = w["L"], w["B"], w["S"], w["kappa"]
+    nthreads = omp_threads()
+    prm = oracle.params(kappa, tol_inner=tol_inner)
+    t0 = time.perf_counter()
+    xo, st, ok = oracle.solve(L, B, S, U, F, prm, b, tol=tol)
+    t_solve = time.perf_counter() - t0
+    print(f"# oracle solve to {tol:g}: {t_solve:.1f} s on {nthreads} threads, outer {st['outer']} inner "
+          f"{st['inner']} relres {st['relres']:.2e}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    xo12, st12, ok12 = oracle.solve(L, B, S, U, F, prm, b, tol=1e-12, x0=xo)
+    t12 = time.perf_counter() - t0
+    rr = float(np.linalg.norm(b - oracle.dslash(L, U, F, kappa, x_gpu)) / np.linalg.norm(b))
+    err = float(np.linalg.norm(x_gpu - xo12) / np.linalg.norm(xo12))
+    cpu = dict(value=t_solve, unit="s", cores=nthreads, kind="oracle",
+               sample=(f"full FP64 oracle solve of the same system to {tol:g} from x = 0 (nested flexible "
+                       f"BiCGStab, M_SAP N_SAP 4, SSOR x4, inner tolerance {tol_inner}), timed on {nthreads} "
+                       f"OpenMP threads: {st['outer']} outer and {st['inner']} inner iterations, true relative "
+                       f"residual {st['relres']:.2e}"),
+               converged=bool(ok))
+    if one_thread_sample:
+        omp_threads(1)
+        v = np.ascontiguousarray(b)
+        t0 = time.perf_counter()
+        oracle.dk(L, B, S, U, F, prm, v)
+        t_dk = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.dslash(L, U, F, kappa, v)
+        t_d = time.perf_counter() - t0
+        omp_threads(nthreads)
+        n_dk = 4 * (2 * st["inner"] + 1)  # N_SAP DKs per M_SAP, about two M_SAP per inner iteration
+        cpu["one_thread"] = dict(dk_s=t_dk, dslash_s=t_d, estimate_s=n_dk * t_dk,
+                                 note=("timed sample at 1 thread: one DK application and one operator "
+                                       "application; estimate_s = the solve's ~4 (2 inner + 1) DK "
+                                       "applications times the DK time (an estimate, not a measurement)"))
+    acc = dict(err_vs_oracle=err, true_relres_oracle_D=rr, oracle_relres_1e12=st12["relres"],
+               oracle_continue_to_1e12_s=t12,
+               note=("x_oracle: the oracle's solve continued to 1e-12; err_vs_oracle = |x - x_oracle| / "
+                     "|x_oracle|; true_relres_oracle_D = |b - D x| / |b| with the oracle's D"))
+    return cpu, acc
+
+
 def precision_study(args):
     """The precision workload: one lattice solved with FP32, FP16 and BF16 storage for the SAP
     preconditioner and inner solver, FP64 outer iteration, tol 1e-10.  Prints one JSON line
@@ -91,8 +158,7 @@ def precision_study(args):
     U, F, b = make_inputs(w)
     dev = torch.device("cuda:0")
     Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
-    del U, F
-    res, xref = [], None
+    res, xref, xs = [], None, []
     for prec in ("fp32", "fp16", "bf16"):
         s = sapq.Solver(w["L"], w["B"], w["S"], w["kappa"], prec=prec, outer=args.outer, maxit_outer=400, device=dev)
         s.load_gauge(Ud)
@@ -108,6 +174,7 @@ def precision_study(args):
         if xref is None:
             xref = x.clone()
         diff = float(torch.linalg.vector_norm(x - xref) / torch.linalg.vector_norm(xref))
+        xs.append(x.cpu().numpy())
         ph = st["kernels"].get("phase_E", {}), st["kernels"].get("phase_O", {})
         n_ph = ph[0].get("n", 0) + ph[1].get("n", 0)
         res.append(dict(prec=prec, time_s=sorted(times)[len(times) // 2], outer_its=st["outer_its"],
@@ -118,8 +185,20 @@ def precision_study(args):
         s.close()
         del s
         torch.cuda.empty_cache()
-    print(json.dumps({"mode": "precision", "workload": wl, "outer": args.outer, "tol": 1e-10, "results": res}),
-          flush=True)
+    # the error of every run against the FP64 oracle's own solve of the system to 1e-12
+    import oracle
+
+    del Ud, Fd
+    t0 = time.perf_counter()
+    xo, sto, ok = oracle.solve(w["L"], w["B"], w["S"], U, F, oracle.params(w["kappa"], tol_inner=0.1), b, tol=1e-12)
+    t_or = time.perf_counter() - t0
+    for r, x in zip(res, xs):
+        r["err_vs_oracle"] = float(np.linalg.norm(x - xo) / np.linalg.norm(xo))
+        r["true_relres_oracle_D"] = float(np.linalg.norm(b - oracle.dslash(w["L"], U, F, w["kappa"], x))
+                                          / np.linalg.norm(b))
+    oracle_info = dict(tol=1e-12, converged=bool(ok), relres=sto["relres"], time_s=t_or, threads=omp_threads())
+    print(json.dumps({"mode": "precision", "workload": wl, "outer": args.outer, "tol": 1e-10, "results": res,
+                      "oracle": oracle_info}), flush=True)
 
 
 def _solve_stats(s, bd, steps):
@@ -304,11 +383,12 @@ def batch_study(args):
     kappa, B = 0.125, (4, 4, 4, 4)
     dev = torch.device("cuda:0")
     t0 = time.time()
-    flds = []
+    flds, host_fields = [], []
     for L, eps, seed in BATCH_FIELDS:
         U = synth.gauge_field(L, eps, seed, device=dev)
         F = synth.clover_inverse(L, U, 1.0, kappa, device=dev)
         flds.append((L, U, F))
+        host_fields.append((L, U.cpu().numpy(), F.cpu().numpy()))
         torch.cuda.synchronize()
         print(f"# field {L} ready after {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     print(f"# fields generated on the GPU in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -365,6 +445,23 @@ def batch_study(args):
         "batched_inner_its_total": sum(x["inner_its"] for x in st),
         "one_at_a_time_max_true_relres": max(x["true_relres"] for x in seq_stats),
     }
+    # error against the FP64 oracle's 1e-12 solve for one source per field (spin 0, colour 0);
+    # the other 11 are the same arithmetic on other sources and are checked by their residuals
+    import oracle
+
+    acc = []
+    for (L, U, F), x in zip(host_fields, xs):
+        b0 = synth.point_source(L, 0, 0)
+        x0 = x[0].cpu().numpy()
+        t1 = time.perf_counter()
+        xo, sto, ok = oracle.solve(L, B, S, U, F, oracle.params(kappa, tol_inner=0.1), b0, tol=1e-12)
+        acc.append(dict(lattice=list(L), err_vs_oracle=float(np.linalg.norm(x0 - xo) / np.linalg.norm(xo)),
+                        true_relres_oracle_D=float(np.linalg.norm(b0 - oracle.dslash(L, U, F, kappa, x0))
+                                                   / np.linalg.norm(b0)),
+                        oracle_converged=bool(ok), oracle_s=time.perf_counter() - t1))
+        print(f"# oracle check {acc[-1]}", file=sys.stderr, flush=True)
+    out["accuracy_source0_per_field"] = acc
+    out["oracle_threads"] = omp_threads()
     print(json.dumps(out), flush=True)
 
 
@@ -498,6 +595,165 @@ def nn_study(args):
                       "results": results, "batched": batched}), flush=True)
 
 
+def point_sources(V, ks, dev):
+    """Spin-colour point sources at the origin, source k = (spin k % 4, colour k // 4 % 3)."""
+    import torch
+
+    bb = torch.zeros((len(ks), V, 4, 3), dtype=torch.complex128, device=dev)
+    for j, k in enumerate(ks):
+        bb[j, 0, k % 4, k // 4 % 3] = 1.0
+    return bb
+
+
+def learned_stage_headline(args):
+    """The learned-preconditioner workload, as the default bench line's "learned_stage" object:
+    the network is trained on the GPU on 2000 residual -> error pairs of the plain SAP solver on
+    four 16^3x32 fields (eps 0.25, seeds 21-24), then the 12 spin-colour point sources of a
+    48^3x96 field (seed 31) are solved to 1e-10, kappa 0.125, 4^4 blocks with the autotuned
+    ordering: plain FP32 SAP one source at a time (the reference) against the NN-augmented FP16
+    batched solver (sub-batches of 6), with plain FP16 batched beside them.  Every solution's
+    true residual is checked with the oracle's FP64 D on the host; the error against the oracle
+    is stated on the training lattice, where the oracle's solve is feasible."""
+    import torch
+
+    import oracle
+    from paper_1210_7398_amd import sapq, synth, train_nn
+
+    kappa, B, tol = 0.125, (4, 4, 4, 4), 1e-10
+    dev = torch.device("cuda:0")
+    Lt, La = (16, 16, 16, 32), (48, 48, 48, 96)
+    n_src, steps, sub = 100, args.nn_train_steps, 6
+    t_all = time.time()
+    U = synth.gauge_field(Lt, 0.25, 21, device=dev)
+    F = synth.clover_inverse(Lt, U, 1.0, kappa, device=dev)
+    tuner = sapq.Solver(Lt, B, (2, 2, 2, 2), kappa, device=dev)
+    tuner.load_gauge(U)
+    tuner.load_clover(F)
+    t0 = time.time()
+    S = tuner.autotune()
+    tune_s = time.time() - t0
+    tuner.close()
+    # the error statement on the training lattice: a Gaussian source on field 21, plain FP32
+    s = sapq.Solver(Lt, B, S, kappa, device=dev)
+    s.load_gauge(U)
+    s.load_clover(F)
+    bt = synth.gaussian_spinor(Lt, 2101)
+    xt, _ = s.solve(torch.from_numpy(bt).to(dev), tol=tol)
+    s.close()
+    Uh, Fh = U.cpu().numpy(), F.cpu().numpy()
+    xo, sto, _ = oracle.solve(Lt, B, S, Uh, Fh, oracle.params(kappa, tol_inner=0.1), bt, tol=1e-12)
+    xt = xt.cpu().numpy()
+    train_lattice = dict(lattice=list(Lt), err_vs_oracle=float(np.linalg.norm(xt - xo) / np.linalg.norm(xo)),
+                         true_relres_oracle_D=float(np.linalg.norm(bt - oracle.dslash(Lt, Uh, Fh, kappa, xt))
+                                                    / np.linalg.norm(bt)))
+    del Uh, Fh
+    print(f"# learned stage: sub-block {S}; training-lattice check {train_lattice}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    sets = []
+    for seed in (21, 22, 23, 24):
+        U = synth.gauge_field(Lt, 0.25, seed, device=dev)
+        F = synth.clover_inverse(Lt, U, 1.0, kappa, device=dev)
+        s = sapq.Solver(Lt, B, S, kappa, nn=True, device=dev)
+        s.load_gauge(U)
+        s.load_clover(F)
+        srcs = [torch.from_numpy(synth.gaussian_spinor(Lt, 100 * seed + k)).to(dev) for k in range(n_src)]
+        sets.append((s, train_nn.make_pairs(s, srcs, n_iter=5)))
+    pairs_s = time.time() - t0
+    w0 = train_nn.init_weights(0, device=dev)
+    for s, _ in sets:
+        s.nn_set_weights(w0)
+    t0 = time.time()
+    losses = train_nn.train(sets, steps=steps, batch=8, lr=2e-3, log=100)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    w = sets[-1][0].nn_get_weights().clone()
+    for s, _ in sets:
+        s.close()
+    del sets
+    torch.cuda.empty_cache()
+    print(f"# trained {steps} steps in {train_s:.1f} s (pairs {pairs_s:.1f} s), loss {losses[0]:.3f} -> "
+          f"{np.mean(losses[-20:]):.3f}", file=sys.stderr, flush=True)
+
+    U = synth.gauge_field(La, 0.25, 31, device=dev)
+    F = synth.clover_inverse(La, U, 1.0, kappa, device=dev)
+    V = synth.volume(La)
+    Uh, Fh = U.cpu().numpy(), F.cpu().numpy()
+    ks = list(range(12))
+    bh = point_sources(V, ks, "cpu").numpy()
+
+    def oracle_check(xs):
+        return max(float(np.linalg.norm(bh[j] - oracle.dslash(La, Uh, Fh, kappa, xs[j])) / np.linalg.norm(bh[j]))
+                   for j in range(len(xs)))
+
+    res = {}
+    # reference: plain FP32 SAP, one source at a time, FP64 flexible BiCGStab
+    s = sapq.Solver(La, B, S, kappa, prec="fp32", device=dev)
+    s.load_gauge(U)
+    s.load_clover(F)
+    tot, msap, its, xs = 0.0, 0, 0, []
+    for k in ks:
+        bk = point_sources(V, [k], dev)[0]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, st = s.solve(bk, tol=tol)
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t1
+        msap += st["n_msap"]
+        its += st["inner_its"]
+        xs.append(x.cpu().numpy())
+        del x, bk
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    res["plain_fp32_one_at_a_time"] = dict(time_s=tot, n_msap=msap, inner_its=its,
+                                           max_true_relres_oracle_D=oracle_check(xs))
+    print(f"# plain fp32: {res['plain_fp32_one_at_a_time']}", file=sys.stderr, flush=True)
+    del xs
+    # batched FP16 storage, FP64 defect correction, with and without the learned stage
+    for key, use in (("nn_fp16_batched", True), ("plain_fp16_batched", False)):
+        s = sapq.Solver(La, B, S, kappa, prec="fp16", outer="defect", nn=True, device=dev)
+        s.load_gauge(U)
+        s.load_clover(F)
+        s.nn_set_weights(w)
+        s.use_nn(use)
+        tot, its, xs = 0.0, 0, []
+        for k0 in range(0, len(ks), sub):
+            bb = point_sources(V, ks[k0 : k0 + sub], dev)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            xb, sts = sapq.solve_batch([s], [bb], tol=tol)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t1
+            its += sum(q["inner_its"] for q in sts)
+            xs.extend(list(xb[0].cpu().numpy()))
+            del xb, bb
+        s.close()
+        del s
+        sapq.release_batch_arena()
+        torch.cuda.empty_cache()
+        res[key] = dict(time_s=tot, inner_its=its, sub_batch=sub, max_true_relres_oracle_D=oracle_check(xs))
+        print(f"# {key}: {res[key]}", file=sys.stderr, flush=True)
+        del xs
+    base = res["plain_fp32_one_at_a_time"]["time_s"]
+    return {
+        "metric": "time-to-1e-10 residual (s) of 12 point sources; NN + FP16 batched vs plain FP32 SAP",
+        "workload": (f"48^3x96 clover-Wilson field (eps 0.25, seed 31), kappa 0.125, c_SW 1.0, SAP blocks 4^4, "
+                     f"sub-block {list(S)} (autotuned; 0 = even-odd site order), SSOR x4, N_SAP 4, 12 spin-colour "
+                     "point sources, tol 1e-10; network 1->8->8->1 parallel-transport layers, BF16 MFMA, trained "
+                     f"on the GPU: {steps} Adam steps on {4 * n_src * 5} pairs of four 16^3x32 fields"),
+        "plain_fp32_s": base,
+        "nn_fp16_batched_s": res["nn_fp16_batched"]["time_s"],
+        "speedup_nn_fp16_batched_vs_plain_fp32": base / res["nn_fp16_batched"]["time_s"],
+        "plain_fp16_batched_s": res["plain_fp16_batched"]["time_s"],
+        "speedup_plain_fp16_batched_vs_plain_fp32": base / res["plain_fp16_batched"]["time_s"],
+        "results": res,
+        "train": dict(pair_generation_s=pairs_s, train_s=train_s, steps=steps, loss_first=losses[0],
+                      loss_last20=float(np.mean(losses[-20:])), autotune_s=tune_s),
+        "training_lattice_accuracy": train_lattice,
+        "wall_s": time.time() - t_all,
+    }
+
+
 def phase_model(B, n_ssor, prec_bytes):
     """Algorithmic bytes and flops per site of one SAP phase kernel launch (a cycle after the
     first: it gathers the other colour and accumulates y).  Each operand is counted once."""
@@ -562,6 +818,9 @@ def main():
     ap.add_argument("--workload", default="24^3x48", choices=list(WORKLOADS))
     ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned-stage", dest="learned_stage", action="store_false",
+                    help="leave out the learned-stage headline object (48^3x96, 12 sources)")
+    ap.add_argument("--nn-train-steps", type=int, default=300)
     ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision", "batch", "nn", "blocks",
                                                         "sustained", "nsap", "omega"])
     ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
@@ -675,26 +934,14 @@ def main():
         face=dict(avg_us=k["face"]["avg_us"], launches=k["face"]["launches"]),
     )
 
-    cpu = None
+    cpu, accuracy = None, None
     if not args.no_cpu_baseline:
-        import oracle
+        cpu, accuracy = oracle_reference(w, U, F, b, x.cpu().numpy())
+        print(f"# GPU solution vs oracle: {accuracy}", file=sys.stderr, flush=True)
 
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        prm = oracle.params(w["kappa"])
-        tc = time.perf_counter()
-        oracle.msap(L, B, S, U, F, prm, b)
-        t_msap = time.perf_counter() - tc
-        tc = time.perf_counter()
-        for _ in range(3):
-            oracle.dslash(L, U, F, w["kappa"], b)
-        t_d = (time.perf_counter() - tc) / 3
-        st0 = stats[0]
-        est = st0["n_msap"] * t_msap + st0["n_dslash64"] * t_d
-        cpu = dict(value=est, unit="s", cores=nthreads, kind="oracle",
-                   sample=(f"oracle (FP64, OpenMP) on the full {args.workload} fields: 1 M_SAP application "
-                           f"({t_msap:.2f} s) and 3 operator applications ({t_d:.2f} s each), scaled by the "
-                           f"solve's {st0['n_msap']} M_SAP and {st0['n_dslash64']} operator applications "
-                           "(vector updates not counted)"))
+    learned = None
+    if args.learned_stage:
+        learned = learned_stage_headline(args)
 
     st0 = stats[-1]
     out = {
@@ -722,7 +969,9 @@ def main():
         "cpu_baseline": cpu,
         "solver": dict(outer_its=st0["outer_its"], inner_its=st0["inner_its"], n_msap=st0["n_msap"],
                        n_dslash64=st0["n_dslash64"], true_relres=st0["true_relres"]),
+        "accuracy": accuracy,
         "kernels": kernels,
+        "learned_stage": learned,
     }
     print(json.dumps(out), flush=True)
 

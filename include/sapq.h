@@ -110,6 +110,11 @@ typedef struct {
  * SAPQ_EINVAL).  omega is unused.  sapq_autotune and sapq_solve_batch refuse such a context
  * (SAPQ_EINVAL). */
 #define SAPQ_FLAG_EOMR 16
+/* Reserve FP32 copies of the fields (at sapq_create; an FP16/BF16 context only, else ignored)
+ * so that sapq_solve can fall back to FP32 storage when an inner solve in FP16/BF16 storage
+ * breaks down (see sapq_solve).  Costs 480 bytes per site of fields and widens the inner work
+ * vectors to FP32. */
+#define SAPQ_FLAG_FALLBACK_FP32 32
 
 /* Per-solve statistics (host struct). */
 typedef struct {
@@ -127,7 +132,13 @@ typedef struct {
     double kern_ms[8];
     int kern_n[8];
     double relres_hist[256];
+    int breakdowns;      /* inner solves that broke down (a non-finite scalar) and were redone */
+    int fallback;        /* SAPQ_FALLBACK_* taken during the solve (bit mask) */
 } sapq_stats;
+
+/* sapq_stats.fallback bits */
+#define SAPQ_FALLBACK_NN 1   /* the learned stage was dropped: plain M_SAP for the rest of the solve */
+#define SAPQ_FALLBACK_FP32 2 /* FP16/BF16 storage was replaced by FP32 for the rest of the solve */
 
 enum { SAPQ_K_PHASE_E = 0, SAPQ_K_PHASE_O = 1, SAPQ_K_FACE = 2, SAPQ_K_DSLASH64 = 3, SAPQ_K_BLAS = 4 };
 
@@ -145,6 +156,9 @@ size_t sapq_arena_bytes(const sapq_geom *geom, const sapq_params *params);
  *   SAPQ_NO_STAGING=1       four-lane kernels keep the block's links in HBM instead of LDS.
  *   SAPQ_HALO_TIMEOUT_TEST=1  every halo wait of a split block times out after 64 polls,
  *                           so that the SAPQ_EHIP path can be tested.
+ *   SAPQ_TEST_LOWPREC_NAN=1 every inner solve in FP16/BF16 storage gets a NaN scale for its
+ *                           right-hand side, so that the breakdown and FP32 fallback paths of
+ *                           sapq_solve can be tested (FP32 storage is left alone).
  * sapq_solve_batch reads SAPQ_BATCH_NR=1..4 (sources per workgroup; default 1).
  */
 int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, size_t arena_bytes,
@@ -191,6 +205,13 @@ int sapq_dk(sapq_ctx *ctx, double *x, double *w, const double *v);
 int sapq_sap_precondition(sapq_ctx *ctx, double *out, double *d_out, const double *in);
 
 /*
+ * out = P in for the inner solver's preconditioner P: M_SAP, or, with the learned stage on
+ * (SAPQ_FLAG_NN and weights set), P = N + M_SAP (1 - D N); d_out (nullable) = D P in, which
+ * the SAP recurrence yields without another operator application.  Inner precision.
+ */
+int sapq_precondition(sapq_ctx *ctx, double *out, double *d_out, const double *in);
+
+/*
  * e ~ D^-1 r by the inner BiCGStab right-preconditioned with M_SAP (section 2), from
  * e = 0, to |r - D e| <= tol_inner |r| (recursive residual) or maxit_inner iterations.
  * *iters (host, nullable) receives the iteration count.  Inner precision.
@@ -202,6 +223,15 @@ int sapq_inner_solve(sapq_ctx *ctx, double *e, const double *r, int *iters);
  * outer FP64 flexible BiCGStab (or defect correction) whose preconditioner is the inner
  * low-precision BiCGStab with M_SAP.  x: initial guess if params.flags & SAPQ_FLAG_GUESS,
  * solution on return.  stats (host, nullable).  SAPQ_ENOTCONV leaves the best iterate.
+ * b = 0 gives x = 0 at once.
+ * Failure handling: every scalar the iterations read back is checked.  An inner solve that
+ * meets a non-finite scalar is redone on the same input with a more robust preconditioner,
+ * which the flexible outer iteration allows (its preconditioner may change from one call to
+ * the next): first without the learned stage (plain M_SAP), then, for a context created with
+ * SAPQ_FLAG_FALLBACK_FP32, with FP32 storage; the change holds until the solve returns
+ * (stats->fallback, stats->breakdowns).  With nothing left to fall back to, or a source or an
+ * outer scalar that is not finite, the solve returns SAPQ_EBREAKDOWN with the last finite
+ * iterate in x.
  */
 int sapq_solve(sapq_ctx *ctx, double *x, const double *b, double tol, sapq_stats *stats);
 
@@ -288,6 +318,27 @@ int sapq_nn_backward(sapq_ctx *ctx, float *grad_w, double *grad_in, const double
  */
 int sapq_nn_train_step(sapq_ctx *ctx, const float *e, long n_vec, const int *idx, int batch, float lr, int t,
                        double *loss);
+
+/*
+ * One Adam step (Kingma and Ba: beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of the FP32
+ * master weights with the gradient grad_w that the caller supplies (device float,
+ * sapq_nn_param_count() entries in the weight-blob layout, e.g. from sapq_nn_backward), learning
+ * rate lr > 0 and step count t >= 1; the BF16-rounded weights the layers use are refreshed.
+ * The moments live in the context (reset by sapq_nn_set_weights, carried by
+ * sapq_nn_copy_state).  Needs set weights (else SAPQ_ESTATE).
+ */
+int sapq_nn_adam_step(sapq_ctx *ctx, const float *grad_w, float lr, int t);
+
+/*
+ * Residual -> error training pairs from the plain SAP solver (the learned stage's training
+ * data).  From x_0 = 0, the defect-correction iterates x_{k+1} = x_k + Inner(b - D x_k) of
+ * section 2's outer iteration (this context's inner solver, learned stage off) give
+ * e_k = xstar - x_k for k = 0 .. n_iter - 1, written to e (device float, [n_iter][V][4][3]
+ * as (re, im) pairs, the layout sapq_nn_train_step reads; when xstar solves D x = b, the
+ * residual of the pair is r_k = b - D x_k = D e_k).  b, xstar: spinor layout, FP64.  Returns
+ * SAPQ_EBREAKDOWN (the remaining e_k unwritten) if an inner solve breaks down.
+ */
+int sapq_defect_errors(sapq_ctx *ctx, float *e, const double *b, const double *xstar, int n_iter);
 
 /*
  * The SAP phase kernel a context runs, chosen at creation from the block and the device's

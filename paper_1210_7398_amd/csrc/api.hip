@@ -110,10 +110,16 @@ static void carve(Ctx *c, Arena &A, const HostTables &T, const PartTables &PT) {
     c->F64 = (double2 *)A.take((size_t)V * 36 * 16);
     c->Uin = A.take((size_t)V * 24 * eb);
     c->Fin = A.take((size_t)V * 36 * eb);
+    c->Uin_lp = c->Uin;
+    c->Fin_lp = c->Fin;
+    // inner work vectors wide enough for FP32 when the context may fall back to it
+    const size_t ev = c->fb_fp32 ? elem_bytes(SAPQ_FP32) : eb;
+    c->Uin32 = c->fb_fp32 ? A.take((size_t)V * 24 * ev) : nullptr;
+    c->Fin32 = c->fb_fp32 ? A.take((size_t)V * 36 * ev) : nullptr;
     double2 **d64[] = {&c->d_b, &c->d_x, &c->d_r, &c->d_rt, &c->d_p, &c->d_v, &c->d_s, &c->d_t, &c->d_ph, &c->d_sh, &c->d_tmp};
     for (auto p : d64) *p = (double2 *)A.take(nv * 16);
     void **din[] = {&c->i_r, &c->i_rt, &c->i_p, &c->i_v, &c->i_s, &c->i_t, &c->i_e, &c->i_ph, &c->i_sh, &c->i_rin, &c->i_tmp, &c->sap_r, &c->sap_x};
-    for (auto p : din) *p = A.take(nv * eb);
+    for (auto p : din) *p = A.take(nv * ev);
     c->ssor_scratch = (c->ssor_lds || c->use_parts) ? nullptr : (float2 *)A.take(nv * 8);
     c->xch = nullptr;
     c->xsync = nullptr;
@@ -137,8 +143,8 @@ static void carve(Ctx *c, Arena &A, const HostTables &T, const PartTables &PT) {
                                                {&c->nn_gz, 1}, {&c->nn_g2, NN_C}, {&c->nn_g1, NN_C}, {&c->nn_gin, 1},
                                                {&c->nn_e, 1}};
         for (auto &e : f) *e.p = (float2 *)A.take(nv * e.ch * sizeof(float2));
-        c->i_z = A.take(nv * eb);
-        c->i_rp = A.take(nv * eb);
+        c->i_z = A.take(nv * ev);
+        c->i_rp = A.take(nv * ev);
         for (int k = 0; k < 3; ++k) c->nn_afrag[k] = A.take(nn_afrag_elems(NN_CIN[k], NN_COUT[k]) * 2);
         c->nn_afrag_t = A.take(nn_afrag_elems(NN_C, NN_C) * 2);
         c->nn_L = (float2 *)A.take(nn_link_elems(c) * sizeof(float2));
@@ -203,6 +209,15 @@ static int parts_status(Ctx *c) {
     return SAPQ_EHIP;
 }
 
+// Point the context at the FP32 copies of the fields (the fallback of an FP16/BF16 context)
+// or back at the fields of its creation precision.
+static void use_fp32_storage(Ctx *c, bool on) {
+    if (!c->fb_fp32) return;
+    c->Uin = on ? c->Uin32 : c->Uin_lp;
+    c->Fin = on ? c->Fin32 : c->Fin_lp;
+    c->prm.prec_inner = on ? SAPQ_FP32 : c->prec_created;
+}
+
 static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTables &T, PartTables &PT, int max_lds) {
     build_tables(geom, T);
     c->geom = *geom;
@@ -251,6 +266,8 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
             c->ssor_staged = false;
         }
     }
+    c->prec_created = prm->prec_inner;
+    c->fb_fp32 = (prm->flags & SAPQ_FLAG_FALLBACK_FP32) && prm->prec_inner != SAPQ_FP32 && !c->ssor_staged;
     Arena A{nullptr, 0, 0};
     carve(c, A, T, PT);
     return A.used + 256;
@@ -343,12 +360,19 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     }
     rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (rc) { hipHostFree(c->host_res); delete h; return rc; }
-    if (set_sap_lds_limits(c) || set_parts_lds_limit(c) || set_eomr_lds_limit(c)) {
+    bool lds_ok = !(set_sap_lds_limits(c) || set_parts_lds_limit(c) || set_eomr_lds_limit(c));
+    if (lds_ok && c->fb_fp32) {  // the FP32 instantiations the fallback would launch
+        c->prm.prec_inner = SAPQ_FP32;
+        lds_ok = !(set_sap_lds_limits(c) || set_parts_lds_limit(c) || set_eomr_lds_limit(c));
+        c->prm.prec_inner = c->prec_created;
+    }
+    if (!lds_ok) {
         hipHostFree(c->host_res);
         delete h;
         set_error("hipFuncSetAttribute refused the LDS size of the SAP kernel");
         return SAPQ_EHIP;
     }
+    if (const char *e = getenv("SAPQ_TEST_LOWPREC_NAN")) c->poison_lowprec = atoi(e) == 1;
     *out = h;
     return SAPQ_OK;
 }
@@ -381,6 +405,12 @@ int sapq_load_gauge(sapq_ctx *h, const double *U, double *max_dev) {
     if (!h || !U) { set_error("null argument"); return SAPQ_EINVAL; }
     Ctx *c = &h->c;
     double dev = 0;
+    if (c->fb_fp32) {  // the FP32 copy first, then the creation precision (which sets have_U)
+        use_fp32_storage(c, true);
+        const int bad = launch_pack_links(c, U, &dev);
+        use_fp32_storage(c, false);
+        if (bad) return hipcheck(hipGetLastError(), "load_gauge");
+    }
     if (launch_pack_links(c, U, &dev)) return hipcheck(hipGetLastError(), "load_gauge");
     int rc = hipcheck(hipGetLastError(), "k_pack_links");
     if (rc) return rc;
@@ -402,6 +432,11 @@ int sapq_load_gauge(sapq_ctx *h, const double *U, double *max_dev) {
 
 int sapq_load_clover_inv(sapq_ctx *h, const double *F) {
     if (!h || !F) { set_error("null argument"); return SAPQ_EINVAL; }
+    if (h->c.fb_fp32) {
+        use_fp32_storage(&h->c, true);
+        launch_pack_clover(&h->c, F);
+        use_fp32_storage(&h->c, false);
+    }
     launch_pack_clover(&h->c, F);
     int rc = hipcheck(hipGetLastError(), "k_pack_clover");
     if (rc) return rc;
@@ -582,7 +617,7 @@ void nn_apply(Ctx *c, const void *p, void *z, void *rp, const int *skip) {
 // z = N p.  Either way D ph = p - r_N comes out of the SAP recurrence: v = p - sap_r.
 static void precondition(Ctx *c, const void *p, void *ph) {
     const int pi = c->prm.prec_inner;
-    if (!(c->have_nn && (c->prm.flags & SAPQ_FLAG_NN))) {
+    if (!(c->have_nn && (c->prm.flags & SAPQ_FLAG_NN)) || c->nn_suspended) {
         msap(c, p, ph);
         return;
     }
@@ -592,7 +627,36 @@ static void precondition(Ctx *c, const void *p, void *ph) {
     // the SAP recurrence left sap_r = r' - D M r', so p - sap_r = D z + D M r' = D ph
 }
 
+static bool finite(zc a) { return std::isfinite(a.real()) && std::isfinite(a.imag()); }
+
+}  // namespace sapq
+
+extern "C" {
+
+int sapq_precondition(sapq_ctx *h, double *out, double *d_out, const double *in) {
+    if (!h || !out || !in) { set_error("null argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    const int pi = c->prm.prec_inner;
+    launch_pack_spinor(c, pi, c->i_tmp, in, 1.0);
+    precondition(c, c->i_tmp, c->i_ph);
+    launch_unpack_spinor(c, pi, out, c->i_ph, 1.0);
+    if (d_out) {
+        blas_xpay(c, pi, c->i_v, c->i_tmp, make_double2(-1, 0), c->sap_r);  // D P in = in - r_N
+        launch_unpack_spinor(c, pi, d_out, c->i_v, 1.0);
+    }
+    rc = hipcheck(hipGetLastError(), "sapq_precondition");
+    return rc ? rc : parts_status(c);
+}
+
+}  // extern "C"
+
+namespace sapq {
+
 // Inner BiCGStab (right-preconditioned by M_SAP) on inner-precision vectors, e from 0.
+// SAPQ_EBREAKDOWN when a scalar read back is not finite (e is then not usable); an exact
+// zero denominator ends the iteration with the e reached so far.
 static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
     const int pi = c->prm.prec_inner;
     blas_copy(c, pi, c->i_r, rhs);
@@ -608,7 +672,9 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
     zc rho = Z(res[0]), rho_old = 1, alpha = 1, om = 1;
     const double r0 = std::sqrt(res[1].x), tol = c->prm.tol_inner * r0;
     int it = 0;
-    if (r0 == 0) { *iters = 0; return SAPQ_OK; }
+    *iters = 0;
+    if (!finite(rho) || !std::isfinite(r0)) return SAPQ_EBREAKDOWN;
+    if (r0 == 0) return SAPQ_OK;
     while (it < c->prm.maxit_inner) {
         if (std::abs(rho) == 0) break;
         zc beta = (rho / rho_old) * (alpha / om);
@@ -616,11 +682,13 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
         precondition(c, c->i_p, c->i_ph);                             // p^ = M p
         blas_xpay(c, pi, c->i_v, c->i_p, make_double2(-1, 0), c->sap_r);  // v = D p^ = p - r_N
         zc rv = Z(dot1(c, pi, c->i_rt, c->i_v));
+        if (!finite(rv)) { *iters = it; return SAPQ_EBREAKDOWN; }
         if (std::abs(rv) == 0) break;
         alpha = rho / rv;
         blas_xpay(c, pi, c->i_s, c->i_r, D2(-alpha), c->i_v);          // s = r - alpha v
         double ss = dot1(c, pi, c->i_s, c->i_s).x;
         ++it;
+        if (!std::isfinite(ss)) { *iters = it; return SAPQ_EBREAKDOWN; }
         if (std::sqrt(ss) <= tol) {
             blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, make_double2(0, 0), c->i_ph);
             break;
@@ -631,6 +699,7 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
             const void *A[2] = {c->i_t, c->i_t}, *B[2] = {c->i_s, c->i_t};
             blas_dots(c, pi, 2, A, B, res);
         }
+        if (!finite(Z(res[0])) || !std::isfinite(res[1].x)) { *iters = it; return SAPQ_EBREAKDOWN; }
         if (res[1].x == 0) {
             blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, make_double2(0, 0), c->i_ph);
             break;
@@ -644,6 +713,7 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
         }
         rho_old = rho;
         rho = Z(res[0]);
+        if (!finite(rho) || !std::isfinite(res[1].x)) { *iters = it; return SAPQ_EBREAKDOWN; }
         if (std::sqrt(res[1].x) <= tol) break;
         if (std::abs(om) == 0) break;
     }
@@ -651,17 +721,40 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
     return SAPQ_OK;
 }
 
-// p^ = Inner(p) for an FP64 internal vector: normalise, convert, solve, convert back
+// p^ = Inner(p) for an FP64 internal vector: normalise, convert, solve, convert back.  An
+// inner solve that breaks down is redone on the same p with the next fallback: the learned
+// stage dropped, then FP32 storage (SAPQ_FLAG_FALLBACK_FP32); SAPQ_EBREAKDOWN when none is
+// left (out is then untouched).
 static int apply_inner(Ctx *c, double2 *out, const double2 *in, int *its) {
     double nrm = std::sqrt(dot1(c, SAPQ_FP64, in, in).x);
-    if (nrm == 0) { blas_zero(c, SAPQ_FP64, out); *its = 0; return SAPQ_OK; }
+    *its = 0;
+    if (!std::isfinite(nrm)) { set_error("inner right-hand side is not finite"); return SAPQ_EBREAKDOWN; }
+    if (nrm == 0) { blas_zero(c, SAPQ_FP64, out); return SAPQ_OK; }
     // unit RMS per complex component keeps FP16 storage away from under- and overflow
-    double scale = std::sqrt((double)c->nvec) / nrm;
-    const int pi = c->prm.prec_inner;
-    blas_convert(c, pi, c->i_rin, SAPQ_FP64, in, scale);
-    int rc = inner_bicgstab(c, c->i_e, c->i_rin, its);
-    blas_convert(c, SAPQ_FP64, out, pi, c->i_e, 1.0 / scale);
-    return rc;
+    const double scale = std::sqrt((double)c->nvec) / nrm;
+    for (;;) {
+        const int pi = c->prm.prec_inner;
+        const double sc = (c->poison_lowprec && pi != SAPQ_FP32) ? std::nan("") : scale;
+        blas_convert(c, pi, c->i_rin, SAPQ_FP64, in, sc);
+        int n = 0;
+        const int rc = inner_bicgstab(c, c->i_e, c->i_rin, &n);
+        *its += n;
+        if (rc == SAPQ_OK) {
+            blas_convert(c, SAPQ_FP64, out, pi, c->i_e, 1.0 / scale);
+            return SAPQ_OK;
+        }
+        c->breakdowns++;
+        if (c->have_nn && (c->prm.flags & SAPQ_FLAG_NN) && !c->nn_suspended) {
+            c->nn_suspended = true;
+            c->fallback |= SAPQ_FALLBACK_NN;
+        } else if (c->fb_fp32 && pi != SAPQ_FP32) {
+            use_fp32_storage(c, true);
+            c->fallback |= SAPQ_FALLBACK_FP32;
+        } else {
+            set_error("inner BiCGStab broke down (a non-finite scalar) with no fallback left");
+            return SAPQ_EBREAKDOWN;
+        }
+    }
 }
 
 static void d64(Ctx *c, double2 *out, const double2 *in) {
@@ -671,29 +764,48 @@ static void d64(Ctx *c, double2 *out, const double2 *in) {
     c->n_d64++;
 }
 
+// The outer iteration on the FP64 internal vectors d_b (source) and d_x (guess in,
+// solution out).  Fallbacks taken by the inner solves last until it returns.
 static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
-    int outer = 0, inner = 0, restarts = 0, its = 0, conv = 0, nh = 0;
+    int outer = 0, inner = 0, restarts = 0, its = 0, conv = 0, nh = 0, rc = SAPQ_OK;
     double hist[256];
+    c->nn_suspended = false;
+    c->fallback = c->breakdowns = 0;
     const double bn = std::sqrt(dot1(c, SAPQ_FP64, c->d_b, c->d_b).x);
-    d64(c, c->d_tmp, c->d_x);
-    blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
-    double relres = bn > 0 ? std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn : 0.0;
-    if (relres <= tol) conv = 1;
+    double relres = 0.0;
+    // the residual of the iterate in d_x: r = b - D x, |r| / |b|
+    auto true_residual = [&]() {
+        d64(c, c->d_tmp, c->d_x);
+        blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
+        relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
+    };
+    if (!std::isfinite(bn)) {
+        set_error("the source is not finite");
+        rc = SAPQ_EBREAKDOWN;
+        relres = std::nan("");
+    } else if (bn == 0) {
+        blas_zero(c, SAPQ_FP64, c->d_x);  // D x = 0 has the solution x = 0
+        conv = 1;
+    } else {
+        true_residual();
+        if (!std::isfinite(relres)) { set_error("the initial guess gives a non-finite residual"); rc = SAPQ_EBREAKDOWN; }
+        if (relres <= tol) conv = 1;
+    }
     const int maxit = c->prm.maxit_outer;
-    if (c->prm.outer == SAPQ_OUTER_DEFECT) {
+    if (rc == SAPQ_OK && c->prm.outer == SAPQ_OUTER_DEFECT) {
         while (!conv && outer < maxit) {
-            apply_inner(c, c->d_ph, c->d_r, &its);
+            rc = apply_inner(c, c->d_ph, c->d_r, &its);
             inner += its;
+            if (rc) break;
             blas_xpay(c, SAPQ_FP64, c->d_x, c->d_x, make_double2(1, 0), c->d_ph);
-            d64(c, c->d_tmp, c->d_x);
-            blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
             ++outer;
-            relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
+            true_residual();
+            if (!std::isfinite(relres)) { set_error("non-finite outer residual"); rc = SAPQ_EBREAKDOWN; break; }
             if (nh < 256) hist[nh++] = relres;
             if (relres <= tol) conv = 1;
         }
-    } else {
-        while (!conv && outer < maxit) {
+    } else if (rc == SAPQ_OK) {
+        while (!conv && outer < maxit && rc == SAPQ_OK) {
             blas_copy(c, SAPQ_FP64, c->d_rt, c->d_r);
             blas_zero(c, SAPQ_FP64, c->d_p);
             blas_zero(c, SAPQ_FP64, c->d_v);
@@ -701,52 +813,71 @@ static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
             bool restart = false;
             while (!restart && outer < maxit) {
                 zc rho = Z(dot1(c, SAPQ_FP64, c->d_rt, c->d_r));
+                if (!finite(rho)) { set_error("non-finite outer scalar rho"); rc = SAPQ_EBREAKDOWN; break; }
                 zc beta = (rho / rho_old) * (alpha / om);
                 blas_bicg_p(c, SAPQ_FP64, c->d_p, c->d_r, D2(beta), D2(om), c->d_v);
-                apply_inner(c, c->d_ph, c->d_p, &its);                       // p^ = Inner(p)
+                rc = apply_inner(c, c->d_ph, c->d_p, &its);                  // p^ = Inner(p)
                 inner += its;
+                if (rc) break;
                 d64(c, c->d_v, c->d_ph);                                     // v = D p^
                 zc rv = Z(dot1(c, SAPQ_FP64, c->d_rt, c->d_v));
                 ++outer;
+                if (!finite(rv)) { set_error("non-finite outer scalar <r~, v>"); rc = SAPQ_EBREAKDOWN; break; }
                 if (std::abs(rv) == 0) { restart = true; }
                 else {
                     alpha = rho / rv;
                     blas_xpay(c, SAPQ_FP64, c->d_s, c->d_r, D2(-alpha), c->d_v);  // s = r - alpha v
                     double sn = std::sqrt(dot1(c, SAPQ_FP64, c->d_s, c->d_s).x);
+                    if (!std::isfinite(sn)) { set_error("non-finite outer norm |s|"); rc = SAPQ_EBREAKDOWN; break; }
                     if (sn <= tol * bn) {
                         blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, make_double2(0, 0), c->d_ph);
                         restart = true;
                     } else {
-                        apply_inner(c, c->d_sh, c->d_s, &its);               // s^ = Inner(s)
+                        rc = apply_inner(c, c->d_sh, c->d_s, &its);          // s^ = Inner(s)
                         inner += its;
+                        if (rc) {
+                            // x += alpha p^ is still a sound step: keep it before giving up
+                            blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, make_double2(0, 0), c->d_ph);
+                            break;
+                        }
                         d64(c, c->d_t, c->d_sh);                             // t = D s^
                         double2 res[2];
                         const void *A[2] = {c->d_t, c->d_t}, *B[2] = {c->d_s, c->d_t};
                         blas_dots(c, SAPQ_FP64, 2, A, B, res);
-                        om = Z(res[0]) / res[1].x;
-                        blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, D2(om), c->d_sh);
-                        blas_xpay(c, SAPQ_FP64, c->d_r, c->d_s, D2(-om), c->d_t);
-                        rho_old = rho;
-                        double rn = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x);
-                        if (nh < 256) hist[nh++] = rn / bn;
-                        if (rn <= tol * bn || std::abs(om) == 0) restart = true;
+                        if (!finite(Z(res[0])) || !std::isfinite(res[1].x)) {
+                            blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, make_double2(0, 0), c->d_ph);
+                            set_error("non-finite outer scalar <t, s> or |t|");
+                            rc = SAPQ_EBREAKDOWN;
+                            break;
+                        }
+                        if (res[1].x == 0) {
+                            // t = 0: keep the alpha step and restart from the true residual
+                            blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, make_double2(0, 0), c->d_ph);
+                            restart = true;
+                        } else {
+                            om = Z(res[0]) / res[1].x;
+                            blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, D2(om), c->d_sh);
+                            blas_xpay(c, SAPQ_FP64, c->d_r, c->d_s, D2(-om), c->d_t);
+                            rho_old = rho;
+                            double rn = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x);
+                            if (nh < 256) hist[nh++] = rn / bn;
+                            if (!std::isfinite(rn)) { set_error("non-finite outer residual"); rc = SAPQ_EBREAKDOWN; break; }
+                            if (rn <= tol * bn || std::abs(om) == 0) restart = true;
+                        }
                     }
                 }
                 if (restart) {
-                    d64(c, c->d_tmp, c->d_x);                                // true residual
-                    blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
-                    relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
+                    true_residual();
+                    if (!std::isfinite(relres)) { set_error("non-finite true residual"); rc = SAPQ_EBREAKDOWN; break; }
                     if (relres <= tol) conv = 1;
                     else ++restarts;
                 }
             }
         }
-        if (!conv) {
-            d64(c, c->d_tmp, c->d_x);
-            blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
-            relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
-        }
     }
+    if (!conv && std::isfinite(bn) && bn > 0) true_residual();  // the residual of the iterate returned
+    use_fp32_storage(c, false);
+    c->nn_suspended = false;
     if (st) {
         st->outer_its = outer;
         st->inner_its = inner;
@@ -754,7 +885,10 @@ static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
         st->true_relres = relres;
         st->n_hist = nh;
         for (int i = 0; i < nh; ++i) st->relres_hist[i] = hist[i];
+        st->breakdowns = c->breakdowns;
+        st->fallback = c->fallback;
     }
+    if (rc) return rc;
     return conv ? SAPQ_OK : SAPQ_ENOTCONV;
 }
 
@@ -870,6 +1004,44 @@ int sapq_nn_train_step(sapq_ctx *h, const float *e, long n_vec, const int *idx, 
     nn_prepare(c);
     if (loss) *loss = total / batch;
     return hipcheck(hipGetLastError(), "sapq_nn_train_step");
+}
+
+int sapq_nn_adam_step(sapq_ctx *h, const float *grad_w, float lr, int t) {
+    if (!h || !grad_w || t < 1 || !(lr > 0)) { set_error("bad argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = nn_ready(c, true);
+    if (rc) return rc;
+    launch_nn_adam(c, NN_PARAMS, c->nn_w, grad_w, 1.f, c->nn_m, c->nn_v, lr, t, c->nn_wq);
+    nn_prepare(c);
+    return hipcheck(hipGetLastError(), "sapq_nn_adam_step");
+}
+
+int sapq_defect_errors(sapq_ctx *h, float *e, const double *b, const double *xstar, int n_iter) {
+    if (!h || !e || !b || !xstar || n_iter < 1) { set_error("bad argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    int rc = ready(c);
+    if (rc) return rc;
+    launch_pack_spinor(c, SAPQ_FP64, c->d_b, b, 1.0);
+    launch_pack_spinor(c, SAPQ_FP64, c->d_sh, xstar, 1.0);
+    blas_zero(c, SAPQ_FP64, c->d_x);
+    c->nn_suspended = true;  // the plain SAP solver's iterates
+    c->fallback = c->breakdowns = 0;
+    for (int k = 0; k < n_iter && rc == SAPQ_OK; ++k) {
+        blas_xpay(c, SAPQ_FP64, c->d_t, c->d_sh, make_double2(-1, 0), c->d_x);  // e_k = x* - x_k
+        launch_unpack_spinor_f32(c, e + (size_t)k * c->V * 24, c->d_t);
+        if (k + 1 == n_iter) break;
+        d64(c, c->d_tmp, c->d_x);
+        blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);  // r_k = b - D x_k
+        int its = 0;
+        rc = apply_inner(c, c->d_ph, c->d_r, &its);
+        if (rc == SAPQ_OK) blas_xpay(c, SAPQ_FP64, c->d_x, c->d_x, make_double2(1, 0), c->d_ph);  // x_{k+1}
+    }
+    use_fp32_storage(c, false);
+    c->nn_suspended = false;
+    int hr = hipcheck(hipStreamSynchronize(c->stream), "sapq_defect_errors");
+    if (hr == SAPQ_OK) hr = hipcheck(hipGetLastError(), "sapq_defect_errors");
+    if (hr == SAPQ_OK) hr = parts_status(c);
+    return hr ? hr : rc;
 }
 
 // Rebuild the sub-block dependent tables (ll order, hyperplanes, neighbours) for shape S.

@@ -31,6 +31,20 @@ __global__ void k_pack_spinor_f32(GeomDev g, float2 *dst, const float2 *src) {
     for (int c = 0; c < 12; ++c) q[(size_t)c * g.Vb] = p[c];
 }
 
+// FP64 internal layout -> FP32 (re, im) pairs in the interchange layout (rounded)
+__global__ void k_unpack_spinor_f32(GeomDev g, float2 *dst, const double2 *src) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= g.V) return;
+    int ib = (int)(i / g.Vb), s = (int)(i - (long)ib * g.Vb);
+    float2 *p = dst + lex_site(g, ib, s) * 12;
+    const double2 *q = src + (size_t)ib * 12 * g.Vb + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double2 v = q[(size_t)c * g.Vb];
+        p[c] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
 template <int P>
 __global__ void k_unpack_spinor(GeomDev g, double2 *dst, const typename Prec<P>::S2 *src, double scale) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -531,6 +545,10 @@ void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src) {
     k_pack_spinor_f32<<<grid_for(c->V, 256), 256, 0, c->stream>>>(c->g, (float2 *)dst, (const float2 *)src);
 }
 
+void launch_unpack_spinor_f32(Ctx *c, float *dst, const double2 *src) {
+    k_unpack_spinor_f32<<<grid_for(c->V, 256), 256, 0, c->stream>>>(c->g, (float2 *)dst, src);
+}
+
 void launch_unpack_spinor(Ctx *c, int prec, double *dst, const void *src, double scale) {
     PREC_SWITCH(prec, (k_unpack_spinor<P_><<<grid_for(c->V, 256), 256, 0, c->stream>>>(
                           c->g, (double2 *)dst, (const typename Prec<P_>::S2 *)src, scale)));
@@ -584,15 +602,17 @@ static bool permute_rows(Ctx *c, void *f, long rows, const int *perm) {
 // does not fit the LDS.
 bool launch_permute_fields(Ctx *c, const int *perm) {
     const long NB = c->g.NB;
-    const bool half = elem_bytes(c->prm.prec_inner) == 4;
+    const bool half = elem_bytes(c->prec_created) == 4;
     bool ok = true;
     if (c->have_U) {
         ok = ok && permute_rows<uint4>(c, c->U64, NB * 24, perm);
-        ok = ok && (half ? permute_rows<unsigned>(c, c->Uin, NB * 24, perm) : permute_rows<uint2>(c, c->Uin, NB * 24, perm));
+        ok = ok && (half ? permute_rows<unsigned>(c, c->Uin_lp, NB * 24, perm) : permute_rows<uint2>(c, c->Uin_lp, NB * 24, perm));
+        if (c->fb_fp32) ok = ok && permute_rows<uint2>(c, c->Uin32, NB * 24, perm);
     }
     if (c->have_F) {
         ok = ok && permute_rows<uint4>(c, c->F64, NB * 36, perm);
-        ok = ok && (half ? permute_rows<unsigned>(c, c->Fin, NB * 36, perm) : permute_rows<uint2>(c, c->Fin, NB * 36, perm));
+        ok = ok && (half ? permute_rows<unsigned>(c, c->Fin_lp, NB * 36, perm) : permute_rows<uint2>(c, c->Fin_lp, NB * 36, perm));
+        if (c->fb_fp32) ok = ok && permute_rows<uint2>(c, c->Fin32, NB * 36, perm);
     }
     return ok;
 }

@@ -223,6 +223,15 @@ struct Ctx {
     unsigned halo_wait_xor = 0;     // nonzero: every such wait times out (failure-path tests)
     void *Uin, *Fin;  // inner storage precision
     bool have_U, have_F;
+    // failure handling (sapq_solve): FP32 copies of the fields that an FP16/BF16 context can
+    // fall back to (SAPQ_FLAG_FALLBACK_FP32), the fields of the creation precision while it
+    // has, and the state of the current solve
+    int prec_created = SAPQ_FP32;
+    bool fb_fp32 = false;
+    void *Uin32 = nullptr, *Fin32 = nullptr, *Uin_lp = nullptr, *Fin_lp = nullptr;
+    bool nn_suspended = false;   // learned stage dropped for the rest of the solve
+    int fallback = 0, breakdowns = 0;
+    bool poison_lowprec = false; // SAPQ_TEST_LOWPREC_NAN: NaN-scaled inner solves in FP16/BF16
     // FP64 work vectors (internal layout)
     double2 *d_b, *d_x, *d_r, *d_rt, *d_p, *d_v, *d_s, *d_t, *d_ph, *d_sh, *d_tmp;
     // inner-precision work vectors
@@ -270,6 +279,7 @@ void launch_nn_afrag(Ctx *c, int cin, int cout, const float2 *W, void *A);
 void launch_nn_layer_mfma(Ctx *c, int cin, int cout, const void *in, void *out, const void *A, int p_in, int p_out,
                           const int *skip);
 void launch_pack_spinor_f32(Ctx *c, void *dst, const float *src);
+void launch_unpack_spinor_f32(Ctx *c, float *dst, const double2 *src);
 // learned stage on inner-precision vectors: z = N p, rp = p - D z
 void nn_apply(Ctx *c, const void *p, void *z, void *rp, const int *skip = nullptr);
 

@@ -16,7 +16,8 @@ _LIB = None
 
 FP64, FP32, FP16, BF16 = 0, 1, 2, 3
 OUTER_FBICGSTAB, OUTER_DEFECT = 0, 1
-FLAG_GUESS, FLAG_PROFILE, FLAG_NN, FLAG_NN_FP32, FLAG_EOMR = 1, 2, 4, 8, 16
+FLAG_GUESS, FLAG_PROFILE, FLAG_NN, FLAG_NN_FP32, FLAG_EOMR, FLAG_FALLBACK_FP32 = 1, 2, 4, 8, 16, 32
+FALLBACK_NN, FALLBACK_FP32 = 1, 2
 PREC = {"fp64": FP64, "fp32": FP32, "fp16": FP16, "bf16": BF16}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ENOTSU3", -4: "ENOTCONV", -5: "EBREAKDOWN", -6: "EHIP",
           -7: "ENOMEM", -8: "ESTATE"}
@@ -44,7 +45,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("outer_its", ctypes.c_int), ("inner_its", ctypes.c_int), ("n_msap", ctypes.c_int),
                 ("n_dslash64", ctypes.c_int), ("restarts", ctypes.c_int), ("n_hist", ctypes.c_int),
                 ("true_relres", ctypes.c_double), ("time_s", ctypes.c_double), ("kern_ms", ctypes.c_double * 8),
-                ("kern_n", ctypes.c_int * 8), ("relres_hist", ctypes.c_double * 256)]
+                ("kern_n", ctypes.c_int * 8), ("relres_hist", ctypes.c_double * 256), ("breakdowns", ctypes.c_int),
+                ("fallback", ctypes.c_int)]
 
     KINDS = ("phase_E", "phase_O", "face", "dslash64", "blas")
 
@@ -52,6 +54,7 @@ class Stats(ctypes.Structure):
         return dict(outer_its=self.outer_its, inner_its=self.inner_its, n_msap=self.n_msap,
                     n_dslash64=self.n_dslash64, restarts=self.restarts, true_relres=self.true_relres,
                     time_s=self.time_s, relres_hist=list(self.relres_hist[: self.n_hist]),
+                    breakdowns=self.breakdowns, fallback=self.fallback,
                     kernels={k: dict(ms=self.kern_ms[i], n=self.kern_n[i]) for i, k in enumerate(self.KINDS)
                              if self.kern_n[i]})
 
@@ -68,12 +71,15 @@ _SIGS = {
     "sapq_ssor": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "sapq_dk": (ctypes.c_int, [_P, _P, _P, _P]),
     "sapq_sap_precondition": (ctypes.c_int, [_P, _P, _P, _P]),
+    "sapq_precondition": (ctypes.c_int, [_P, _P, _P, _P]),
     "sapq_inner_solve": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(ctypes.c_int)]),
     "sapq_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(Stats)]),
     "sapq_nn_param_count": (ctypes.c_size_t, []),
     "sapq_nn_set_weights": (ctypes.c_int, [_P, _P]),
     "sapq_nn_get_weights": (ctypes.c_int, [_P, _P]),
     "sapq_nn_copy_state": (ctypes.c_int, [_P, _P]),
+    "sapq_nn_adam_step": (ctypes.c_int, [_P, _P, ctypes.c_float, ctypes.c_int]),
+    "sapq_defect_errors": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int]),
     "sapq_nn_forward": (ctypes.c_int, [_P, _P, _P]),
     "sapq_nn_backward": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "sapq_nn_train_step": (ctypes.c_int, [_P, _P, ctypes.c_long, ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -123,7 +129,7 @@ class Solver:
 
     def __init__(self, L, block, subblock, kappa, bc=(1, 1, 1, 1), omega=1.0, n_ssor=4, n_sap=4, tol_inner=0.1,
                  maxit_inner=50, maxit_outer=100, prec="fp32", outer="fbicgstab", device=None, nn=False,
-                 nn_fp32=False, block_solver="ssor"):
+                 nn_fp32=False, block_solver="ssor", fallback_fp32=False):
         self.L = tuple(L)
         self.V = int(L[0] * L[1] * L[2] * L[3])
         self.geom = Geom((ctypes.c_int * 4)(*L), (ctypes.c_int * 4)(*block), (ctypes.c_int * 4)(*subblock),
@@ -131,7 +137,7 @@ class Solver:
         if block_solver not in ("ssor", "eomr"):
             raise ValueError("block_solver must be 'ssor' or 'eomr'")
         self.base_flags = ((FLAG_NN if nn else 0) | (FLAG_NN_FP32 if nn_fp32 else 0) |
-                           (FLAG_EOMR if block_solver == "eomr" else 0))
+                           (FLAG_EOMR if block_solver == "eomr" else 0) | (FLAG_FALLBACK_FP32 if fallback_fp32 else 0))
         self.params = Params(kappa, omega, tol_inner, n_ssor, n_sap, maxit_inner, maxit_outer, PREC[prec],
                              OUTER_FBICGSTAB if outer == "fbicgstab" else OUTER_DEFECT, self.base_flags)
         self.prec = prec
@@ -201,6 +207,21 @@ class Solver:
         _check(lib().sapq_sap_precondition(self.h, _ptr(y), _ptr(dy) if with_d else None, _ptr(v, self.V, (4, 3))))
         return (y, dy) if with_d else y
 
+    def precondition(self, v):
+        """(P v, D P v) for the inner solver's preconditioner P (sapq_precondition): M_SAP, or
+        N + M_SAP (1 - D N) with the learned stage on."""
+        y, dy = self._spinor(), self._spinor()
+        _check(lib().sapq_precondition(self.h, _ptr(y), _ptr(dy), _ptr(v, self.V, (4, 3))))
+        return y, dy
+
+    def defect_errors(self, b, xstar, n_iter):
+        """Errors e_k = xstar - x_k of the plain solver's defect-correction iterates from x_0 = 0
+        (sapq_defect_errors): float32 tensor [n_iter, V, 4, 3, 2]."""
+        e = torch.empty((n_iter, self.V, 4, 3, 2), dtype=torch.float32, device=self.device)
+        _check(lib().sapq_defect_errors(self.h, ctypes.c_void_p(e.data_ptr()), _ptr(b, self.V, (4, 3)),
+                                        _ptr(xstar, self.V, (4, 3)), int(n_iter)))
+        return e
+
     def inner_solve(self, r):
         e = self._spinor()
         it = ctypes.c_int(0)
@@ -260,6 +281,13 @@ class Solver:
         _check(lib().sapq_nn_backward(self.h, ctypes.c_void_p(gw.data_ptr()), _ptr(gin), _ptr(grad_out, self.V, (4, 3)),
                                       _ptr(inp, self.V, (4, 3))))
         return gw, gin
+
+    def nn_adam_step(self, grad_w, lr, t):
+        """One Adam step of the weights with a caller-supplied gradient (sapq_nn_adam_step)."""
+        if (grad_w.dtype != torch.float32 or not grad_w.is_contiguous() or grad_w.numel() != nn_param_count()
+                or grad_w.device.type != "cuda"):
+            raise TypeError("expected a contiguous float32 GPU tensor with nn_param_count() entries")
+        _check(lib().sapq_nn_adam_step(self.h, ctypes.c_void_p(grad_w.data_ptr()), float(lr), int(t)))
 
     def nn_train_step(self, e, idx, lr, t):
         """e: float32 GPU tensor [n, V, 4, 3, 2] of error vectors; idx: batch indices."""

@@ -3,8 +3,8 @@
 Training pairs come from the plain SAP solver: for a Gaussian source b the nested
 solve gives x* (to 1e-12), and defect-correction iterates x_0 = 0,
 x_{k+1} = x_k + Inner(b - D x_k) give the pairs (r_k, e_k) = (b - D x_k, x* - x_k).
-Only e_k is stored (float32, interchange layout); the library forms r_k = D e_k in
-FP32 inside sapq_nn_train_step.  The loss is the batch mean of |N r - e|^2 / |e|^2
+Only e_k is stored (float32, interchange layout, formed by sapq_defect_errors); the
+library forms r_k = D e_k in FP32 inside sapq_nn_train_step.  The loss is the batch mean of |N r - e|^2 / |e|^2
 and the update is Adam; forward, backward and the update run in the library's kernels.
 """
 import sys
@@ -34,18 +34,13 @@ def init_weights(seed, scale=0.02, device="cuda"):
 
 def make_pairs(solver, sources, n_iter=5, tol=1e-12):
     """Error vectors e_k = x* - x_k of defect-correction iterates of the plain SAP solver,
-    k = 0 .. n_iter-1, for each source; returns a float32 tensor [n, V, 4, 3, 2]."""
+    k = 0 .. n_iter-1, for each source (x* its solve to tol; the iterates and errors are formed
+    by the library, sapq_defect_errors); returns a float32 tensor [n, V, 4, 3, 2]."""
     out = []
     for b in sources:
-        xs, st = solver.solve(b, tol=tol, check=False)
-        x = torch.zeros_like(b)
-        for _ in range(n_iter):
-            e = xs - x
-            out.append(torch.view_as_real(e.to(torch.complex64)).contiguous())
-            r = b - solver.dslash(x, "fp64")
-            dx, _ = solver.inner_solve(r)
-            x = x + dx
-    return torch.stack(out)
+        xs, _ = solver.solve(b, tol=tol, check=False)
+        out.append(solver.defect_errors(b, xs, n_iter))
+    return torch.cat(out)
 
 
 def train(solvers_and_pairs, steps, batch=8, lr=1e-3, seed=0, log=None):
@@ -65,17 +60,3 @@ def train(solvers_and_pairs, steps, batch=8, lr=1e-3, seed=0, log=None):
         if log and (t % log == 0 or t == 1):
             print(f"# nn step {t}: loss {np.mean(losses[-log:]):.4f}", file=sys.stderr, flush=True)
     return losses
-
-
-def preconditioned_residual(solver, r, use_nn):
-    """|(1 - D P) r| / |r| for P the inner preconditioner (M_SAP, or the stage + M_SAP)."""
-    solver.use_nn(use_nn)
-    if use_nn:
-        z = solver.nn_forward(r)
-        rp = r - solver.dslash(z, "fp64")
-        _, dy = solver.sap_precondition(rp)
-        res = rp - dy
-    else:
-        _, dy = solver.sap_precondition(r)
-        res = r - dy
-    return float(torch.linalg.vector_norm(res) / torch.linalg.vector_norm(r))

@@ -29,6 +29,32 @@ def relerr(a, b):
     return float(np.linalg.norm((a - b).reshape(-1)) / np.linalg.norm(b.reshape(-1)))
 
 
+# A site is its 12 spin-colour components.  The per-site check bounds the largest error of
+# any one site by SITE_FACTOR times the relative 2-norm tolerance, in units of the RMS site
+# norm of the expected vector: an error spread evenly over the sites stays at a few times the
+# global ratio, while one wrong site (an error the size of the site itself, about 1 in these
+# units) fails it even at the loosest BF16 tolerance, where the global 2-norm cannot see it.
+SITE_FACTOR = 6.0
+
+
+def site_maxerr(a, b):
+    """max_n |a_n - b_n| / RMS_n |b_n| over the sites n (a: [..., V, 4, 3])."""
+    a = np.asarray(a).reshape(-1, 12)
+    b = np.asarray(b).reshape(-1, 12)
+    d = np.sqrt(np.sum(np.abs(a - b) ** 2, axis=1))
+    rms = np.sqrt(np.mean(np.sum(np.abs(b) ** 2, axis=1)))
+    return float(d.max() / rms)
+
+
+def check_close(got, want, tol, what=""):
+    """Relative 2-norm error below tol and per-site error below SITE_FACTOR * tol."""
+    e, m = relerr(got, want), site_maxerr(got, want)
+    print(f"{what}: relerr {e:.2e} (tol {tol:.0e}), site max {m:.2e} (tol {SITE_FACTOR * tol:.0e})")
+    assert e < tol, (what, e, tol)
+    assert m < SITE_FACTOR * tol, (what, "site", m, SITE_FACTOR * tol)
+    return e, m
+
+
 def to_dev(a):
     import torch
 

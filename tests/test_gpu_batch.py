@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from paper_1210_7398_amd import synth
-from tests.gpu_common import relerr, to_dev, to_host
+from tests.gpu_common import check_close, relerr, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +58,7 @@ def test_solve_batch_two_fields(torch_cuda, orc, prec, group, monkeypatch):
             assert rr <= 1e-10, (L, k, rr, stats[q])
             assert stats[q]["true_relres"] <= 1e-10
             x1, _ = s.solve(to_dev(np.ascontiguousarray(b[k])), tol=1e-10)
-            assert relerr(x[k], to_host(x1)) < 1e-8
+            check_close(x[k], to_host(x1), 1e-8, f"batched vs one-source solution {L} source {k}")
             q += 1
 
 
@@ -94,7 +94,7 @@ def test_solve_batch_with_learned_stage(torch_cuda, orc, prec):
         for k in range(b.shape[0]):
             assert relerr(orc.dslash(L, U, F, kappa, x[k]), b[k]) <= 1e-10, (L, k, stats[q])
             x1, _ = s.solve(to_dev(np.ascontiguousarray(b[k])), tol=1e-10)
-            assert relerr(x[k], to_host(x1)) < 1e-8
+            check_close(x[k], to_host(x1), 1e-8, f"batched vs one-source solution {L} source {k}")
             q += 1
 
 
@@ -119,7 +119,7 @@ def test_autotune_picks_a_valid_subblock_and_caches(torch_cuda, orc, tmp_path):
     v = synth.gaussian_spinor(L, 35)
     y_w, _ = orc.msap(L, B, S, U, F, orc.params(kappa), v)
     y, _ = s.sap_precondition(to_dev(v))
-    assert relerr(to_host(y), y_w) < 2e-5
+    check_close(to_host(y), y_w, 2e-5, "M_SAP after the sub-block change")
 
 
 def test_subblock_change_relays_out_the_fields(torch_cuda, orc, tmp_path):
@@ -155,7 +155,7 @@ def test_subblock_change_relays_out_the_fields(torch_cuda, orc, tmp_path):
     v = synth.gaussian_spinor(L, 38)
     y_w, _ = orc.msap(L, B, S_new, U, F, orc.params(kappa), v)
     y, _ = s.sap_precondition(to_dev(v))
-    assert relerr(to_host(y), y_w) < 2e-5
+    check_close(to_host(y), y_w, 2e-5, "M_SAP after the sub-block change")
     rng = np.random.default_rng(39)
     w = (0.15 * rng.normal(size=orc.nn_param_count())).astype(np.float32)
     w = w.view(np.uint32) & np.uint32(0xFFFF0000)  # BF16-exact weights (truncated)
@@ -163,7 +163,7 @@ def test_subblock_change_relays_out_the_fields(torch_cuda, orc, tmp_path):
     s.nn_set_weights(torch.from_numpy(w).cuda())
     r = synth.gaussian_spinor(L, 40)
     z_w, _ = orc.nn_forward(L, U, orc.nn_unflatten(w), r)
-    assert relerr(to_host(s.nn_forward(to_dev(r))), z_w) < 1e-5
+    check_close(to_host(s.nn_forward(to_dev(r))), z_w, 1e-5, "network after the sub-block change")
     s.close()
 
 
@@ -190,6 +190,6 @@ def test_solve_batch_even_odd_order(torch_cuda, orc):
         for k in range(b.shape[0]):
             assert relerr(orc.dslash(L, U, F, kappa, x[k]), b[k]) <= 1e-10
             x1, _ = s.solve(to_dev(np.ascontiguousarray(b[k])), tol=1e-10)
-            assert relerr(x[k], to_host(x1)) < 1e-8
+            check_close(x[k], to_host(x1), 1e-8, f"batched vs one-source solution {L} source {k}")
     for s in solvers:
         s.close()

@@ -10,7 +10,7 @@ import pytest
 
 from paper_1210_7398_amd import synth
 from tests import helpers as H
-from tests.gpu_common import GEOMS, fields, relerr, to_dev, to_host
+from tests.gpu_common import GEOMS, check_close, fields, relerr, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +23,26 @@ def torch_cuda():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch
+
+
+def _check_weights(got, want, tol):
+    """Relative 2-norm error of a weight blob below tol, and no single weight off by more than
+    SITE_FACTOR * tol of the RMS weight."""
+    from tests.gpu_common import SITE_FACTOR
+
+    assert relerr(got, want) < tol, relerr(got, want)
+    m = float(np.abs(got - want).max() / np.sqrt(np.mean(want**2)))
+    assert m < SITE_FACTOR * tol, m
+
+
+def _preconditioned_residual(s, r, use_nn):
+    """|(1 - D P) r| / |r| for the inner preconditioner P of the library (sapq_precondition):
+    M_SAP, or the learned stage ahead of M_SAP."""
+    import torch
+
+    s.use_nn(use_nn)
+    _, dz = s.precondition(r)
+    return float(torch.linalg.vector_norm(r - dz) / torch.linalg.vector_norm(r))
 
 
 def bf16_exact(x):
@@ -60,7 +80,7 @@ def test_nn_forward_parity(torch_cuda, orc):
     r = synth.gaussian_spinor(L, 201)
     z_w, _ = orc.nn_forward(L, U, orc.nn_unflatten(w), r, bc)
     z = to_host(s.nn_forward(to_dev(r)))
-    assert relerr(z, z_w) < 1e-5
+    check_close(z, z_w, 1e-5, "network forward fp32")
 
 
 def test_nn_mfma_forward_and_backward_parity(torch_cuda, orc):
@@ -73,12 +93,12 @@ def test_nn_mfma_forward_and_backward_parity(torch_cuda, orc):
     r = synth.gaussian_spinor(L, 211)
     Ws = orc.nn_unflatten(w)
     z_w, _ = orc.nn_forward(L, U, Ws, r, bc)
-    assert relerr(to_host(s.nn_forward(to_dev(r))), z_w) < 1e-2
+    check_close(to_host(s.nn_forward(to_dev(r))), z_w, 1e-2, "network forward mfma")
     gz = synth.gaussian_spinor(L, 212)
     gw, gin = s.nn_backward(to_dev(gz), to_dev(r))
     grads, gin_w = orc.nn_backward(L, U, Ws, r, gz, bc)
-    assert relerr(gw.cpu().numpy().astype(np.float64), orc.nn_flatten(grads)) < 2e-2
-    assert relerr(to_host(gin), gin_w) < 1e-2
+    _check_weights(gw.cpu().numpy().astype(np.float64), orc.nn_flatten(grads), 2e-2)
+    check_close(to_host(gin), gin_w, 1e-2, "input gradient mfma")
 
 
 def test_nn_forward_gauge_equivariance(torch_cuda, orc):
@@ -97,7 +117,7 @@ def test_nn_forward_gauge_equivariance(torch_cuda, orc):
         s.load_gauge(to_dev(Uk))
         s.nn_set_weights(w)
         outs.append(to_host(s.nn_forward(to_dev(rk))))
-    assert relerr(outs[1], H.transform_spinor(outs[0], g)) < 1e-5
+    check_close(outs[1], H.transform_spinor(outs[0], g), 1e-5, "network equivariance")
 
 
 def test_nn_backward_parity(torch_cuda, orc):
@@ -111,8 +131,8 @@ def test_nn_backward_parity(torch_cuda, orc):
     gz = synth.gaussian_spinor(L, 205)
     gw, gin = s.nn_backward(to_dev(gz), to_dev(r))
     grads, gin_w = orc.nn_backward(L, U, orc.nn_unflatten(w), r, gz, bc)
-    assert relerr(gw.cpu().numpy().astype(np.float64), orc.nn_flatten(grads)) < 1e-4
-    assert relerr(to_host(gin), gin_w) < 1e-5
+    _check_weights(gw.cpu().numpy().astype(np.float64), orc.nn_flatten(grads), 1e-4)
+    check_close(to_host(gin), gin_w, 1e-5, "input gradient fp32")
 
 
 def test_nn_train_step_is_adam_on_the_batch_loss(torch_cuda, orc):
@@ -195,8 +215,8 @@ def test_nn_training_gain(torch_cuda, orc):
     for k in range(1, held.shape[0]):
         e = torch.view_as_complex(held[k]).to(torch.complex128).contiguous()
         r = s.dslash(e, "fp64")
-        plain = train_nn.preconditioned_residual(s, r, False)
-        learned = train_nn.preconditioned_residual(s, r, True)
+        plain = _preconditioned_residual(s, r, False)
+        learned = _preconditioned_residual(s, r, True)
         gains.append(plain / learned)
     print("preconditioned-residual gain per held-out iterate:", gains)
     assert np.mean(gains) > 1.0
@@ -232,3 +252,86 @@ def test_nn_copy_state_continues_adam(torch_cuda, orc):
     assert not torch.equal(d.nn_get_weights(), c.nn_get_weights())
     for s in (a, b, c, d):
         s.close()
+
+
+def test_nn_adam_step_matches_adam(torch_cuda, orc):
+    """sapq_nn_adam_step with a caller-supplied gradient is Adam (Kingma and Ba) on the FP32
+    master weights: two steps against the oracle's Adam in FP64, the moments carried in the
+    context between them; the layers then use the BF16-rounded result."""
+    torch = torch_cuda
+    L, B, S, kappa, eps, bc = GEOMS[NAME]
+    s = make(torch)
+    rng = np.random.default_rng(31)
+    w = rand_weights(orc, 30, 0.05).astype(np.float64)
+    s.nn_set_weights(torch.from_numpy(w.astype(np.float32)).cuda())
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    p = w.copy()
+    for t, lr in ((1, 1e-3), (2, 5e-4)):
+        g = rng.normal(size=w.size).astype(np.float32)
+        s.nn_adam_step(torch.from_numpy(g).cuda(), lr, t)
+        orc.adam_step(p, g.astype(np.float64), m, v, lr, t)
+        got = s.nn_get_weights().cpu().numpy().astype(np.float64)
+        # FP32 update of O(1e-3) steps on O(0.1) weights: a few FP32 ulps of the weights
+        assert np.abs(got - p).max() < 1e-6, (t, np.abs(got - p).max())
+    # the forward pass uses the updated weights, rounded to BF16 like any set weights
+    q = torch.from_numpy(p.astype(np.float32)).cuda()
+    r = to_dev(synth.gaussian_spinor(L, 32))
+    z1 = s.nn_forward(r)
+    s2 = make(torch)
+    s2.nn_set_weights(s.nn_get_weights())
+    assert torch.equal(z1, s2.nn_forward(r))
+    assert torch.allclose(q, s.nn_get_weights(), rtol=0, atol=1e-6)
+    s.close()
+    s2.close()
+
+
+def test_defect_errors_are_the_plain_solver_iterates(torch_cuda, orc):
+    """sapq_defect_errors: e_0 = x* (x_0 = 0) rounded to FP32; every later e_k = x* - x_k has
+    a residual b - D x_k = D e_k (checked with the oracle's D) that the defect correction
+    shrinks by about the inner tolerance per step, as section 2's outer iteration does."""
+    torch = torch_cuda
+    L, B, S, kappa, eps, bc = GEOMS[NAME]
+    U, F = fields(NAME)
+    s = make(torch)
+    b = synth.gaussian_spinor(L, 33)
+    xs, _ = s.solve(to_dev(b), tol=1e-12)
+    e = s.defect_errors(to_dev(b), xs, 4)
+    assert tuple(e.shape) == (4, int(np.prod(L)), 4, 3, 2)
+    ek = [e[k].cpu().numpy().astype(np.float64) for k in range(4)]
+    ek = [a[..., 0] + 1j * a[..., 1] for a in ek]
+    x_star = to_host(xs)
+    assert np.array_equal(ek[0], x_star.astype(np.complex64).astype(np.complex128))
+    res = []
+    for k in range(4):
+        xk = x_star - ek[k]
+        res.append(relerr(orc.dslash(L, U, F, kappa, xk, bc=bc), b))
+    print("defect-correction residuals:", res)
+    assert res[0] > 0.99  # x_0 = 0 up to FP32 rounding of e_0
+    for k in range(1, 4):
+        assert res[k] < 0.25 * res[k - 1], res  # inner tolerance 0.1 per step
+
+
+def test_precondition_with_and_without_the_stage(torch_cuda, orc):
+    """sapq_precondition: with the stage off it is M_SAP (the oracle's), with it on it is
+    N + M_SAP (1 - D N), with D P v from the SAP recurrence; both against the oracle."""
+    torch = torch_cuda
+    L, B, S, kappa, eps, bc = GEOMS[NAME]
+    U, F = fields(NAME)
+    s = make(torch, nn_fp32=True)
+    v = synth.gaussian_spinor(L, 34)
+    y_w, dy_w = orc.msap(L, B, S, U, F, orc.params(kappa), v, bc=bc)
+    y, dy = (to_host(t) for t in s.precondition(to_dev(v)))
+    check_close(y, y_w, 2e-5, "P = M_SAP")
+    check_close(dy, dy_w, 2e-5, "D P = D M_SAP")
+    w = rand_weights(orc, 35, 0.05)
+    s.nn_set_weights(torch.from_numpy(w).cuda())
+    s.use_nn(True)
+    z, _ = orc.nn_forward(L, U, orc.nn_unflatten(w), v, bc)
+    rp = v - orc.dslash(L, U, F, kappa, z, bc=bc)
+    m_w, dm_w = orc.msap(L, B, S, U, F, orc.params(kappa), rp, bc=bc)
+    y, dy = (to_host(t) for t in s.precondition(to_dev(v)))
+    # the FP32 network (1e-5) feeds the M_SAP chain (2e-5)
+    check_close(y, z + m_w, 5e-5, "P = N + M_SAP (1 - D N)")
+    check_close(dy, v - rp + dm_w, 5e-5, "D P")
+    s.close()

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_1210_7398_amd import synth
-from tests.gpu_common import GEOMS, fields, relerr, to_dev, to_host
+from tests.gpu_common import GEOMS, check_close, fields, relerr, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -41,9 +41,9 @@ def test_dslash_fp64_fp32(torch_cuda, orc, name):
     psi = synth.gaussian_spinor(L, 101)
     want = orc.dslash(L, U, F, kappa, psi, bc=bc)
     got64 = to_host(s.dslash(to_dev(psi), "fp64"))
-    assert relerr(got64, want) < 1e-14
+    check_close(got64, want, 1e-14, f"{name} D fp64")
     got32 = to_host(s.dslash(to_dev(psi), "fp32"))
-    assert relerr(got32, want) < 2e-6
+    check_close(got32, want, 2e-6, f"{name} D fp32")
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
@@ -56,7 +56,7 @@ def test_ssor_both_colours(torch_cuda, orc, name):
     for colour in (0, 1):
         want = orc.ssor(L, B, S, U, F, prm, colour, v, bc=bc)
         got = to_host(s.ssor(to_dev(v), colour))
-        assert relerr(got, want) < 2e-5, (colour, relerr(got, want))
+        check_close(got, want, 2e-5, f"{name} SSOR colour {colour}")
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
@@ -67,8 +67,8 @@ def test_dk_algorithm1(torch_cuda, orc, name):
     v = synth.gaussian_spinor(L, 103)
     x_w, w_w = orc.dk(L, B, S, U, F, orc.params(kappa), v, bc=bc)
     x, w = (to_host(t) for t in s.dk(to_dev(v)))
-    assert relerr(x, x_w) < 2e-5
-    assert relerr(w, w_w) < 2e-5
+    check_close(x, x_w, 2e-5, f"{name} DK x")
+    check_close(w, w_w, 2e-5, f"{name} DK w")
 
 
 @pytest.mark.parametrize("name", list(GEOMS))
@@ -80,8 +80,8 @@ def test_sap_precondition(torch_cuda, orc, name, n_sap):
     v = synth.gaussian_spinor(L, 104)
     y_w, dy_w = orc.msap(L, B, S, U, F, orc.params(kappa, n_sap=n_sap), v, bc=bc)
     y, dy = (to_host(t) for t in s.sap_precondition(to_dev(v)))
-    assert relerr(y, y_w) < 2e-5
-    assert relerr(dy, dy_w) < 2e-5
+    check_close(y, y_w, 2e-5, f"{name} M_SAP n_sap {n_sap}")
+    check_close(dy, dy_w, 2e-5, f"{name} D M_SAP n_sap {n_sap}")
 
 
 @pytest.mark.parametrize("name", ["8^4/4^4/2^4", "12^3x24/6^3x12/3^3x6"])
@@ -113,15 +113,18 @@ def test_solve_true_residual(torch_cuda, orc, name, outer):
     assert st["true_relres"] <= 1e-10
     xo, sto, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
     assert ok
-    assert relerr(x, xo) < 1e-8
+    check_close(x, xo, 1e-8, f"{name} {outer} solution")
 
 
 # ---------------------------------------------------------------- storage precisions
-# FP16 has a 2^-11 unit roundoff and BF16 2^-8; one operator application inherits a few of
-# them from the rounded fields and input, the SAP chain a few more per stored vector.
+# FP16 has a unit roundoff u = 2^-11 (4.9e-4) and BF16 u = 2^-8 (3.9e-3).  One operator
+# application rounds its fields and input once (about u relative over a site's sums); the SSOR
+# and the M_SAP chain store their vectors a few more times, but each stored rounding is damped
+# by the contraction that follows.  Measured on MI355X: D 0.65 u, SSOR 0.7 u, M_SAP 1.1 u in both
+# formats.  The bounds are 2 u for D and SSOR and 3 u for M_SAP.
 PREC_TOL = {
-    "fp16": dict(dslash=2e-3, ssor=5e-3, msap=1e-2),
-    "bf16": dict(dslash=2e-2, ssor=4e-2, msap=8e-2),
+    "fp16": dict(dslash=1e-3, ssor=1e-3, msap=1.5e-3),
+    "bf16": dict(dslash=8e-3, ssor=8e-3, msap=1.2e-2),
 }
 
 
@@ -134,15 +137,15 @@ def test_low_precision_storage(torch_cuda, orc, name, prec):
     s = make_solver(name, prec=prec)
     psi = synth.gaussian_spinor(L, 111)
     want = orc.dslash(L, U, F, kappa, psi, bc=bc)
-    assert relerr(to_host(s.dslash(to_dev(psi), prec)), want) < tol["dslash"]
+    check_close(to_host(s.dslash(to_dev(psi), prec)), want, tol["dslash"], f"{name} D {prec}")
     assert relerr(to_host(s.dslash(to_dev(psi), "fp64")), want) < 1e-14  # FP64 copy untouched
     prm = orc.params(kappa)
     x_w = orc.ssor(L, B, S, U, F, prm, 0, psi, bc=bc)
-    assert relerr(to_host(s.ssor(to_dev(psi), 0)), x_w) < tol["ssor"]
+    check_close(to_host(s.ssor(to_dev(psi), 0)), x_w, tol["ssor"], f"{name} SSOR {prec}")
     y_w, dy_w = orc.msap(L, B, S, U, F, prm, psi, bc=bc)
     y, dy = (to_host(t) for t in s.sap_precondition(to_dev(psi)))
-    assert relerr(y, y_w) < tol["msap"]
-    assert relerr(dy, dy_w) < tol["msap"]
+    check_close(y, y_w, tol["msap"], f"{name} M_SAP {prec}")
+    check_close(dy, dy_w, tol["msap"], f"{name} D M_SAP {prec}")
 
 
 @pytest.mark.parametrize("prec", ["fp16", "bf16"])
@@ -160,7 +163,8 @@ def test_low_precision_solve(torch_cuda, orc, prec, outer):
     rr = relerr(orc.dslash(L, U, F, kappa, x, bc=bc), b)
     assert rr <= 1e-10, (rr, st)
     xo, _, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
-    assert ok and relerr(x, xo) < 1e-8
+    assert ok
+    check_close(x, xo, 1e-8, f"{prec} {outer} solution")
 
 
 # ---------------------------------------------------------------- phase kernel variants
@@ -199,13 +203,13 @@ def test_phase_kernel_variants(torch_cuda, orc, name, kernel, monkeypatch):
     prm = orc.params(kappa, n_sap=2)
     for colour in (0, 1):
         want = orc.ssor(L, B, S, U, F, prm, colour, v, bc=bc)
-        assert relerr(to_host(s.ssor(to_dev(v), colour)), want) < 2e-5, colour
+        check_close(to_host(s.ssor(to_dev(v), colour)), want, 2e-5, f"{name} {kernel} SSOR colour {colour}")
     y_w, dy_w = orc.msap(L, B, S, U, F, prm, v, bc=bc)
     # twice in a row: the split kernel's tickets and epochs must carry over between launches
     for _ in range(2):
         y, dy = (to_host(t) for t in s.sap_precondition(to_dev(v)))
-        assert relerr(y, y_w) < 2e-5
-        assert relerr(dy, dy_w) < 2e-5
+        check_close(y, y_w, 2e-5, f"{name} {kernel} M_SAP")
+        check_close(dy, dy_w, 2e-5, f"{name} {kernel} D M_SAP")
 
 
 @pytest.mark.parametrize("kernel", ["two-lane", "two-lane split"])
@@ -220,8 +224,8 @@ def test_phase_kernel_variants_low_precision(torch_cuda, orc, kernel, prec, monk
     v = synth.gaussian_spinor(L, 122)
     y_w, dy_w = orc.msap(L, B, S, U, F, orc.params(kappa), v, bc=bc)
     y, dy = (to_host(t) for t in s.sap_precondition(to_dev(v)))
-    assert relerr(y, y_w) < PREC_TOL[prec]["msap"]
-    assert relerr(dy, dy_w) < PREC_TOL[prec]["msap"]
+    check_close(y, y_w, PREC_TOL[prec]["msap"], f"{kernel} M_SAP {prec}")
+    check_close(dy, dy_w, PREC_TOL[prec]["msap"], f"{kernel} D M_SAP {prec}")
 
 
 def test_split_kernel_solve_24x24x24x48_block(torch_cuda, orc):
@@ -238,4 +242,5 @@ def test_split_kernel_solve_24x24x24x48_block(torch_cuda, orc):
         x = to_host(x)
         assert relerr(orc.dslash(L, U, F, kappa, x, bc=bc), b) <= 1e-10, st
     xo, _, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
-    assert ok and relerr(x, xo) < 1e-8
+    assert ok
+    check_close(x, xo, 1e-8, "split-kernel solution")
