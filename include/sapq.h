@@ -187,6 +187,20 @@ int sapq_load_clover_inv(sapq_ctx *ctx, const double *F);
 int sapq_dslash(sapq_ctx *ctx, double *out, const double *in, int prec);
 
 /*
+ * For callers that cannot allocate device memory at call time (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): out = D in exactly as sapq_dslash
+ * computes it, but its two staging vectors (the operand and the result in the internal layout)
+ * live in a static device array of the library, 256 MiB per GPU, held until the process ends,
+ * instead of the context's arena.  Needs 2 x 12 V x (16 bytes for SAPQ_FP64, 8 for FP32, 4 for
+ * FP16/BF16) rounded up to 256-byte vectors, at most 256 MiB (FP64: V <= 699,050 sites, e.g.
+ * 24^3x48); a larger lattice is refused with SAPQ_ENOMEM before any work.  Allocates nothing
+ * (no hipMalloc, hipFree or allocating library call).  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (several streams or threads) race.  in, out, prec and
+ * errors as for sapq_dslash; asynchronous on the context's stream.
+ */
+int sapq_dslash_noalloc(sapq_ctx *ctx, double *out, const double *in, int prec);
+
+/*
  * x = A_cc v: the SSOR approximate inverse of the block operator on every block of
  * colour `colour` (0 = E, 1 = O), section 3 "Inverse of block operator": from x = 0,
  * n_ssor forward+backward substitution sweeps in locally-lexicographic order (with

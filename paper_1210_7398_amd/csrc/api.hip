@@ -327,6 +327,9 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     c->nn_alloc = false;
     carve(c, A, T, PT);
     c->stream = (hipStream_t)stream;
+    rc = hipcheck(hipGetDevice(&c->device), "hipGetDevice");
+    if (rc == SAPQ_OK) rc = noalloc_scratch_init(c->device);  // set-up of sapq_dslash_noalloc
+    if (rc) { delete h; return rc; }
     c->g.Vb = T.Vb;
     c->g.NB = T.NB;
     c->g.NBc = T.NB / 2;

@@ -198,6 +198,7 @@ struct Ctx {
     sapq_geom geom;
     sapq_params prm;
     hipStream_t stream;
+    int device = 0;  // the device current at creation (the arena's)
     GeomDev g;
     int max_plane;
     int ssor_threads;
@@ -289,6 +290,10 @@ void prof_end(Ctx *c, int slot);
 void prof_harvest(Ctx *c);
 
 size_t elem_bytes(int prec);  // bytes of one stored complex
+// the static scratch of sapq_dslash_noalloc: its device address on device dev (the current
+// device), looked up once per device
+int noalloc_scratch_init(int dev);
+size_t noalloc_scratch_bytes();
 void set_error(const std::string &msg);
 
 }  // namespace sapq

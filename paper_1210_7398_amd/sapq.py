@@ -68,6 +68,7 @@ _SIGS = {
     "sapq_load_gauge": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_double)]),
     "sapq_load_clover_inv": (ctypes.c_int, [_P, _P]),
     "sapq_dslash": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "sapq_dslash_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "sapq_ssor": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "sapq_dk": (ctypes.c_int, [_P, _P, _P, _P]),
     "sapq_sap_precondition": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -189,6 +190,12 @@ class Solver:
     def dslash(self, psi, prec="fp64"):
         out = self._spinor()
         _check(lib().sapq_dslash(self.h, _ptr(out), _ptr(psi, self.V, (4, 3)), PREC[prec]))
+        return out
+
+    def dslash_noalloc(self, psi, out, prec="fp64"):
+        """out = D psi through the allocation-free entry point (sapq_dslash_noalloc); out is the
+        caller's tensor, so the call allocates nothing."""
+        _check(lib().sapq_dslash_noalloc(self.h, _ptr(out, self.V, (4, 3)), _ptr(psi, self.V, (4, 3)), PREC[prec]))
         return out
 
     def ssor(self, v, colour):
