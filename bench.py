@@ -414,6 +414,13 @@ def batch_study(args):
         solvers.append(s)
         srcs.append(b)
     del flds
+    # the batched kernels' sources per workgroup and inner iterations per graph replay, timed
+    # on the batch itself (median of 3 solves per candidate, to 1e-6 to keep the tuning short)
+    t0 = time.time()
+    nr, k_inner = sapq.autotune_batch(solvers, srcs, tol=1e-6)
+    tune_batch_s = time.time() - t0
+    print(f"# batch autotune: {nr} sources per workgroup, {k_inner} inner iterations per replay "
+          f"({tune_batch_s:.1f} s)", file=sys.stderr, flush=True)
     xs, st = sapq.solve_batch(solvers, srcs, tol=1e-10)  # warm-up
     times = []
     for _ in range(max(1, args.steps)):
@@ -439,6 +446,8 @@ def batch_study(args):
         "mode": "batch", "metric": "time-to-1e-10 residual (s), 48 sources on 4 fields", "prec": args.prec,
         "fields": [dict(lattice=list(L), eps=eps, seed=seed, sources=12) for L, eps, seed in BATCH_FIELDS],
         "kappa": kappa, "block": list(B), "subblock": list(S), "autotune_s": tune_s,
+        "batch_sources_per_workgroup": nr, "batch_inner_iterations_per_replay": k_inner,
+        "autotune_batch_s": tune_batch_s,
         "batched_s": t_batch, "one_at_a_time_s": t_seq, "speedup": t_seq / t_batch,
         "batched_max_true_relres": max(x["true_relres"] for x in st),
         "batched_outer_its_max": max(x["outer_its"] for x in st),

@@ -254,10 +254,16 @@ int sapq_solve(sapq_ctx *ctx, double *x, const double *b, double tol, sapq_stats
  * sub-block shape and one prec_inner), with nrhs[i] right-hand sides for context i.  b[i] and x[i]
  * are device arrays of nrhs[i] spinors in the spinor layout ([nrhs[i]][V_i][4][3]).  All fields and
  * right-hand sides advance together: the outer iteration is FP64 defect correction
- * (x += Inner(b - D x), true residual per right-hand side), each inner BiCGStab iteration is one
- * hipGraph replay, and each SAP phase is one kernel launch over all fields, blocks and groups of
- * right-hand sides, the links and clover rows of a site being loaded once per group.  Krylov
- * scalars are per right-hand side; converged ones are masked.  When every context has the
+ * (x += Inner(b - D x), true residual per right-hand side), and each SAP phase is one kernel
+ * launch over all fields, blocks and groups of right-hand sides, the links and clover rows of a
+ * site being loaded once per group.  The whole iteration runs on the device as two hipGraphs:
+ * the outer step (apply the inner solve, true residual, per-source status and scale, a fresh
+ * inner solve) and K inner iterations; the host reads one count of running sources per replay.
+ * Krylov scalars and convergence flags are per right-hand side, on the device; finished ones are
+ * masked.  The graphs, the batch's stream and a pinned host buffer are kept (per device) and a
+ * later call on the same batch replays them.  A non-finite source, residual or inner scalar
+ * stops that right-hand side at its last finite iterate (stats.breakdowns = 1) and the call
+ * returns SAPQ_EBREAKDOWN.  When every context has the
  * learned stage on (weights set, params.flags & SAPQ_FLAG_NN), the inner preconditioner is
  * z = N r + M_SAP (r - D N r) for each right-hand side, the network applied per right-hand side
  * on its context and the SAP phases batched.  The arena size depends on that setting: size it
@@ -271,10 +277,29 @@ int sapq_solve_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *c
                      double tol, void *arena, size_t arena_bytes, sapq_stats *stats);
 
 /*
+ * Autotune the batched solver's kernel choices for one batch (arguments as sapq_solve_batch):
+ * right-hand sides per workgroup of the SAP phase kernel, NR in 1..4 (where the LDS and the
+ * workgroup size allow), and inner BiCGStab iterations per graph replay between two host
+ * checks, K in {1, 2, 4}.  Every candidate times three batched solves of the given sources to
+ * tol and keeps the median; the fastest pair is stored in every context, where later
+ * sapq_solve_batch calls use it, and returned in *nr_out, *k_out (host, nullable).  x holds
+ * the last solve's solutions.  cache_json_path (host, nullable): JSON lines keyed by the
+ * lattices, right-hand-side counts, block, sub-block, prec_inner and learned stage; a hit skips
+ * the timing, a miss appends the result.  SAPQ_ENOTCONV if no candidate reaches tol.
+ * The sub-block shape is sapq_autotune's (per context); the environment switch SAPQ_BATCH_NR,
+ * when set, overrides NR.
+ */
+int sapq_autotune_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *const *x, const double *const *b,
+                        double tol, void *arena, size_t arena_bytes, const char *cache_json_path, int *nr_out,
+                        int *k_out);
+
+/*
  * Autotune the sub-block shape of a context: every sub-block shape whose extents are 2 or more
  * and divide the block, and the even-odd site order {0, 0, 0, 0} where the context's phase
- * kernel takes it, is timed on a solve of the point source at the origin (spin 0, colour 0)
- * to 1e-10, and the fastest is kept (the ordering, hence the preconditioner, changes with it).
+ * kernel takes it, is timed on three solves of the point source at the origin (spin 0,
+ * colour 0) to 1e-10, and the one with the fastest median is kept (the ordering, hence the
+ * preconditioner, changes with it).  The phase kernel's workgroup size is not a free choice:
+ * two lanes per site of the widest hyperplane.
  * cache_json_path (host, nullable): a JSON file of earlier choices, keyed by lattice, block,
  * kappa and prec_inner; a hit skips the timing, a miss appends the result.  *subblock_out
  * (host, nullable, 4 ints) receives the choice.

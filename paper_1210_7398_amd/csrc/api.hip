@@ -2,6 +2,7 @@
 // field loading, and the host drivers of M_SAP, the inner BiCGStab and the
 // outer flexible BiCGStab / defect correction.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -327,6 +328,8 @@ int sapq_create(const sapq_geom *geom, const sapq_params *params, void *arena, s
     c->nn_alloc = false;
     carve(c, A, T, PT);
     c->stream = (hipStream_t)stream;
+    static std::atomic<unsigned long long> next_serial{1};
+    c->serial = next_serial++;
     rc = hipcheck(hipGetDevice(&c->device), "hipGetDevice");
     if (rc == SAPQ_OK) rc = noalloc_scratch_init(c->device);  // set-up of sapq_dslash_noalloc
     if (rc) { delete h; return rc; }
@@ -388,6 +391,7 @@ int sapq_set_params(sapq_ctx *h, const sapq_params *p) {
     if (p->prec_inner != h->c.prm.prec_inner) { set_error("prec_inner is fixed at creation"); return SAPQ_EINVAL; }
     if ((p->flags & SAPQ_FLAG_EOMR) && !eomr_supported(&h->c, why)) { set_error(why); return SAPQ_EINVAL; }
     h->c.prm = *p;
+    h->c.version++;
     return SAPQ_OK;
 }
 
@@ -920,6 +924,7 @@ int sapq_nn_set_weights(sapq_ctx *h, const float *w) {
     nn_prepare(c);
     rc = hipcheck(hipGetLastError(), "sapq_nn_set_weights");
     if (rc == SAPQ_OK) c->have_nn = true;
+    c->version++;
     return rc;
 }
 
@@ -951,6 +956,7 @@ int sapq_nn_copy_state(sapq_ctx *dh, sapq_ctx *sh) {
     }
     nn_prepare(d);
     d->have_nn = true;
+    d->version++;
     return hipcheck(hipGetLastError(), "sapq_nn_copy_state");
 }
 
@@ -1107,6 +1113,7 @@ static int apply_subblock(Ctx *c, const int S[4]) {
     rc = hipcheck(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     if (rc) return rc;
     c->geom.subblock[0] = S[0]; c->geom.subblock[1] = S[1]; c->geom.subblock[2] = S[2]; c->geom.subblock[3] = S[3];
+    c->version++;
     c->g.nplanes = T.nplanes;
     c->max_plane = T.max_plane;
     c->ssor_threads = std::min(512, ((4 * T.max_plane + 63) / 64) * 64);
@@ -1169,17 +1176,24 @@ int sapq_autotune(sapq_ctx *h, const char *cache_json_path, int *subblock_out) {
     c->prm.flags &= ~SAPQ_FLAG_PROFILE;
     auto try_shape = [&](const int S[4]) {
         if (apply_subblock(c, S) != SAPQ_OK) return;
-        (void)hipMemcpyAsync(c->d_ph, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
-        launch_pack_spinor(c, SAPQ_FP64, c->d_b, (const double *)c->d_ph, 1.0);
-        blas_zero(c, SAPQ_FP64, c->d_x);
-        (void)hipStreamSynchronize(c->stream);
-        auto t0 = std::chrono::steady_clock::now();
-        sapq_stats st;
-        int r2 = outer_solve(c, 1e-10, &st);
-        (void)hipStreamSynchronize(c->stream);
-        double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (r2 == SAPQ_OK && t < best_t) {
-            best_t = t;
+        // three timed solves of the point source; the median counts
+        double t3[3];
+        int r2 = SAPQ_OK;
+        for (int rep = 0; rep < 3 && r2 == SAPQ_OK; ++rep) {
+            (void)hipMemcpyAsync(c->d_ph, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            launch_pack_spinor(c, SAPQ_FP64, c->d_b, (const double *)c->d_ph, 1.0);
+            blas_zero(c, SAPQ_FP64, c->d_x);
+            (void)hipStreamSynchronize(c->stream);
+            auto t0 = std::chrono::steady_clock::now();
+            sapq_stats st;
+            r2 = outer_solve(c, 1e-10, &st);
+            (void)hipStreamSynchronize(c->stream);
+            t3[rep] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        if (r2 != SAPQ_OK) return;
+        std::sort(t3, t3 + 3);
+        if (t3[1] < best_t) {
+            best_t = t3[1];
             memcpy(best, S, sizeof best);
         }
     };

@@ -9,7 +9,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,11 +50,19 @@ struct BatchDev {
     BField f[MAX_FIELDS];
 };
 
-// per right-hand-side Krylov state on the device
+// per right-hand-side Krylov state on the device; bad: a scalar of the inner solve was not
+// finite (the source stops, its solution keeps the last finite iterate)
 struct BState {
     double2 rho, rho_old, alpha, omega, beta;
     double r0, rr;
-    int done, its;
+    int done, its, bad, pad;
+};
+
+// per right-hand-side outer state on the device
+enum { OS_RUNNING = 0, OS_CONVERGED = 1, OS_BREAKDOWN = 2 };
+struct BOuter {
+    double bnorm, relres, scale;
+    int status, outer_its, inner_its, pad;
 };
 
 // ---------------------------------------------------------------- work list decode
@@ -619,53 +629,115 @@ __device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+__device__ __forceinline__ bool finite2(double2 a) { return isfinite(a.x) && isfinite(a.y); }
+
 __global__ void k_bscalar(int step, int total, const double *__restrict__ partials, BState *__restrict__ st, double tol,
-                          int maxit, int *__restrict__ active) {
+                          int maxit) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < total) {
-        BState &S = st[k];
-        if (step == SC_INIT) {
-            // partials hold <rt, r> and <r, r>; S.done was set by the caller for converged systems
+    if (k >= total) return;
+    BState &S = st[k];
+    if (step == SC_INIT) {
+        // partials hold <rt, r> and <r, r>; S.done was set by k_bouter for stopped sources
+        S.rho = sum_part(partials, k, 0);
+        S.rr = sum_part(partials, k, 1).x;
+        S.r0 = sqrt(S.rr);
+        S.rho_old = make_double2(1, 0);
+        S.alpha = make_double2(1, 0);
+        S.omega = make_double2(1, 0);
+        S.its = 0;
+        S.bad = 0;
+        if (!S.done && (!finite2(S.rho) || !isfinite(S.r0))) { S.done = 1; S.bad = 1; }
+        if (S.r0 == 0) S.done = 1;
+    } else if (!S.done) {
+        if (step == SC_BETA) {
+            S.beta = cmul2(cdiv(S.rho, S.rho_old), cdiv(S.alpha, S.omega));
+        } else if (step == SC_ALPHA) {
+            const double2 rv = sum_part(partials, k, 0);
+            if (!finite2(rv)) { S.done = 1; S.bad = 1; }
+            else if (rv.x == 0 && rv.y == 0) { S.done = 1; S.alpha = make_double2(0, 0); }
+            else S.alpha = cdiv(S.rho, rv);
+        } else if (step == SC_OMEGA) {
+            const double2 ts = sum_part(partials, k, 0);
+            const double tt = sum_part(partials, k, 1).x;
+            if (!finite2(ts) || !isfinite(tt)) { S.done = 1; S.bad = 1; }
+            else S.omega = tt > 0 ? make_double2(ts.x / tt, ts.y / tt) : make_double2(0, 0);
+        } else if (step == SC_UPDATE) {
+            S.rho_old = S.rho;
             S.rho = sum_part(partials, k, 0);
             S.rr = sum_part(partials, k, 1).x;
-            S.r0 = sqrt(S.rr);
-            S.rho_old = make_double2(1, 0);
-            S.alpha = make_double2(1, 0);
-            S.omega = make_double2(1, 0);
-            S.its = 0;
-            if (S.r0 == 0) S.done = 1;
-        } else if (!S.done) {
-            if (step == SC_BETA) {
-                S.beta = cmul2(cdiv(S.rho, S.rho_old), cdiv(S.alpha, S.omega));
-            } else if (step == SC_ALPHA) {
-                const double2 rv = sum_part(partials, k, 0);
-                if (rv.x == 0 && rv.y == 0) { S.done = 1; S.alpha = make_double2(0, 0); }
-                else S.alpha = cdiv(S.rho, rv);
-            } else if (step == SC_OMEGA) {
-                const double2 ts = sum_part(partials, k, 0);
-                const double tt = sum_part(partials, k, 1).x;
-                S.omega = tt > 0 ? make_double2(ts.x / tt, ts.y / tt) : make_double2(0, 0);
-            } else if (step == SC_UPDATE) {
-                S.rho_old = S.rho;
-                S.rho = sum_part(partials, k, 0);
-                S.rr = sum_part(partials, k, 1).x;
-                S.its += 1;
-                if (sqrt(S.rr) <= tol * S.r0 || S.its >= maxit || (S.omega.x == 0 && S.omega.y == 0) ||
-                    (S.rho.x == 0 && S.rho.y == 0))
-                    S.done = 1;
-            }
+            S.its += 1;
+            if (!finite2(S.rho) || !isfinite(S.rr)) { S.done = 1; S.bad = 1; }
+            else if (sqrt(S.rr) <= tol * S.r0 || S.its >= maxit || (S.omega.x == 0 && S.omega.y == 0) ||
+                     (S.rho.x == 0 && S.rho.y == 0))
+                S.done = 1;
         }
     }
-    if (step == SC_UPDATE && blockIdx.x == 0 && threadIdx.x == 0) {
+}
+
+// the number of right-hand sides whose inner solve is still running, after every k_bscalar
+// of the launch has ended (one thread, in a launch of its own)
+__global__ void k_bcount(const BState *__restrict__ st, int total, int *__restrict__ active) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         int n = 0;
         for (int q = 0; q < total; ++q) n += st[q].done ? 0 : 1;
         *active = n;
     }
 }
 
+// |b| per right-hand side from the partial sums of <b, b> (start of a batched solve)
+__global__ void k_bouter_start(int total, const double *__restrict__ partials, BOuter *__restrict__ os,
+                               BState *__restrict__ st) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;
+    BOuter &O = os[k];
+    O.bnorm = sqrt(sum_part(partials, k, 0).x);
+    O.relres = 1.0;
+    O.scale = 0.0;
+    O.status = isfinite(O.bnorm) ? OS_RUNNING : OS_BREAKDOWN;
+    O.outer_its = O.inner_its = 0;
+    st[k].done = 1;
+    st[k].bad = 0;
+    st[k].its = 0;
+}
+
+// The outer step of the FP64 defect correction per right-hand side, from the partial sums of
+// |r|^2 for r = b - D x: count the inner solve just applied, the relative residual, the
+// status (converged, or breakdown on a non-finite residual or inner scalar), and for the
+// running sources the scale of the next inner right-hand side (unit RMS per complex
+// component of that field) and a fresh inner state.
+__global__ void k_bouter(const BatchDev *__restrict__ Bd, const double *__restrict__ partials, BOuter *__restrict__ os,
+                         BState *__restrict__ st, double tol) {
+    const BatchDev &B = *Bd;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= B.total_rhs) return;
+    int f = 0;
+    while (f + 1 < B.nf && k >= B.f[f + 1].rhs0) ++f;
+    BOuter &O = os[k];
+    BState &S = st[k];
+    if (O.status == OS_RUNNING && O.scale != 0) {  // an inner solve ran for this source
+        O.outer_its += 1;
+        O.inner_its += S.its;
+        if (S.bad) O.status = OS_BREAKDOWN;
+    }
+    const double rr = sum_part(partials, k, 0).x;
+    if (O.bnorm == 0) {
+        O.relres = 0.0;
+        if (O.status == OS_RUNNING) O.status = OS_CONVERGED;
+    } else {
+        O.relres = sqrt(rr) / O.bnorm;
+        if (O.status == OS_RUNNING && !isfinite(O.relres)) O.status = OS_BREAKDOWN;
+        if (O.status == OS_RUNNING && O.relres <= tol) O.status = OS_CONVERGED;
+    }
+    const bool run = O.status == OS_RUNNING;
+    O.scale = run ? sqrt((double)B.f[f].nvec) / sqrt(rr) : 0.0;
+    S.done = run ? 0 : 1;
+    S.bad = 0;
+    S.its = 0;
+}
+
 // inner storage <-> FP64 outer, with a per-right-hand-side scale from the outer norms
 template <int P>
-__global__ void k_bconvert_in(const BatchDev *__restrict__ Bd, const double *__restrict__ scale) {
+__global__ void k_bconvert_in(const BatchDev *__restrict__ Bd, const BOuter *__restrict__ os) {
     using C = typename Prec<P>::C;
     using S2 = typename Prec<P>::S2;
     const BatchDev &B = *Bd;
@@ -673,7 +745,8 @@ __global__ void k_bconvert_in(const BatchDev *__restrict__ Bd, const double *__r
     if (fi >= B.nf) return;
     const BField &F = B.f[fi];
     if (k >= F.nrhs) return;
-    const double sc = scale[F.rhs0 + k];
+    const double sc = os[F.rhs0 + k].scale;
+    if (sc == 0) return;
     const size_t ko = (size_t)k * F.nvec;
     S2 *d = (S2 *)F.iv[IV_RIN] + ko;
     const double2 *s = F.dv[DV_R] + ko;
@@ -683,16 +756,19 @@ __global__ void k_bconvert_in(const BatchDev *__restrict__ Bd, const double *__r
     }
 }
 
+// x += e / scale after an inner solve (not for a source whose inner solve broke down)
 template <int P>
-__global__ void k_bconvert_out(const BatchDev *__restrict__ Bd, const double *__restrict__ scale) {
+__global__ void k_bconvert_out(const BatchDev *__restrict__ Bd, const BOuter *__restrict__ os,
+                               const BState *__restrict__ st) {
     using S2 = typename Prec<P>::S2;
     const BatchDev &B = *Bd;
     const int fi = blockIdx.y, k = blockIdx.z;
     if (fi >= B.nf) return;
     const BField &F = B.f[fi];
     if (k >= F.nrhs) return;
-    const double sc = scale[F.rhs0 + k];
-    if (sc == 0) return;
+    const BOuter &O = os[F.rhs0 + k];
+    const double sc = O.scale;
+    if (sc == 0 || O.status != OS_RUNNING || st[F.rhs0 + k].bad) return;
     const size_t ko = (size_t)k * F.nvec;
     double2 *x = F.dv[DV_X] + ko;
     const S2 *e = (const S2 *)F.iv[IV_E] + ko;
@@ -744,9 +820,10 @@ struct Batch {
     BatchDev host;
     BatchDev *dev = nullptr;
     BState *st = nullptr;
-    double *partials = nullptr, *scale = nullptr;
-    int *active = nullptr, *host_active = nullptr;
-    double *host_scalars = nullptr;
+    BOuter *os = nullptr;
+    double *partials = nullptr;
+    int *active = nullptr;
+    int k_inner = 2;  // inner iterations per graph replay (one host check each)
 };
 
 static size_t rhs_bytes(Ctx *c, int prec) { return c->nvec * elem_bytes(prec); }
@@ -761,7 +838,7 @@ static size_t layout_batch(Batch &B, char *base) {
     B.dev = (BatchDev *)take(sizeof(BatchDev));
     B.st = (BState *)take(sizeof(BState) * B.total);
     B.partials = (double *)take(sizeof(double) * 4 * BDOT_BLOCKS * B.total);
-    B.scale = (double *)take(sizeof(double) * B.total);
+    B.os = (BOuter *)take(sizeof(BOuter) * B.total);
     B.active = (int *)take(sizeof(int) * 4);
     for (int f = 0; f < B.nf; ++f) {
         BField &F = B.host.f[f];
@@ -817,13 +894,16 @@ static int setup_batch(Batch &B, sapq_ctx *const *ctxs, int nctx, const int *nrh
     // through its L2 anyway, and one source per workgroup measured fastest.  Among the
     // permitted sizes the one that leaves the fewest empty slots in the groups of all fields
     // wins (ties to the larger).
-    int nr_cap = 1;
+    // sapq_autotune_batch's choice (batch_nr > 0) is taken as it is where the LDS allows it
+    int nr_cap = c0->batch_nr > 0 ? c0->batch_nr : 1;
     if (const char *e = getenv("SAPQ_BATCH_NR")) nr_cap = std::max(1, std::min(4, atoi(e)));
+    const int nr_only = (c0->batch_nr > 0 && !getenv("SAPQ_BATCH_NR")) ? c0->batch_nr : 0;
+    B.k_inner = c0->batch_k > 0 ? c0->batch_k : 2;
     B.NR = 0;
     long best_slots = 0;
     for (int nr : {4, 3, 2, 1}) {
         if (nr > nr_cap || nr > std::max(1, B.max_rhs) || per * nr + extra > (size_t)max_lds ||
-            (B.two_lane && nr * tpr > 768))
+            (B.two_lane && nr * tpr > 768) || (nr_only && nr != nr_only))
             continue;
         long slots = 0;
         for (int f = 0; f < nctx; ++f) slots += (long)(nrhs[f] + nr - 1) / nr * nr;
@@ -920,8 +1000,10 @@ static void bdots(Batch &B, int nd, int a0, int b0, int a1, int b1) {
 }
 
 static void bscalar(Batch &B, int step, double tol, int maxit) {
-    k_bscalar<<<(B.total + 63) / 64, 64, 0, B.stream>>>(step, B.total, B.partials, B.st, tol, maxit, B.active);
+    k_bscalar<<<(B.total + 63) / 64, 64, 0, B.stream>>>(step, B.total, B.partials, B.st, tol, maxit);
 }
+
+static void bcount(Batch &B) { k_bcount<<<1, 64, 0, B.stream>>>(B.st, B.total, B.active); }
 
 static void bxpay(Batch &B, int z, int x, int which, int y, int masked) {
     BPREC(B.prec, (k_bxpay<P_><<<vgrid(B), 256, 0, B.stream>>>(B.dev, z, x, which, y, B.st, masked)));
@@ -968,6 +1050,79 @@ static void inner_iteration(Batch &B, double tol, int maxit) {
     bscalar(B, SC_UPDATE, tol, maxit);
 }
 
+// What a batched solve keeps between calls, per device: its stream (graphs cannot be captured
+// on the legacy default stream), an event, a pinned host buffer, and the two instantiated
+// graphs with the identity of the batch they were captured for (contexts, their versions and
+// right-hand sides, arena, tolerances, kernel choices).  A call on the same batch replays them.
+struct BatchCache {
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    std::vector<unsigned long long> key;
+    hipGraphExec_t g_outer = nullptr, g_inner = nullptr;
+};
+constexpr int BATCH_MAX_DEVICES = 64;
+static BatchCache g_bcache[BATCH_MAX_DEVICES];
+static std::mutex g_bcache_mu;
+
+static void drop_graphs(BatchCache &C) {
+    if (C.g_outer) (void)hipGraphExecDestroy(C.g_outer);
+    if (C.g_inner) (void)hipGraphExecDestroy(C.g_inner);
+    C.g_outer = C.g_inner = nullptr;
+    C.key.clear();
+}
+
+static std::vector<unsigned long long> batch_key(const Batch &B, const void *arena, size_t bytes, double tol) {
+    std::vector<unsigned long long> k;
+    auto dbl = [](double v) { unsigned long long u; memcpy(&u, &v, sizeof u); return u; };
+    k.push_back((unsigned long long)(uintptr_t)arena);
+    k.push_back(bytes);
+    k.push_back(dbl(tol));
+    k.push_back((unsigned long long)B.prec | (unsigned long long)B.NR << 8 | (unsigned long long)B.k_inner << 16 |
+                (unsigned long long)B.use_nn << 24 | (unsigned long long)B.two_lane << 25);
+    for (int f = 0; f < B.nf; ++f) {
+        const Ctx *c = B.ctx[f];
+        k.push_back(c->serial);
+        k.push_back(c->version);
+        k.push_back((unsigned long long)B.host.f[f].nrhs);
+        k.push_back(dbl(c->prm.tol_inner));
+        k.push_back((unsigned long long)c->prm.maxit_inner | (unsigned long long)c->prm.n_sap << 32);
+    }
+    return k;
+}
+
+// The outer step of every right-hand side, on the device (captured once as a graph): apply the
+// inner solve just finished (x += e / scale), the true residual r = b - D x in FP64, its norms,
+// the status and scale of each source (k_bouter), the count of the running ones, and a fresh
+// inner BiCGStab on the scaled residual for those.
+static void outer_step(Batch &B, double tol, double tol_in, int maxit_in) {
+    dim3 vg = vgrid(B);
+    dim3 dg((unsigned)((4 * B.max_V + 255) / 256), (unsigned)B.nf, (unsigned)B.max_rhs);
+    dim3 bd(BDOT_BLOCKS, (unsigned)B.nf, (unsigned)B.max_rhs);
+    BPREC(B.prec, (k_bconvert_out<P_><<<vg, 256, 0, B.stream>>>(B.dev, B.os, B.st)));
+    k_bdslash64<<<dg, 256, 0, B.stream>>>(B.dev, DV_T, DV_X);
+    k_bresid<<<vg, 256, 0, B.stream>>>(B.dev);
+    k_bdots<SAPQ_FP64, true><<<bd, 256, 0, B.stream>>>(B.dev, 1, DV_R, DV_R, DV_R, DV_R, B.partials);
+    k_bouter<<<(B.total + 63) / 64, 64, 0, B.stream>>>(B.dev, B.partials, B.os, B.st, tol);
+    bcount(B);
+    BPREC(B.prec, (k_bconvert_in<P_><<<vg, 256, 0, B.stream>>>(B.dev, B.os)));
+    BPREC(B.prec, (k_bcopy<P_><<<dim3(256, B.nf), 256, 0, B.stream>>>(B.dev, IV_R, IV_RIN)));
+    BPREC(B.prec, (k_bcopy<P_><<<dim3(256, B.nf), 256, 0, B.stream>>>(B.dev, IV_RT, IV_RIN)));
+    BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, B.stream>>>(B.dev, IV_P)));
+    BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, B.stream>>>(B.dev, IV_V)));
+    BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, B.stream>>>(B.dev, IV_E)));
+    bdots(B, 2, IV_RT, IV_R, IV_R, IV_R);
+    bscalar(B, SC_INIT, tol_in, maxit_in);
+}
+
+// k_inner inner iterations of every running right-hand side and the count of those still
+// running (captured once as a graph; finished sources are masked inside the kernels)
+static void inner_steps(Batch &B, double tol_in, int maxit_in) {
+    for (int i = 0; i < B.k_inner; ++i) inner_iteration(B, tol_in, maxit_in);
+    bcount(B);
+}
+
 static int hipok(hipError_t e, const char *what) {
     if (e == hipSuccess) return SAPQ_OK;
     set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -1000,42 +1155,44 @@ int sapq_solve_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *c
     if (arena_bytes < need) { set_error("batch arena too small: need " + std::to_string(need)); return SAPQ_ENOMEM; }
     layout_batch(B, (char *)arena);
     auto t0 = std::chrono::steady_clock::now();
-    // graphs cannot be captured on the legacy default stream: run the batch on a stream of its
-    // own (default priority), ordered after the work already queued on the caller's stream
-    hipStream_t caller = B.stream, s = nullptr;
-    if ((rc = hipok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
-    {
-        hipEvent_t ev;
-        if ((rc = hipok(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreate"))) {
-            (void)hipStreamDestroy(s);
-            return rc;
-        }
-        (void)hipEventRecord(ev, caller);
-        (void)hipStreamWaitEvent(s, ev, 0);
-        (void)hipStreamSynchronize(s);
-        (void)hipEventDestroy(ev);
+    Ctx *c0 = B.ctx[0];
+    const int dev = c0->device;
+    if (dev < 0 || dev >= BATCH_MAX_DEVICES) { set_error("device index beyond the batch cache"); return SAPQ_EINVAL; }
+    std::lock_guard<std::mutex> lock(g_bcache_mu);
+    BatchCache &C = g_bcache[dev];
+    // the batch's own stream (default priority) and pinned buffer, kept for later calls
+    if (!C.stream && (rc = hipok(hipStreamCreateWithFlags(&C.stream, hipStreamNonBlocking), "hipStreamCreate"))) return rc;
+    if (!C.ev && (rc = hipok(hipEventCreateWithFlags(&C.ev, hipEventDisableTiming), "hipEventCreate"))) return rc;
+    const size_t pin_need = sizeof(int) * 4 + sizeof(BOuter) * B.total;
+    if (C.pinned_bytes < pin_need) {
+        if (C.pinned) (void)hipHostFree(C.pinned);
+        C.pinned = nullptr;
+        C.pinned_bytes = 0;
+        if ((rc = hipok(hipHostMalloc(&C.pinned, pin_need, hipHostMallocDefault), "hipHostMalloc"))) return rc;
+        C.pinned_bytes = pin_need;
     }
+    int *host_active = (int *)C.pinned;
+    BOuter *host_os = (BOuter *)((char *)C.pinned + sizeof(int) * 4);
+    hipStream_t caller = B.stream, s = C.stream;
+    // ordered after the work already queued on the caller's stream
+    (void)hipEventRecord(C.ev, caller);
+    (void)hipStreamWaitEvent(s, C.ev, 0);
     B.stream = s;
-    // the context launchers below (pack / unpack) use the context's stream: point it at ours
+    // the context launchers below (pack / unpack, the network) use the context's stream
     std::vector<hipStream_t> saved;
     for (Ctx *c : B.ctx) {
         saved.push_back(c->stream);
         c->stream = s;
     }
-    Ctx *c0 = B.ctx[0];
-    rc = hipok(hipMemcpyAsync(B.dev, &B.host, sizeof(BatchDev), hipMemcpyHostToDevice, s), "copy batch descriptor");
-    if (rc == SAPQ_OK) rc = hipok(hipHostMalloc((void **)&B.host_active, 4 * sizeof(int), hipHostMallocDefault), "hipHostMalloc");
-    if (rc) {
+    auto restore = [&]() {
         (void)hipStreamSynchronize(s);
         for (size_t f = 0; f < B.ctx.size(); ++f) B.ctx[f]->stream = saved[f];
-        (void)hipStreamDestroy(s);
-        return rc;
-    }
-    std::vector<BState> hst(B.total);
-    std::vector<double> hscale(B.total), bnorm(B.total), relres(B.total, 1.0);
-    std::vector<int> outer_its(B.total, 0), inner_its(B.total, 0), conv(B.total, 0);
-    std::vector<double2> dres(B.total * 2);
-    // pack sources, zero solutions
+    };
+    const double tol_in = c0->prm.tol_inner;
+    const int maxit_in = c0->prm.maxit_inner;
+    rc = hipok(hipMemcpyAsync(B.dev, &B.host, sizeof(BatchDev), hipMemcpyHostToDevice, s), "copy batch descriptor");
+    if (rc) { restore(); return rc; }
+    // pack the sources, zero the solutions and the inner state, |b| per source
     for (int f = 0; f < B.nf; ++f) {
         Ctx *c = B.ctx[f];
         BField &F = B.host.f[f];
@@ -1044,121 +1201,173 @@ int sapq_solve_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *c
             (void)hipMemsetAsync(F.dv[DV_X] + (size_t)k * c->nvec, 0, c->nvec * 16, s);
         }
     }
-    auto outer_norms = [&](int a, int bslot, int cslot, int dslot) {
-        dim3 g(BDOT_BLOCKS, (unsigned)B.nf, (unsigned)B.max_rhs);
-        k_bdots<SAPQ_FP64, true><<<g, 256, 0, s>>>(B.dev, 2, a, bslot, cslot, dslot, B.partials);
-        std::vector<double> hp((size_t)B.total * BDOT_BLOCKS * 4);
-        (void)hipMemcpyAsync(hp.data(), B.partials, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s);
-        (void)hipStreamSynchronize(s);
-        for (int q = 0; q < B.total; ++q) {
-            double v0 = 0, v1 = 0;
-            for (int bb = 0; bb < BDOT_BLOCKS; ++bb) {
-                v0 += hp[((size_t)q * BDOT_BLOCKS + bb) * 4 + 0];
-                v1 += hp[((size_t)q * BDOT_BLOCKS + bb) * 4 + 2];
-            }
-            dres[2 * q] = make_double2(v0, 0);
-            dres[2 * q + 1] = make_double2(v1, 0);
+    (void)hipMemsetAsync(B.st, 0, sizeof(BState) * B.total, s);
+    {
+        dim3 bd(BDOT_BLOCKS, (unsigned)B.nf, (unsigned)B.max_rhs);
+        k_bdots<SAPQ_FP64, true><<<bd, 256, 0, s>>>(B.dev, 1, DV_B, DV_B, DV_B, DV_B, B.partials);
+        k_bouter_start<<<(B.total + 63) / 64, 64, 0, s>>>(B.total, B.partials, B.os, B.st);
+    }
+    // the outer step and k_inner inner iterations as two graphs, captured on the first call for
+    // this batch and replayed after
+    const std::vector<unsigned long long> key = batch_key(B, arena, arena_bytes, tol);
+    if (C.key != key || !C.g_outer || !C.g_inner) {
+        drop_graphs(C);
+        for (int which = 0; which < 2 && rc == SAPQ_OK; ++which) {
+            hipGraph_t graph = nullptr;
+            rc = hipok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            if (rc) break;
+            if (which == 0) outer_step(B, tol, tol_in, maxit_in);
+            else inner_steps(B, tol_in, maxit_in);
+            rc = hipok(hipStreamEndCapture(s, &graph), "hipStreamEndCapture");
+            if (rc == SAPQ_OK)
+                rc = hipok(hipGraphInstantiate(which == 0 ? &C.g_outer : &C.g_inner, graph, nullptr, nullptr, 0),
+                           "hipGraphInstantiate");
+            if (graph) (void)hipGraphDestroy(graph);
         }
+        if (rc) { drop_graphs(C); restore(); return rc; }
+        C.key = key;
+    }
+    // the host reads one count per graph replay: running sources after an outer step, sources
+    // whose inner solve still runs after k_inner inner iterations
+    auto replay = [&](hipGraphExec_t g, int *count) {
+        int r = hipok(hipGraphLaunch(g, s), "hipGraphLaunch");
+        if (r == SAPQ_OK) r = hipok(hipMemcpyAsync(host_active, B.active, sizeof(int), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        if (r == SAPQ_OK) r = hipok(hipStreamSynchronize(s), "hipStreamSynchronize");
+        *count = *host_active;
+        return r;
     };
-    outer_norms(DV_B, DV_B, DV_B, DV_B);
-    for (int q = 0; q < B.total; ++q) bnorm[q] = std::sqrt(dres[2 * q].x);
-    dim3 vg(256, (unsigned)B.nf, (unsigned)B.max_rhs);
-    dim3 dg((unsigned)((4 * B.max_V + 255) / 256), (unsigned)B.nf, (unsigned)B.max_rhs);
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    const double tol_in = c0->prm.tol_inner;
-    const int maxit_in = c0->prm.maxit_inner;
-    int outer = 0;
-    rc = SAPQ_OK;
-    while (outer < c0->prm.maxit_outer) {
-        // true residual r = b - D x and convergence per right-hand side
-        k_bdslash64<<<dg, 256, 0, s>>>(B.dev, DV_T, DV_X);
-        k_bresid<<<vg, 256, 0, s>>>(B.dev);
-        outer_norms(DV_R, DV_R, DV_R, DV_R);
-        int left = 0;
-        for (int q = 0; q < B.total; ++q) {
-            relres[q] = bnorm[q] > 0 ? std::sqrt(dres[2 * q].x) / bnorm[q] : 0.0;
-            conv[q] = relres[q] <= tol;
-            hscale[q] = conv[q] ? 0.0 : std::sqrt((double)B.ctx[0]->nvec) / std::max(1e-300, std::sqrt(dres[2 * q].x));
-            left += !conv[q];
-        }
-        // per-field scale: unit RMS per complex component of that field
-        for (int f = 0; f < B.nf; ++f)
-            for (int k = 0; k < B.host.f[f].nrhs; ++k) {
-                int q = B.host.f[f].rhs0 + k;
-                if (!conv[q]) hscale[q] = std::sqrt((double)B.ctx[f]->nvec) / std::sqrt(dres[2 * q].x);
-            }
-        if (!left) break;
+    int outer = 0, running = 0, left = 0;
+    for (;;) {
+        if ((rc = replay(C.g_outer, &running))) break;
+        if (running == 0 || outer == c0->prm.maxit_outer) break;
         ++outer;
-        // inner solve of D e = r (scaled) for the unconverged right-hand sides
-        for (int q = 0; q < B.total; ++q) {
-            memset(&hst[q], 0, sizeof(BState));
-            hst[q].done = conv[q];
-            if (!conv[q]) outer_its[q]++;
-        }
-        (void)hipMemcpyAsync(B.st, hst.data(), sizeof(BState) * B.total, hipMemcpyHostToDevice, s);
-        (void)hipMemcpyAsync(B.scale, hscale.data(), sizeof(double) * B.total, hipMemcpyHostToDevice, s);
-        BPREC(B.prec, (k_bconvert_in<P_><<<vg, 256, 0, s>>>(B.dev, B.scale)));
-        BPREC(B.prec, (k_bcopy<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_R, IV_RIN)));
-        BPREC(B.prec, (k_bcopy<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_RT, IV_RIN)));
-        BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_P)));
-        BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_V)));
-        BPREC(B.prec, (k_bzero<P_><<<dim3(256, B.nf), 256, 0, s>>>(B.dev, IV_E)));
-        bdots(B, 2, IV_RT, IV_R, IV_R, IV_R);
-        bscalar(B, SC_INIT, tol_in, maxit_in);
-        if (!gexec) {
-            if ((rc = hipok(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))) break;
-            inner_iteration(B, tol_in, maxit_in);
-            if ((rc = hipok(hipStreamEndCapture(s, &graph), "hipStreamEndCapture"))) break;
-            if ((rc = hipok(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate"))) break;
-        }
-        for (int it = 0; it < maxit_in; ++it) {
-            if ((rc = hipok(hipGraphLaunch(gexec, s), "hipGraphLaunch"))) break;
-            (void)hipMemcpyAsync(B.host_active, B.active, sizeof(int), hipMemcpyDeviceToHost, s);
-            if ((rc = hipok(hipStreamSynchronize(s), "hipStreamSynchronize"))) break;
-            if (*B.host_active == 0) break;
+        for (int it = 0; it < maxit_in; it += B.k_inner) {
+            if ((rc = replay(C.g_inner, &left))) break;
+            if (left == 0) break;
         }
         if (rc) break;
-        (void)hipMemcpyAsync(hst.data(), B.st, sizeof(BState) * B.total, hipMemcpyDeviceToHost, s);
-        BPREC(B.prec, (k_bconvert_out<P_><<<vg, 256, 0, s>>>(B.dev, B.scale)));
-        (void)hipStreamSynchronize(s);
-        for (int q = 0; q < B.total; ++q)
-            if (!conv[q]) inner_its[q] += hst[q].its;
     }
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
     if (rc == SAPQ_OK) {
-        // final true residuals, unpack
-        k_bdslash64<<<dg, 256, 0, s>>>(B.dev, DV_T, DV_X);
-        k_bresid<<<vg, 256, 0, s>>>(B.dev);
-        outer_norms(DV_R, DV_R, DV_R, DV_R);
-        for (int f = 0; f < B.nf; ++f) {
+        rc = hipok(hipMemcpyAsync(host_os, B.os, sizeof(BOuter) * B.total, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+        for (int f = 0; f < B.nf && rc == SAPQ_OK; ++f) {
             Ctx *c = B.ctx[f];
             BField &F = B.host.f[f];
             for (int k = 0; k < F.nrhs; ++k)
                 launch_unpack_spinor(c, SAPQ_FP64, x[f] + (size_t)k * c->V * 24, F.dv[DV_X] + (size_t)k * c->nvec, 1.0);
         }
-        rc = hipok(hipStreamSynchronize(s), "sapq_solve_batch");
+        if (rc == SAPQ_OK) rc = hipok(hipStreamSynchronize(s), "sapq_solve_batch");
+        if (rc == SAPQ_OK) rc = hipok(hipGetLastError(), "sapq_solve_batch");
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    bool all = true;
-    for (int q = 0; q < B.total; ++q) {
-        relres[q] = bnorm[q] > 0 ? std::sqrt(dres[2 * q].x) / bnorm[q] : 0.0;
-        all = all && relres[q] <= tol;
+    bool all = rc == SAPQ_OK, broke = false;
+    for (int q = 0; q < B.total && rc == SAPQ_OK; ++q) {
+        const BOuter &O = host_os[q];
+        all = all && O.status == OS_CONVERGED;
+        broke = broke || O.status == OS_BREAKDOWN;
         if (stats) {
             memset(&stats[q], 0, sizeof(sapq_stats));
-            stats[q].outer_its = outer_its[q];
-            stats[q].inner_its = inner_its[q];
-            stats[q].true_relres = relres[q];
+            stats[q].outer_its = O.outer_its;
+            stats[q].inner_its = O.inner_its;
+            stats[q].true_relres = O.relres;
+            stats[q].breakdowns = O.status == OS_BREAKDOWN ? 1 : 0;
             stats[q].time_s = secs;
         }
     }
-    (void)hipHostFree(B.host_active);
-    (void)hipStreamSynchronize(s);
-    for (size_t f = 0; f < B.ctx.size(); ++f) B.ctx[f]->stream = saved[f];
-    (void)hipStreamDestroy(s);
+    restore();
     if (rc) return rc;
+    if (broke) { set_error("some right-hand sides broke down (a non-finite source, residual or inner scalar)"); return SAPQ_EBREAKDOWN; }
     if (!all) { set_error("some right-hand sides did not reach the tolerance"); return SAPQ_ENOTCONV; }
+    return SAPQ_OK;
+}
+
+static std::string batch_tune_key(sapq_ctx *const *ctxs, int nctx, const int *nrhs) {
+    std::string k = "batch";
+    for (int f = 0; f < nctx; ++f) {
+        const Ctx *c = &ctxs[f]->c;
+        char b[160];
+        snprintf(b, sizeof b, ";L=%dx%dx%dx%d,nrhs=%d", c->geom.L[0], c->geom.L[1], c->geom.L[2], c->geom.L[3], nrhs[f]);
+        k += b;
+    }
+    const Ctx *c = &ctxs[0]->c;
+    char b[160];
+    snprintf(b, sizeof b, ";B=%dx%dx%dx%d;S=%dx%dx%dx%d;prec=%d;nn=%d", c->geom.block[0], c->geom.block[1],
+             c->geom.block[2], c->geom.block[3], c->geom.subblock[0], c->geom.subblock[1], c->geom.subblock[2],
+             c->geom.subblock[3], c->prm.prec_inner, (c->prm.flags & SAPQ_FLAG_NN) ? 1 : 0);
+    return k + b;
+}
+
+int sapq_autotune_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *const *x, const double *const *b,
+                        double tol, void *arena, size_t arena_bytes, const char *cache_json_path, int *nr_out,
+                        int *k_out) {
+    if (!ctxs || !nrhs || !x || !b || !arena || nctx < 1 || nctx > MAX_FIELDS) { set_error("bad argument"); return SAPQ_EINVAL; }
+    for (int f = 0; f < nctx; ++f)
+        if (!ctxs[f]) { set_error("null context"); return SAPQ_EINVAL; }
+    auto set_all = [&](int nr, int k) {
+        for (int f = 0; f < nctx; ++f) {
+            ctxs[f]->c.batch_nr = nr;
+            ctxs[f]->c.batch_k = k;
+        }
+    };
+    const std::string key = batch_tune_key(ctxs, nctx, nrhs);
+    if (cache_json_path) {
+        if (FILE *fp = fopen(cache_json_path, "r")) {
+            char line[2048];
+            int nr = 0, k = 0;
+            while (fgets(line, sizeof line, fp)) {
+                const char *q = strstr(line, "\"key\": \"");
+                if (!q || strncmp(q + 8, key.c_str(), key.size()) != 0 || q[8 + key.size()] != '"') continue;
+                const char *a = strstr(line, "\"nr\": "), *c = strstr(line, "\"k_inner\": ");
+                if (a && c) { nr = atoi(a + 6); k = atoi(c + 11); }
+            }
+            fclose(fp);
+            if (nr >= 1 && nr <= 4 && k >= 1) {
+                set_all(nr, k);
+                if (nr_out) *nr_out = nr;
+                if (k_out) *k_out = k;
+                return SAPQ_OK;
+            }
+        }
+    }
+    // every candidate times three batched solves of the sources; the median counts (the first
+    // call of a candidate also captures its graphs)
+    double best_t = 1e300;
+    int best_nr = 1, best_k = 2, rc = SAPQ_OK;
+    const int K[3] = {1, 2, 4};
+    for (int nr = 1; nr <= 4; ++nr)
+        for (int ki = 0; ki < 3; ++ki) {
+            set_all(nr, K[ki]);
+            Batch B;
+            std::string why;
+            if (setup_batch(B, ctxs, nctx, nrhs, why) != SAPQ_OK || B.NR != nr) continue;
+            double t[3];
+            bool ok = true;
+            for (int r = 0; r < 3 && ok; ++r) {
+                auto t0 = std::chrono::steady_clock::now();
+                const int rr = sapq_solve_batch(ctxs, nctx, nrhs, x, b, tol, arena, arena_bytes, nullptr);
+                t[r] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                if (rr == SAPQ_EHIP || rr == SAPQ_EINVAL || rr == SAPQ_ENOMEM || rr == SAPQ_ESTATE) { rc = rr; ok = false; }
+                else if (rr != SAPQ_OK) ok = false;
+            }
+            if (rc) { set_all(0, 0); return rc; }
+            if (!ok) continue;
+            std::sort(t, t + 3);
+            if (t[1] < best_t) {
+                best_t = t[1];
+                best_nr = nr;
+                best_k = K[ki];
+            }
+        }
+    if (best_t >= 1e300) { set_all(0, 0); set_error("no candidate of the batched solver reached the tolerance"); return SAPQ_ENOTCONV; }
+    set_all(best_nr, best_k);
+    if (nr_out) *nr_out = best_nr;
+    if (k_out) *k_out = best_k;
+    if (cache_json_path) {
+        if (FILE *fp = fopen(cache_json_path, "a")) {
+            fprintf(fp, "{\"key\": \"%s\", \"nr\": %d, \"k_inner\": %d, \"time_s\": %.6f}\n", key.c_str(), best_nr,
+                    best_k, best_t);
+            fclose(fp);
+        }
+    }
     return SAPQ_OK;
 }
 

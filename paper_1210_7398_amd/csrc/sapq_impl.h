@@ -199,6 +199,12 @@ struct Ctx {
     sapq_params prm;
     hipStream_t stream;
     int device = 0;  // the device current at creation (the arena's)
+    // identity for the batched solver's graph cache: a number unique to the context and a
+    // count of the changes that alter what a captured graph launches (sub-block shape,
+    // parameters, learned stage)
+    unsigned long long serial = 0, version = 0;
+    // the batched solver's kernel choices from sapq_autotune_batch (0: default)
+    int batch_nr = 0, batch_k = 0;
     GeomDev g;
     int max_plane;
     int ssor_threads;

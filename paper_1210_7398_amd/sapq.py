@@ -89,6 +89,9 @@ _SIGS = {
     "sapq_solve_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_P),
                                         ctypes.POINTER(_P), ctypes.c_double, _P, ctypes.c_size_t, ctypes.POINTER(Stats)]),
     "sapq_autotune": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
+    "sapq_autotune_batch": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, _P, ctypes.c_size_t,
+                                           ctypes.c_char_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "sapq_phase_kernel": (ctypes.c_int, [_P]),
     "sapq_destroy": (None, [_P]),
     "sapq_last_error": (ctypes.c_char_p, []),
@@ -353,6 +356,28 @@ def solve_batch(solvers, sources, tol=1e-10, check=True):
     if check:
         _check(rc)
     return xs, [st[i].as_dict() for i in range(total)]
+
+
+def autotune_batch(solvers, sources, tol=1e-10, cache_path=None):
+    """Choose the batched solver's sources per workgroup and inner iterations per graph replay
+    for this batch (sapq_autotune_batch); returns (nr, k_inner)."""
+    n = len(solvers)
+    ctxs = (_P * n)(*[s.h for s in solvers])
+    nrhs = (ctypes.c_int * n)(*[int(b.shape[0]) for b in sources])
+    for s, b in zip(solvers, sources):
+        if b.dtype != torch.complex128 or not b.is_contiguous() or tuple(b.shape[1:]) != (s.V, 4, 3):
+            raise TypeError("expected contiguous complex128 sources [nrhs, V, 4, 3]")
+    xs = [torch.empty_like(b) for b in sources]
+    xp = (_P * n)(*[x.data_ptr() for x in xs])
+    bp = (_P * n)(*[b.data_ptr() for b in sources])
+    nbytes = lib().sapq_batch_arena_bytes(ctxs, n, nrhs)
+    if nbytes == 0:
+        raise SapqError(-1, "batch not allowed (shapes, precisions or block size)")
+    arena = _batch_arena(solvers[0].device, nbytes)
+    nr, k = ctypes.c_int(0), ctypes.c_int(0)
+    _check(lib().sapq_autotune_batch(ctxs, n, nrhs, xp, bp, tol, ctypes.c_void_p(arena.data_ptr()), nbytes,
+                                     cache_path.encode() if cache_path else None, ctypes.byref(nr), ctypes.byref(k)))
+    return nr.value, k.value
 
 
 def nn_param_count():

@@ -193,3 +193,101 @@ def test_solve_batch_even_odd_order(torch_cuda, orc):
             check_close(x[k], to_host(x1), 1e-8, f"batched vs one-source solution {L} source {k}")
     for s in solvers:
         s.close()
+
+
+def test_solve_batch_c4_fields(torch_cuda, orc):
+    """The batched workload's four fields at full size (16^3x32 eps 0.2, 24^3x48 eps 0.25 and
+    0.3, 32^3x64 eps 0.25; kappa 0.125, 4^4 blocks, 2^4 sub-blocks) with their 12 spin-colour
+    point sources, 48 solves in one call: every solution's true residual with the oracle's FP64
+    D, and the first source of every field against the one-source solver.  A second call on the
+    same batch replays the captured graphs and must give the same solutions bit for bit."""
+    from paper_1210_7398_amd import sapq
+
+    torch = torch_cuda
+    kappa, B, S = 0.125, (4, 4, 4, 4), (2, 2, 2, 2)
+    cfg = [((16, 16, 16, 32), 0.2, 11), ((24, 24, 24, 48), 0.25, 12), ((24, 24, 24, 48), 0.3, 13),
+           ((32, 32, 32, 64), 0.25, 14)]
+    dev = torch.device("cuda:0")
+    solvers, srcs, host = [], [], []
+    for L, eps, seed in cfg:
+        U = synth.gauge_field(L, eps, seed, device=dev)
+        F = synth.clover_inverse(L, U, 1.0, kappa, device=dev)
+        s = sapq.Solver(L, B, S, kappa, outer="defect")
+        s.load_gauge(U)
+        s.load_clover(F)
+        host.append((L, U.cpu().numpy(), F.cpu().numpy()))
+        del U, F
+        solvers.append(s)
+        srcs.append(to_dev(point_sources(L, 12)))
+    xs, stats = sapq.solve_batch(solvers, srcs, tol=1e-10)
+    xs2, _ = sapq.solve_batch(solvers, srcs, tol=1e-10)
+    q = 0
+    for (L, U, F), x, x2, s, b in zip(host, xs, xs2, solvers, srcs):
+        assert torch.equal(x, x2), L
+        xh, bh = to_host(x), to_host(b)
+        for k in range(12):
+            rr = relerr(orc.dslash(L, U, F, kappa, xh[k]), bh[k])
+            assert rr <= 1e-10, (L, k, rr, stats[q])
+            assert stats[q]["true_relres"] <= 1e-10 and stats[q]["breakdowns"] == 0
+            q += 1
+        x1, _ = s.solve(b[0].contiguous(), tol=1e-10)
+        check_close(xh[0], to_host(x1), 1e-8, f"C4 batched vs one-source {L}")
+    for s in solvers:
+        s.close()
+    sapq.release_batch_arena()
+
+
+def test_solve_batch_nan_source_breaks_down_alone(torch_cuda, orc):
+    """A source holding a NaN stops at once with a breakdown (EBREAKDOWN for the call); the
+    other sources of the batch still converge."""
+    from paper_1210_7398_amd import sapq
+
+    kappa, B, S, L = 0.125, (4, 4, 4, 4), (2, 2, 2, 2), (8, 8, 8, 8)
+    U, F = _field(L, 0.25, 35, kappa)
+    s = sapq.Solver(L, B, S, kappa, outer="defect")
+    s.load_gauge(to_dev(U))
+    s.load_clover(to_dev(F))
+    b = np.stack([synth.gaussian_spinor(L, 350 + k) for k in range(3)])
+    b[1, 5, 0, 0] = np.nan
+    with pytest.raises(sapq.SapqError) as e:
+        sapq.solve_batch([s], [to_dev(b)], tol=1e-10)
+    assert e.value.code == -5
+    xs, st = sapq.solve_batch([s], [to_dev(b)], tol=1e-10, check=False)
+    assert st[1]["breakdowns"] == 1 and st[1]["outer_its"] == 0
+    x = to_host(xs[0])
+    for k in (0, 2):
+        assert st[k]["breakdowns"] == 0
+        assert relerr(orc.dslash(L, U, F, kappa, x[k]), b[k]) <= 1e-10
+    s.close()
+
+
+def test_autotune_batch_picks_and_caches(torch_cuda, orc, tmp_path):
+    """sapq_autotune_batch times sources per workgroup and inner iterations per graph replay,
+    keeps a valid pair, caches it, and the batched solve with it still meets the oracle."""
+    from paper_1210_7398_amd import sapq
+
+    kappa, B, S = 0.125, (4, 4, 4, 4), (2, 2, 2, 2)
+    cfg = [((8, 8, 8, 8), 0.25, 36, 4), ((8, 8, 8, 16), 0.25, 37, 3)]
+    solvers, srcs, fields = [], [], []
+    for L, eps, seed, n in cfg:
+        U, F = _field(L, eps, seed, kappa)
+        s = sapq.Solver(L, B, S, kappa, outer="defect")
+        s.load_gauge(to_dev(U))
+        s.load_clover(to_dev(F))
+        b = np.stack([synth.gaussian_spinor(L, 360 + seed + k) for k in range(n)])
+        solvers.append(s)
+        srcs.append(to_dev(b))
+        fields.append((L, U, F, b))
+    cache = str(tmp_path / "batch_tune.jsonl")
+    nr, k = sapq.autotune_batch(solvers, srcs, tol=1e-10, cache_path=cache)
+    assert 1 <= nr <= 4 and k in (1, 2, 4)
+    assert len(open(cache).read().strip().splitlines()) == 1
+    assert sapq.autotune_batch(solvers, srcs, tol=1e-10, cache_path=cache) == (nr, k)
+    assert len(open(cache).read().strip().splitlines()) == 1
+    xs, st = sapq.solve_batch(solvers, srcs, tol=1e-10)
+    for (L, U, F, b), x in zip(fields, xs):
+        x = to_host(x)
+        for j in range(b.shape[0]):
+            assert relerr(orc.dslash(L, U, F, kappa, x[j]), b[j]) <= 1e-10
+    for s in solvers:
+        s.close()
