@@ -199,13 +199,28 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
             // i + pst[h] + part (pst[h + 1] - pst[h]) (each part owns one contiguous slot
             // range of every hyperplane, part 0 first)
             const int shift = a.NP == 2 ? pst[h] + part * (pst[h + 1] - pst[h]) : 0;
+            // At the turn of a sweep (w > 0, pi = 0) the plane repeats: the top corner of the
+            // sub-blocks after a forward sweep, the bottom corner after a backward one.  Every
+            // neighbour of such a site lies on the side just swept and has not changed since the
+            // site's last update, so with omega = 1 (no (1 - omega) x term) the update would give
+            // the same value bit for bit: it is skipped and only the boundary words are
+            // published again under the new sweep's tag.
+            const bool repeat = omega == 1.f && w > 0 && pi == 0;
             for (int i = pst[h] + q0; i < pst[h + 1]; i += nq) {
                 const int s = i + shift;
                 const int kx = a.NP == 2 ? expi[i] : -1;
+                cx<float> xn[6];
+                if (repeat) {
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        const float4 f = xs[(3 * d + q) * NS + i];
+                        xn[2 * q] = {f.x, f.y};
+                        xn[2 * q + 1] = {f.z, f.w};
+                    }
+                } else {
                 cx<float> out[6], v[6];
                 block_hop_clover(out, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
                 load6(v, vb, ib, s, d, Vb);
-                cx<float> xn[6];
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     float4 *o = &xs[(3 * d + q) * NS + i];
@@ -214,6 +229,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     xn[2 * q] = {(1.f - omega) * ov.x + omega * n0.r, (1.f - omega) * ov.y + omega * n0.i};
                     xn[2 * q + 1] = {(1.f - omega) * ov.z + omega * n1.r, (1.f - omega) * ov.w + omega * n1.i};
                     *o = make_float4(xn[2 * q].r, xn[2 * q].i, xn[2 * q + 1].r, xn[2 * q + 1].i);
+                }
                 }
                 if (kx >= 0) {
                     const unsigned wt = xch_tag(epoch, w);
