@@ -93,6 +93,23 @@ def omp_threads(n=None):
     return int(gomp.omp_get_max_threads())
 
 
+def oracle_solve_chunked(L, B, S, U, F, kappa, b, tol, label, chunk=2, max_calls=200):
+    """The oracle's solve of D x = b to tol in calls of `chunk` outer iterations, each resuming
+    from the last iterate and printing its residual, so that a long solve reports progress.
+    Returns (x, converged, seconds)."""
+    import oracle
+
+    prm = oracle.params(kappa, tol_inner=0.1, maxit_outer=chunk)
+    x, t0 = None, time.perf_counter()
+    for k in range(max_calls):
+        x, st, ok = oracle.solve(L, B, S, U, F, prm, b, tol=tol, x0=x)
+        print(f"# oracle {label}: call {k}, relres {st['relres']:.2e} after {time.perf_counter() - t0:.0f} s",
+              file=sys.stderr, flush=True)
+        if ok:
+            return x, True, time.perf_counter() - t0
+    return x, False, time.perf_counter() - t0
+
+
 def oracle_reference(w, U, F, b, x_gpu, tol=1e-10, tol_inner=0.1, one_thread_sample=True):
     """The FP64 CPU oracle beside the GPU solve of the same system (fields, source, blocks,
     sweeps and inner tolerance).  Returns (cpu_baseline, accuracy):
@@ -189,9 +206,8 @@ def precision_study(args):
     import oracle
 
     del Ud, Fd
-    t0 = time.perf_counter()
-    xo, sto, ok = oracle.solve(w["L"], w["B"], w["S"], U, F, oracle.params(w["kappa"], tol_inner=0.1), b, tol=1e-12)
-    t_or = time.perf_counter() - t0
+    xo, ok, t_or = oracle_solve_chunked(w["L"], w["B"], w["S"], U, F, w["kappa"], b, 1e-12, wl)
+    sto = dict(relres=float(np.linalg.norm(b - oracle.dslash(w["L"], U, F, w["kappa"], xo)) / np.linalg.norm(b)))
     for r, x in zip(res, xs):
         r["err_vs_oracle"] = float(np.linalg.norm(x - xo) / np.linalg.norm(xo))
         r["true_relres_oracle_D"] = float(np.linalg.norm(b - oracle.dslash(w["L"], U, F, w["kappa"], x))
@@ -201,8 +217,9 @@ def precision_study(args):
                       "oracle": oracle_info}), flush=True)
 
 
-def _solve_stats(s, bd, steps):
-    """Median time of `steps` solves after one warm-up, with the last solve's statistics."""
+def _solve_stats(s, bd, steps, x_oracle=None):
+    """Median time of `steps` solves after one warm-up, with the last solve's statistics; with
+    x_oracle (host), the last solution's error against it is added to the statistics."""
     import torch
 
     s.solve(bd, tol=1e-10)
@@ -213,9 +230,21 @@ def _solve_stats(s, bd, steps):
         x, st = s.solve(bd, tol=1e-10, profile=True)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+    if x_oracle is not None:
+        xh = x.cpu().numpy()
+        st["err_vs_oracle"] = float(np.linalg.norm(xh - x_oracle) / np.linalg.norm(x_oracle))
     ph = st["kernels"].get("phase_E", {}), st["kernels"].get("phase_O", {})
     n_ph = ph[0].get("n", 0) + ph[1].get("n", 0)
     return sorted(times)[len(times) // 2], st, (1e3 * (ph[0].get("ms", 0) + ph[1].get("ms", 0)) / n_ph) if n_ph else None
+
+
+def c2_oracle_solution(w, U, F, b):
+    """The oracle's solve of the 24^3x48 workload's system to 1e-12 (the reference solution the
+    studies state their error against)."""
+    x, ok, t = oracle_solve_chunked(w["L"], w["B"], w["S"], U, F, w["kappa"], b, 1e-12, "24^3x48")
+    if not ok:
+        raise RuntimeError("the oracle's reference solve did not converge")
+    return x, t
 
 
 # (block, sub-block, block solver) of the block study at 24^3x48: sub-block = block is the
@@ -242,23 +271,26 @@ def blocks_study(args):
     U, F, b = make_inputs(w)
     dev = torch.device("cuda:0")
     Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
+    xo, t_or = c2_oracle_solution(w, U, F, b)
     del U, F
     res = []
     for B, S, solver in BLOCK_SHAPES:
         s = sapq.Solver(w["L"], B, S, w["kappa"], device=dev, block_solver=solver)
         s.load_gauge(Ud)
         s.load_clover(Fd)
-        t, st, ph_us = _solve_stats(s, bd, args.steps)
+        t, st, ph_us = _solve_stats(s, bd, args.steps, xo)
         res.append(dict(block=list(B), subblock=list(S), block_solver=solver, phase_kernel=s.phase_kernel, time_s=t,
                         n_msap=st["n_msap"],
                         inner_its=st["inner_its"], outer_its=st["outer_its"], true_relres=st["true_relres"],
-                        sap_phase_avg_us=ph_us))
+                        err_vs_oracle=st["err_vs_oracle"], sap_phase_avg_us=ph_us))
         print(f"# {res[-1]}", file=sys.stderr, flush=True)
         s.close()
         del s
         torch.cuda.empty_cache()
-    print(json.dumps({"mode": "blocks", "lattice": list(w["L"]), "kappa": w["kappa"], "tol": 1e-10, "results": res}),
-          flush=True)
+    print(json.dumps({"mode": "blocks", "lattice": list(w["L"]), "kappa": w["kappa"], "tol": 1e-10, "results": res,
+                      "oracle": dict(tol=1e-12, time_s=t_or, threads=omp_threads(),
+                                     note="err_vs_oracle = |x - x_oracle| / |x_oracle|, x_oracle the oracle's 1e-12 "
+                                          "solve of the same system")}), flush=True)
 
 
 def nsap_study(args):
@@ -273,16 +305,17 @@ def nsap_study(args):
     U, F, b = make_inputs(w)
     dev = torch.device("cuda:0")
     Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
+    xo, t_or = c2_oracle_solution(w, U, F, b)
     del U, F
     res = []
     for n_sap in (1, 2, 3, 4, 6, 8):
         s = sapq.Solver(w["L"], w["B"], w["S"], w["kappa"], n_sap=n_sap, maxit_outer=400, device=dev)
         s.load_gauge(Ud)
         s.load_clover(Fd)
-        t, st, ph_us = _solve_stats(s, bd, args.steps)
+        t, st, ph_us = _solve_stats(s, bd, args.steps, xo)
         res.append(dict(n_sap=n_sap, time_s=t, n_msap=st["n_msap"], phase_launches=2 * n_sap * st["n_msap"],
                         inner_its=st["inner_its"], outer_its=st["outer_its"], true_relres=st["true_relres"],
-                        sap_phase_avg_us=ph_us))
+                        err_vs_oracle=st["err_vs_oracle"], sap_phase_avg_us=ph_us))
         print(f"# {res[-1]}", file=sys.stderr, flush=True)
         s.close()
         del s
@@ -304,17 +337,18 @@ def omega_study(args):
     dev = torch.device("cuda:0")
     Ud, Fd, bd = (torch.from_numpy(a).to(dev) for a in (U, F, b))
     extra = [torch.from_numpy(synth.gaussian_spinor(w["L"], w["seed_b"] + k)).to(dev) for k in (1, 2, 3)]
+    xo, t_or = c2_oracle_solution(w, U, F, b)
     del U, F
     res = []
     for omega in (0.8, 0.9, 1.0, 1.1, 1.2, 1.3, 1.4):
         s = sapq.Solver(w["L"], w["B"], w["S"], w["kappa"], omega=omega, maxit_outer=400, device=dev)
         s.load_gauge(Ud)
         s.load_clover(Fd)
-        t, st, ph_us = _solve_stats(s, bd, args.steps)
+        t, st, ph_us = _solve_stats(s, bd, args.steps, xo)
         n_extra = [s.solve(e, tol=1e-10)[1]["n_msap"] for e in extra]
         res.append(dict(omega=omega, time_s=t, n_msap=st["n_msap"], inner_its=st["inner_its"],
-                        outer_its=st["outer_its"], true_relres=st["true_relres"], sap_phase_avg_us=ph_us,
-                        n_msap_more_sources=n_extra))
+                        outer_its=st["outer_its"], true_relres=st["true_relres"], err_vs_oracle=st["err_vs_oracle"],
+                        sap_phase_avg_us=ph_us, n_msap_more_sources=n_extra))
         print(f"# {res[-1]}", file=sys.stderr, flush=True)
         s.close()
         del s
@@ -348,14 +382,26 @@ def sustained_study(args):
         s = sapq.Solver(L, B, S, kappa, device=dev)
         s.load_gauge(Ud)
         s.load_clover(Fd)
+        Uh, Fh, bh = Ud.cpu().numpy(), Fd.cpu().numpy(), bd.cpu().numpy()
         del Ud, Fd
         t, st, ph_us = _solve_stats(s, bd, args.steps)
+        # the GPU solution against the oracle: its error against the oracle's 1e-12 solve where
+        # that solve is feasible, else (48^3x96) only its residual with the oracle's D
+        import oracle
+
+        xg = s.solve(bd, tol=1e-10)[0].cpu().numpy()
+        acc = dict(true_relres_oracle_D=float(np.linalg.norm(bh - oracle.dslash(L, Uh, Fh, kappa, xg))
+                                              / np.linalg.norm(bh)))
+        if L[3] <= 48:
+            xo, ok, _ = oracle_solve_chunked(L, B, S, Uh, Fh, kappa, bh, 1e-12, "x".join(map(str, L)))
+            acc["err_vs_oracle"] = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+        del Uh, Fh, bh, xg
         V = int(np.prod(L))
         fl = st["n_msap"] * msap_flops(B, V) + st["n_dslash64"] * V * (8 * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS)
         res.append(dict(lattice=list(L), time_s=t, n_msap=st["n_msap"], n_dslash64=st["n_dslash64"],
                         true_relres=st["true_relres"], flops=fl, TFLOPs=fl / t / 1e12,
                         frac_fp32_peak=fl / t / 1e12 / FP32_PEAK_TFLOPS,
-                        frac_fp32_unpacked=fl / t / 1e12 / (FP32_PEAK_TFLOPS / 2), sap_phase_avg_us=ph_us))
+                        frac_fp32_unpacked=fl / t / 1e12 / (FP32_PEAK_TFLOPS / 2), sap_phase_avg_us=ph_us, **acc))
         print(f"# {res[-1]}", file=sys.stderr, flush=True)
         s.close()
         del s, bd
@@ -462,12 +508,11 @@ def batch_study(args):
     for (L, U, F), x in zip(host_fields, xs):
         b0 = synth.point_source(L, 0, 0)
         x0 = x[0].cpu().numpy()
-        t1 = time.perf_counter()
-        xo, sto, ok = oracle.solve(L, B, S, U, F, oracle.params(kappa, tol_inner=0.1), b0, tol=1e-12)
+        xo, ok, t_or = oracle_solve_chunked(L, B, S, U, F, kappa, b0, 1e-12, "x".join(map(str, L)))
         acc.append(dict(lattice=list(L), err_vs_oracle=float(np.linalg.norm(x0 - xo) / np.linalg.norm(xo)),
                         true_relres_oracle_D=float(np.linalg.norm(b0 - oracle.dslash(L, U, F, kappa, x0))
                                                    / np.linalg.norm(b0)),
-                        oracle_converged=bool(ok), oracle_s=time.perf_counter() - t1))
+                        oracle_converged=bool(ok), oracle_s=t_or))
         print(f"# oracle check {acc[-1]}", file=sys.stderr, flush=True)
     out["accuracy_source0_per_field"] = acc
     out["oracle_threads"] = omp_threads()
@@ -942,6 +987,12 @@ def main():
                          frac_hbm=(d_bytes * V / d_avg / 1e9 / HBM_PEAK_GBS) if d_avg else None),
         face=dict(avg_us=k["face"]["avg_us"], launches=k["face"]["launches"]),
     )
+    # the operator in the inner storage precision, timed alone (20 launches between HIP events)
+    p_in = args.prec
+    d_in_bytes, _ = dslash_model(4 if p_in == "fp32" else 2)
+    d_us = solver.time_dslash(bd, p_in, 20)
+    kernels[f"dslash_{p_in}"] = dict(avg_us=d_us, launches=20, GBps=d_in_bytes * V / (d_us * 1e-6) / 1e9,
+                                    frac_hbm=d_in_bytes * V / (d_us * 1e-6) / 1e9 / HBM_PEAK_GBS)
 
     cpu, accuracy = None, None
     if not args.no_cpu_baseline:

@@ -187,6 +187,14 @@ int sapq_load_clover_inv(sapq_ctx *ctx, const double *F);
 int sapq_dslash(sapq_ctx *ctx, double *out, const double *in, int prec);
 
 /*
+ * Measurement: the operator kernel of sapq_dslash alone (without the layout conversions),
+ * applied reps >= 1 times to in (packed once into the context's internal work vectors) between
+ * two HIP events on the context's stream, after one untimed application; *avg_us (host)
+ * receives the mean time per application in microseconds.  prec as for sapq_dslash.  Synchronises.
+ */
+int sapq_time_dslash(sapq_ctx *ctx, const double *in, int prec, int reps, double *avg_us);
+
+/*
  * For callers that cannot allocate device memory at call time (code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation): out = D in exactly as sapq_dslash
  * computes it, but its two staging vectors (the operand and the result in the internal layout)

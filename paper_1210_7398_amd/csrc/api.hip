@@ -471,6 +471,31 @@ int sapq_dslash(sapq_ctx *h, double *out, const double *in, int prec) {
     return hipcheck(hipGetLastError(), "sapq_dslash");
 }
 
+int sapq_time_dslash(sapq_ctx *h, const double *in, int prec, int reps, double *avg_us) {
+    if (!h || !in || !avg_us || reps < 1) { set_error("bad argument"); return SAPQ_EINVAL; }
+    Ctx *c = &h->c;
+    if (prec != SAPQ_FP64 && prec != c->prm.prec_inner) { set_error("prec must be SAPQ_FP64 or the context's prec_inner"); return SAPQ_EINVAL; }
+    int rc = ready(c);
+    if (rc) return rc;
+    void *a = prec == SAPQ_FP64 ? (void *)c->d_tmp : c->i_tmp;
+    void *b = prec == SAPQ_FP64 ? (void *)c->d_v : c->i_v;
+    launch_pack_spinor(c, prec, a, in, 1.0);
+    launch_dslash(c, prec, b, a);  // warm-up
+    hipEvent_t e0, e1;
+    if ((rc = hipcheck(hipEventCreate(&e0), "hipEventCreate"))) return rc;
+    if ((rc = hipcheck(hipEventCreate(&e1), "hipEventCreate"))) { (void)hipEventDestroy(e0); return rc; }
+    (void)hipEventRecord(e0, c->stream);
+    for (int k = 0; k < reps; ++k) launch_dslash(c, prec, b, a);
+    (void)hipEventRecord(e1, c->stream);
+    rc = hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0;
+    if (rc == SAPQ_OK) rc = hipcheck(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == SAPQ_OK) *avg_us = 1e3 * ms / reps;
+    return rc ? rc : hipcheck(hipGetLastError(), "sapq_time_dslash");
+}
+
 int sapq_ssor(sapq_ctx *h, double *x, const double *v, int colour) {
     if (!h || !x || !v || (colour != 0 && colour != 1)) { set_error("bad argument"); return SAPQ_EINVAL; }
     Ctx *c = &h->c;

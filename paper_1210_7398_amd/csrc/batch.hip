@@ -160,6 +160,8 @@ __global__ void __launch_bounds__(512) k_bsap_phase(const BatchDev *__restrict__
     for (int sw = 0; sw < F.n_ssor; ++sw) {
         for (int dir = 0; dir < 2; ++dir) {
             for (int pi = 0; pi < g.nplanes; ++pi) {
+                // omega = 1: the repeated plane at a sweep turn keeps its values (as above)
+                if (omega == 1.f && (sw > 0 || dir > 0) && pi == 0) continue;
                 const int p = dir == 0 ? pi : g.nplanes - 1 - pi;
                 const int s0 = ps_lds[p], s1 = ps_lds[p + 1];
                 for (int s = s0 + q0; s < s1; s += nq) {
@@ -297,10 +299,13 @@ __global__ void __launch_bounds__(768) k_bsap_phase_2l(const BatchDev *__restric
     }
     __syncthreads();
 
-    // 2. sweeps, one hyperplane per step
+    // 2. sweeps, one hyperplane per step; with omega = 1 the repeated plane at the turn of a
+    // sweep would get bit-identical values (its neighbours all lie on the side just swept and
+    // are unchanged), so that step is skipped (uniform over the workgroup: one field)
     const int H = g.nplanes;
     for (int sw = 0; sw < 2 * F.n_ssor; ++sw) {
         for (int pi = 0; pi < H; ++pi) {
+            if (omega == 1.f && sw > 0 && pi == 0) continue;
             const int h = (sw & 1) == 0 ? pi : H - 1 - pi;
             for (int i = F.pst[h] + q0; live && i < F.pst[h + 1]; i += nq) {
                 cx<float> out[6], v[6];

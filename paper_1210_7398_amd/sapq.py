@@ -69,6 +69,7 @@ _SIGS = {
     "sapq_load_clover_inv": (ctypes.c_int, [_P, _P]),
     "sapq_dslash": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "sapq_dslash_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
+    "sapq_time_dslash": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "sapq_ssor": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "sapq_dk": (ctypes.c_int, [_P, _P, _P, _P]),
     "sapq_sap_precondition": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -194,6 +195,12 @@ class Solver:
         out = self._spinor()
         _check(lib().sapq_dslash(self.h, _ptr(out), _ptr(psi, self.V, (4, 3)), PREC[prec]))
         return out
+
+    def time_dslash(self, psi, prec="fp64", reps=20):
+        """Mean microseconds of one operator kernel launch (sapq_time_dslash)."""
+        us = ctypes.c_double(0)
+        _check(lib().sapq_time_dslash(self.h, _ptr(psi, self.V, (4, 3)), PREC[prec], int(reps), ctypes.byref(us)))
+        return us.value
 
     def dslash_noalloc(self, psi, out, prec="fp64"):
         """out = D psi through the allocation-free entry point (sapq_dslash_noalloc); out is the

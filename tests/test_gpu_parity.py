@@ -244,3 +244,17 @@ def test_split_kernel_solve_24x24x24x48_block(torch_cuda, orc):
     xo, _, ok = orc.solve(L, B, S, U, F, orc.params(kappa), b, tol=1e-12, bc=bc)
     assert ok
     check_close(x, xo, 1e-8, "split-kernel solution")
+
+
+def test_time_dslash_measures_the_operator_alone(torch_cuda, orc):
+    """sapq_time_dslash reports a positive mean time per operator launch in both precisions and
+    leaves the context usable: the next dslash still matches the oracle."""
+    name = "12^3x24/6^3x12/3^3x6"
+    L, B, S, kappa, eps, bc = GEOMS[name]
+    U, F = fields(name)
+    s = make_solver(name)
+    psi = synth.gaussian_spinor(L, 131)
+    for p in ("fp64", "fp32"):
+        us = s.time_dslash(to_dev(psi), p, 5)
+        assert 0.0 < us < 1e5, (p, us)
+    check_close(to_host(s.dslash(to_dev(psi), "fp64")), orc.dslash(L, U, F, kappa, psi, bc=bc), 1e-14, "D after timing")
