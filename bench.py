@@ -808,6 +808,50 @@ def learned_stage_headline(args):
     }
 
 
+def nn_apply_study(args):
+    """The cost of the learned stage inside the inner preconditioner at 48^3x96 (the learned-stage
+    workload's application lattice, 4^4 blocks in the even-odd site order the autotuner picks
+    there, FP16 storage): one application of P = N + M_SAP (1 - D N) against one of M_SAP
+    alone (sapq_precondition), each timed with CUDA events over 5 applications after one
+    warm-up.  The weights are the training's starting point (the time does not depend on them).
+    Prints one JSON line; run under rocprofv3 --kernel-trace for the per-layer times."""
+    import torch
+
+    from paper_1210_7398_amd import sapq, synth, train_nn
+
+    kappa, B, S, La = 0.125, (4, 4, 4, 4), (0, 0, 0, 0), (48, 48, 48, 96)
+    dev = torch.device("cuda:0")
+    U = synth.gauge_field(La, 0.25, 31, device=dev)
+    F = synth.clover_inverse(La, U, 1.0, kappa, device=dev)
+    res = {}
+    for prec in ("fp16", "fp32"):
+        s = sapq.Solver(La, B, S, kappa, prec=prec, nn=True, device=dev)
+        s.load_gauge(U)
+        s.load_clover(F)
+        s.nn_set_weights(train_nn.init_weights(0, device=dev))
+        r = torch.from_numpy(synth.gaussian_spinor(La, 3101)).to(dev)
+        for use in (True, False):
+            s.use_nn(use)
+            s.precondition(r)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(5):
+                s.precondition(r)
+            e1.record()
+            torch.cuda.synchronize()
+            key = f"{prec}_{'stage_and_msap' if use else 'msap'}_ms"
+            res[key] = e0.elapsed_time(e1) / 5
+            print(f"# {key}: {res[key]:.2f}", file=sys.stderr, flush=True)
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    for prec in ("fp16", "fp32"):
+        res[f"{prec}_stage_ms"] = res[f"{prec}_stage_and_msap_ms"] - res[f"{prec}_msap_ms"]
+        res[f"{prec}_stage_over_msap"] = res[f"{prec}_stage_ms"] / res[f"{prec}_msap_ms"]
+    print(json.dumps({"mode": "nn_apply", "lattice": list(La), "block": list(B), "subblock": list(S), **res}), flush=True)
+
+
 def phase_model(B, n_ssor, prec_bytes):
     """Algorithmic bytes and flops per site of one SAP phase kernel launch (a cycle after the
     first: it gathers the other colour and accumulates y).  Each operand is counted once."""
@@ -837,14 +881,18 @@ def dslash_model(prec_bytes):
     return S * (24 + 48 + 72 + 24), 8 * HOP_FLOPS + CLOVER_FLOPS + AXPY_FLOPS
 
 
-def csrc_sha256():
-    """Hash of every kernel and host source of the library (sorted by name)."""
+# the sources the SAP phase kernel (k_sap_phase_parts) is built from: its file and the headers
+# it includes (counters taken on other sources no longer describe it)
+PHASE_KERNEL_SOURCES = ("sap_parts.hip", "twolane.h", "sitecore.h", "sapq_impl.h", "tables.h")
+
+
+def csrc_sha256(names=PHASE_KERNEL_SOURCES):
+    """Hash of the named library sources (in the given order)."""
     d = os.path.join(ROOT, "paper_1210_7398_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            h.update(open(os.path.join(d, name), "rb").read())
+    for name in names:
+        h.update(name.encode())
+        h.update(open(os.path.join(d, name), "rb").read())
     return h.hexdigest()
 
 
@@ -876,7 +924,7 @@ def main():
                     help="leave out the learned-stage headline object (48^3x96, 12 sources)")
     ap.add_argument("--nn-train-steps", type=int, default=300)
     ap.add_argument("--mode", default="solve", choices=["solve", "copy", "precision", "batch", "nn", "blocks",
-                                                        "sustained", "nsap", "omega"])
+                                                        "sustained", "nsap", "omega", "nn_apply"])
     ap.add_argument("--outer", default="fbicgstab", choices=["fbicgstab", "defect"])
     args = ap.parse_args()
     if args.gpus != 1:
@@ -906,6 +954,9 @@ def main():
         return
     if args.mode == "sustained":
         sustained_study(args)
+        return
+    if args.mode == "nn_apply":
+        nn_apply_study(args)
         return
 
     import numpy as np
