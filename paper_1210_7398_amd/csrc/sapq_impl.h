@@ -70,6 +70,28 @@ template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
 template <typename T> __device__ __forceinline__ cx<T> conjx(cx<T> a) { return {a.r, -a.i}; }
 template <typename T> __device__ __forceinline__ cx<T> itimes(cx<T> a) { return {-a.i, a.r}; }
 
+// Fused forms for the site kernels: every product is added into its accumulator by a fused
+// multiply-add (two per real component of a complex product, one of a real one), instead of
+// being rounded and added separately.
+__device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {  // acc + a b
+    return {fmx(-a.i, b.i, fmx(a.r, b.r, acc.r)), fmx(a.i, b.r, fmx(a.r, b.i, acc.i))};
+}
+template <typename T> __device__ __forceinline__ cx<T> cfmac(cx<T> a, cx<T> b, cx<T> acc) {  // acc + conj(a) b
+    return {fmx(a.i, b.i, fmx(a.r, b.r, acc.r)), fmx(-a.i, b.r, fmx(a.r, b.i, acc.i))};
+}
+template <typename T> __device__ __forceinline__ cx<T> rfma(T s, cx<T> a, cx<T> acc) {  // acc + s a, s real
+    return {fmx(s, a.r, acc.r), fmx(s, a.i, acc.i)};
+}
+// row 2 of an SU(3) link from rows 0 and 1: conj(row0 x row1)
+template <typename T> __device__ __forceinline__ void su3_row2(cx<T> u[9]) {
+    const cx<T> m1 = {-u[1].r, -u[1].i}, m2 = {-u[2].r, -u[2].i}, m0 = {-u[0].r, -u[0].i};
+    u[6] = conjx(cfma(m2, u[4], cmul(u[1], u[5])));
+    u[7] = conjx(cfma(m0, u[5], cmul(u[2], u[3])));
+    u[8] = conjx(cfma(m1, u[3], cmul(u[0], u[4])));
+}
+
 // storage <-> compute
 __device__ __forceinline__ cx<double> ld(const double2 *p) { double2 v = *p; return {v.x, v.y}; }
 __device__ __forceinline__ cx<float> ld(const float2 *p) { float2 v = *p; return {v.x, v.y}; }
@@ -112,10 +134,7 @@ __device__ __forceinline__ void load_link(cx<C> u[9], const S2 *U, const GeomDev
     const S2 *p = U + ((size_t)ib * 4 + mu) * 6 * g.Vb + s;
 #pragma unroll
     for (int e = 0; e < 6; ++e) u[e] = ld(p + (size_t)e * g.Vb);
-    // row2 = conj(row0 x row1)
-    u[6] = conjx(cmul(u[1], u[5]) - cmul(u[2], u[4]));
-    u[7] = conjx(cmul(u[2], u[3]) - cmul(u[0], u[5]));
-    u[8] = conjx(cmul(u[0], u[4]) - cmul(u[1], u[3]));
+    su3_row2(u);
 }
 
 // out = U h (dag = false) or U^+ h (dag = true) for a colour 3-vector
@@ -123,10 +142,10 @@ template <typename C>
 __device__ __forceinline__ void su3_mul(cx<C> out[3], const cx<C> u[9], const cx<C> h[3], bool dag) {
     if (!dag) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out[a] = cmul(u[3 * a], h[0]) + cmul(u[3 * a + 1], h[1]) + cmul(u[3 * a + 2], h[2]);
+        for (int a = 0; a < 3; ++a) out[a] = cfma(u[3 * a + 2], h[2], cfma(u[3 * a + 1], h[1], cmul(u[3 * a], h[0])));
     } else {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) out[a] = cmulc(u[a], h[0]) + cmulc(u[3 + a], h[1]) + cmulc(u[6 + a], h[2]);
+        for (int a = 0; a < 3; ++a) out[a] = cfmac(u[6 + a], h[2], cfmac(u[3 + a], h[1], cmulc(u[a], h[0])));
     }
 }
 

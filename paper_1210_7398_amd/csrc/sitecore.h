@@ -72,16 +72,16 @@ __device__ __forceinline__ void lane_hop(cx<C> acc[12], const cx<C> psi[12], con
     for (int a = 0; a < 3; ++a) {
         cx<C> pa0 = sel(a0_is3, psi[9 + a], psi[6 + a]);
         cx<C> pa1 = sel(a0_is3, psi[6 + a], psi[9 + a]);
-        h0[a] = psi[a] + cmul(c0, pa0);
-        h1[a] = psi[3 + a] + cmul(c1, pa1);
+        h0[a] = cfma(c0, pa0, psi[a]);
+        h1[a] = cfma(c1, pa1, psi[3 + a]);
     }
     su3_mul(g0, u, h0, dag);
     su3_mul(g1, u, h1, dag);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         cx<C> q0 = phase * g0[a], q1 = phase * g1[a];
-        acc[a] = acc[a] + q0;
-        acc[3 + a] = acc[3 + a] + q1;
+        acc[a] = rfma(phase, g0[a], acc[a]);
+        acc[3 + a] = rfma(phase, g1[a], acc[3 + a]);
         cx<C> t0 = cmulc(c0, q0), t1 = cmulc(c1, q1);
         acc[6 + a] = acc[6 + a] + sel(a0_is3, t1, t0);
         acc[9 + a] = acc[9 + a] + sel(a0_is3, t0, t1);
@@ -249,12 +249,12 @@ __device__ __forceinline__ void lane_clover_apply(cx<C> out[3], const cx<C> h[12
         own[a] = sel(hi, l, u);
         oth[a] = sel(hi, u, l);
     }
-    out[0] = L.dg[0] * own[0] + cmulc(L.h10, own[1]) + cmulc(L.h20, own[2]);
-    out[1] = L.dg[1] * own[1] + cmul(L.h10, own[0]) + cmulc(L.h21, own[2]);
-    out[2] = L.dg[2] * own[2] + cmul(L.h20, own[0]) + cmul(L.h21, own[1]);
+    out[0] = cfmac(L.h20, own[2], cfmac(L.h10, own[1], L.dg[0] * own[0]));
+    out[1] = cfmac(L.h21, own[2], cfma(L.h10, own[0], L.dg[1] * own[1]));
+    out[2] = cfma(L.h21, own[1], cfma(L.h20, own[0], L.dg[2] * own[2]));
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-        out[a] = out[a] + cmul(L.m[3 * a], oth[0]) + cmul(L.m[3 * a + 1], oth[1]) + cmul(L.m[3 * a + 2], oth[2]);
+        out[a] = cfma(L.m[3 * a + 2], oth[2], cfma(L.m[3 * a + 1], oth[1], cfma(L.m[3 * a], oth[0], out[a])));
 }
 
 template <typename S2, typename C>

@@ -18,10 +18,10 @@ __device__ __forceinline__ void hop_lane(cx<float> acc[12], const cx<float> psi[
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const cx<float> p0 = psi[a], p1 = psi[3 + a], p2 = psi[6 + a], p3 = psi[9 + a];
-        if (MU == 0) { h0[a] = p0 + s * itimes(p3); h1[a] = p1 + s * itimes(p2); }
-        if (MU == 1) { h0[a] = p0 + s * p3;         h1[a] = p1 - s * p2; }
-        if (MU == 2) { h0[a] = p0 + s * itimes(p2); h1[a] = p1 - s * itimes(p3); }
-        if (MU == 3) { h0[a] = p0 - s * p2;         h1[a] = p1 - s * p3; }
+        if (MU == 0) { h0[a] = rfma(s, itimes(p3), p0);  h1[a] = rfma(s, itimes(p2), p1); }
+        if (MU == 1) { h0[a] = rfma(s, p3, p0);          h1[a] = rfma(-s, p2, p1); }
+        if (MU == 2) { h0[a] = rfma(s, itimes(p2), p0);  h1[a] = rfma(-s, itimes(p3), p1); }
+        if (MU == 3) { h0[a] = rfma(-s, p2, p0);         h1[a] = rfma(-s, p3, p1); }
     }
     su3_mul(g0, u, h0, false);
     su3_mul(g1, u, h1, false);
@@ -29,19 +29,15 @@ __device__ __forceinline__ void hop_lane(cx<float> acc[12], const cx<float> psi[
     for (int a = 0; a < 3; ++a) {
         acc[a] = acc[a] + g0[a];
         acc[3 + a] = acc[3 + a] + g1[a];
-        if (MU == 0) { acc[6 + a] = acc[6 + a] - s * itimes(g1[a]); acc[9 + a] = acc[9 + a] - s * itimes(g0[a]); }
-        if (MU == 1) { acc[6 + a] = acc[6 + a] - s * g1[a];         acc[9 + a] = acc[9 + a] + s * g0[a]; }
-        if (MU == 2) { acc[6 + a] = acc[6 + a] - s * itimes(g0[a]); acc[9 + a] = acc[9 + a] + s * itimes(g1[a]); }
-        if (MU == 3) { acc[6 + a] = acc[6 + a] - s * g0[a];         acc[9 + a] = acc[9 + a] - s * g1[a]; }
+        if (MU == 0) { acc[6 + a] = rfma(-s, itimes(g1[a]), acc[6 + a]); acc[9 + a] = rfma(-s, itimes(g0[a]), acc[9 + a]); }
+        if (MU == 1) { acc[6 + a] = rfma(-s, g1[a], acc[6 + a]);         acc[9 + a] = rfma(s, g0[a], acc[9 + a]); }
+        if (MU == 2) { acc[6 + a] = rfma(-s, itimes(g0[a]), acc[6 + a]); acc[9 + a] = rfma(s, itimes(g1[a]), acc[9 + a]); }
+        if (MU == 3) { acc[6 + a] = rfma(-s, g0[a], acc[6 + a]);         acc[9 + a] = rfma(-s, g1[a], acc[9 + a]); }
     }
 }
 
 // rows 0, 1 of a stored link and row 2 = conj(row0 x row1)
-__device__ __forceinline__ void link_rebuild(cx<float> u[9]) {
-    u[6] = conjx(cmul(u[1], u[5]) - cmul(u[2], u[4]));
-    u[7] = conjx(cmul(u[2], u[3]) - cmul(u[0], u[5]));
-    u[8] = conjx(cmul(u[0], u[4]) - cmul(u[1], u[3]));
-}
+__device__ __forceinline__ void link_rebuild(cx<float> u[9]) { su3_row2(u); }
 template <typename S2>
 __device__ __forceinline__ void link_rows(cx<float> u[9], const S2 *p, int Vb) {
 #pragma unroll
@@ -77,12 +73,12 @@ __device__ __forceinline__ void clover_apply(cx<float> out[6], const cx<float> i
     const cx<float> a10 = F.f[3], a20 = F.f[4], a21 = F.f[5], c10 = F.f[6], c20 = F.f[7], c21 = F.f[8];
     const cx<float> *B = F.f + 9;
     const cx<float> u0 = in[0], u1 = in[1], u2 = in[2], l0 = in[3], l1 = in[4], l2 = in[5];
-    out[0] = d01.r * u0 + cmulc(a10, u1) + cmulc(a20, u2) + cmul(B[0], l0) + cmul(B[1], l1) + cmul(B[2], l2);
-    out[1] = cmul(a10, u0) + d01.i * u1 + cmulc(a21, u2) + cmul(B[3], l0) + cmul(B[4], l1) + cmul(B[5], l2);
-    out[2] = cmul(a20, u0) + cmul(a21, u1) + d23.r * u2 + cmul(B[6], l0) + cmul(B[7], l1) + cmul(B[8], l2);
-    out[3] = cmulc(B[0], u0) + cmulc(B[3], u1) + cmulc(B[6], u2) + d23.i * l0 + cmulc(c10, l1) + cmulc(c20, l2);
-    out[4] = cmulc(B[1], u0) + cmulc(B[4], u1) + cmulc(B[7], u2) + cmul(c10, l0) + d45.r * l1 + cmulc(c21, l2);
-    out[5] = cmulc(B[2], u0) + cmulc(B[5], u1) + cmulc(B[8], u2) + cmul(c20, l0) + cmul(c21, l1) + d45.i * l2;
+    out[0] = cfma(B[2], l2, cfma(B[1], l1, cfma(B[0], l0, cfmac(a20, u2, cfmac(a10, u1, d01.r * u0)))));
+    out[1] = cfma(B[5], l2, cfma(B[4], l1, cfma(B[3], l0, cfmac(a21, u2, cfma(a10, u0, d01.i * u1)))));
+    out[2] = cfma(B[8], l2, cfma(B[7], l1, cfma(B[6], l0, cfma(a21, u1, cfma(a20, u0, d23.r * u2)))));
+    out[3] = cfmac(c20, l2, cfmac(c10, l1, cfmac(B[6], u2, cfmac(B[3], u1, cfmac(B[0], u0, d23.i * l0)))));
+    out[4] = cfmac(c21, l2, cfma(c10, l0, cfmac(B[7], u2, cfmac(B[4], u1, cfmac(B[1], u0, d45.r * l1)))));
+    out[5] = cfma(c21, l1, cfma(c20, l0, cfmac(B[8], u2, cfmac(B[5], u1, cfmac(B[2], u0, d45.i * l2)))));
 }
 
 template <typename S2>
