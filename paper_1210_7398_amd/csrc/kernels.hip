@@ -1,6 +1,6 @@
 // HIP kernels of libsapq for gfx950: layout conversion, the clover-Wilson operator,
 // the SAP phase kernels (gather, SSOR in hyperplane order, block hop) and BLAS-1.
-#include "sitecore.h"
+#include "twolane.h"
 
 namespace sapq {
 
@@ -128,32 +128,40 @@ __global__ void k_pack_clover(GeomDev g, const double2 *src, double2 *F64, typen
 }
 
 // ================================================================ full operator D
-// out = in - kappa F H in; four lanes per site.  Workgroups are dealt to the 8 XCDs in turn
-// (each with its own L2); the grid is a multiple of 8 and XCD x takes the x-th eighth of the
-// sites, blocks in lexicographic order, so that most neighbours a workgroup reads were
-// fetched into the same L2 by its neighbouring workgroups.
+// out = in - kappa F H in; two lanes per site (lane 0 the four forward hops, lane 1 the four
+// backward ones, as in the SAP phase kernels), 128 sites per workgroup.  Workgroups are dealt
+// to the 8 XCDs in turn (each with its own L2); the grid is a multiple of 8 and XCD x takes
+// the x-th eighth of the sites, blocks in lexicographic order, so that most neighbours a
+// workgroup reads were fetched into the same L2 by its neighbouring workgroups.
 template <int P>
 __global__ void __launch_bounds__(256) k_dslash(GeomDev g, typename Prec<P>::S2 *__restrict__ out,
                                                const typename Prec<P>::S2 *__restrict__ in,
                                                const typename Prec<P>::S2 *__restrict__ U,
                                                const typename Prec<P>::S2 *__restrict__ F, double kappa) {
-    using S2 = typename Prec<P>::S2;
     using C = typename Prec<P>::C;
-    const long i = xcd_site_base(64) + (threadIdx.x >> 2);
-    const int j = (int)(threadIdx.x & 3);
+    const long i = xcd_site_base(128) + (threadIdx.x >> 1);
+    const int d = threadIdx.x & 1;
     if (i >= g.V) return;
     const int bl = (int)(i / g.Vb), s = (int)(i - (long)bl * g.Vb);
     const int ib = g.lex_blk[bl];
-    const LaneNbr n = lane_nbr(g.nbr16[j * g.Vb + s], ib, g.blk_nbr[(2 * j) * g.NB + ib], g.blk_nbr[(2 * j + 1) * g.NB + ib],
-                               g.bc[j]);
-    cx<C> h[12], fh[3], v[3];
-    quad_hop_sum<HOP_ALL, false>(h, g, ib, s, j, n, U, FieldSrc<S2, C>{in});
-    lane_clover(fh, h, F, g, ib, s, j);
-    load_spin(v, in, g, ib, s, j);
+    const C sg = d ? C(-1) : C(1);
+    cx<C> acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = cxz<C>();
+    hop_any<0>(acc, g, in, U, ib, s, d, sg);
+    hop_any<1>(acc, g, in, U, ib, s, d, sg);
+    hop_any<2>(acc, g, in, U, ib, s, d, sg);
+    hop_any<3>(acc, g, in, U, ib, s, d, sg);
+    pair_reduce(acc);
+    cx<C> own[6], fh[6], v[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) own[e] = sel(d != 0, acc[6 + e], acc[e]);
+    clover_block(fh, own, F + ((size_t)ib * 2 + d) * 18 * g.Vb + s, g.Vb);
+    load6(v, in, ib, s, d, g.Vb);
     const C k = C(kappa);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) v[a] = v[a] - k * fh[a];
-    store_spin(out, g, ib, s, j, v);
+    for (int e = 0; e < 6; ++e) v[e] = rfma(-k, fh[e], v[e]);
+    store6(out, ib, s, d, g.Vb, v);
 }
 
 // ================================================================ SAP phase kernel
@@ -618,7 +626,7 @@ bool launch_permute_fields(Ctx *c, const int *perm) {
 }
 
 void launch_dslash(Ctx *c, int prec, void *out, const void *in) {
-    const unsigned grid = (grid_for(4 * c->V, 256) + N_XCD - 1) / N_XCD * N_XCD;
+    const unsigned grid = (grid_for(2 * c->V, 256) + N_XCD - 1) / N_XCD * N_XCD;
     if (prec == SAPQ_FP64) {
         k_dslash<SAPQ_FP64><<<grid, 256, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in, c->U64, c->F64,
                                                          c->prm.kappa);

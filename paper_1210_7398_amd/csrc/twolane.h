@@ -11,13 +11,15 @@
 namespace sapq {
 
 // (1 - s gamma_mu) M psi accumulated into acc, M a full SU(3) matrix; the projection and
-// the rebuild of the lower spins follow the chiral-basis gamma matrices (see sitecore.h)
-template <int MU>
-__device__ __forceinline__ void hop_lane(cx<float> acc[12], const cx<float> psi[12], const cx<float> u[9], float s) {
-    cx<float> h0[3], h1[3], g0[3], g1[3];
+// the rebuild of the lower spins follow the chiral-basis gamma matrices (see sitecore.h).
+// The helpers below are written for the compute type C (float, or double for the FP64
+// operator); the SSOR iterate in LDS is always float.
+template <int MU, typename C>
+__device__ __forceinline__ void hop_lane(cx<C> acc[12], const cx<C> psi[12], const cx<C> u[9], C s) {
+    cx<C> h0[3], h1[3], g0[3], g1[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const cx<float> p0 = psi[a], p1 = psi[3 + a], p2 = psi[6 + a], p3 = psi[9 + a];
+        const cx<C> p0 = psi[a], p1 = psi[3 + a], p2 = psi[6 + a], p3 = psi[9 + a];
         if (MU == 0) { h0[a] = rfma(s, itimes(p3), p0);  h1[a] = rfma(s, itimes(p2), p1); }
         if (MU == 1) { h0[a] = rfma(s, p3, p0);          h1[a] = rfma(-s, p2, p1); }
         if (MU == 2) { h0[a] = rfma(s, itimes(p2), p0);  h1[a] = rfma(-s, itimes(p3), p1); }
@@ -37,42 +39,42 @@ __device__ __forceinline__ void hop_lane(cx<float> acc[12], const cx<float> psi[
 }
 
 // rows 0, 1 of a stored link and row 2 = conj(row0 x row1)
-__device__ __forceinline__ void link_rebuild(cx<float> u[9]) { su3_row2(u); }
-template <typename S2>
-__device__ __forceinline__ void link_rows(cx<float> u[9], const S2 *p, int Vb) {
+template <typename C> __device__ __forceinline__ void link_rebuild(cx<C> u[9]) { su3_row2(u); }
+template <typename S2, typename C>
+__device__ __forceinline__ void link_rows(cx<C> u[9], const S2 *p, int Vb) {
 #pragma unroll
     for (int e = 0; e < 6; ++e) u[e] = ld(p + (size_t)e * Vb);
     link_rebuild(u);
 }
 
 // u <- u^+ on the lanes with dag set, u unchanged on the others (same instructions on both)
-__device__ __forceinline__ void dagger_if(cx<float> u[9], bool dag) {
-    cx<float> t[9];
+template <typename C> __device__ __forceinline__ void dagger_if(cx<C> u[9], bool dag) {
+    cx<C> t[9];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) t[3 * a + b] = sel(dag, u[3 * b + a], u[3 * a + b]);
-    const float sg = dag ? -1.f : 1.f;
+    const C sg = dag ? C(-1) : C(1);
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = {t[e].r, sg * t[e].i};
 }
 
 // one hermitian chiral block [[A, B], [B^+, C]] of F (18 slots, see k_pack_clover)
-struct Clov { cx<float> f[18]; };
+template <typename C = float> struct Clov { cx<C> f[18]; };
 
-template <typename S2>
-__device__ __forceinline__ void load_clov(Clov &F, const S2 *p, int Vb) {
+template <typename S2, typename C>
+__device__ __forceinline__ void load_clov(Clov<C> &F, const S2 *p, int Vb) {
 #pragma unroll
     for (int e = 0; e < 18; ++e) F.f[e] = ld(p + (size_t)e * Vb);
 }
 
 // out = F_k in:  slots 0-2 the six real diagonal entries pairwise, 3-5 / 6-8 the strict
 // lower triangles of A / C, 9-17 B row by row
-__device__ __forceinline__ void clover_apply(cx<float> out[6], const cx<float> in[6], const Clov &F) {
-    const cx<float> d01 = F.f[0], d23 = F.f[1], d45 = F.f[2];
-    const cx<float> a10 = F.f[3], a20 = F.f[4], a21 = F.f[5], c10 = F.f[6], c20 = F.f[7], c21 = F.f[8];
-    const cx<float> *B = F.f + 9;
-    const cx<float> u0 = in[0], u1 = in[1], u2 = in[2], l0 = in[3], l1 = in[4], l2 = in[5];
+template <typename C> __device__ __forceinline__ void clover_apply(cx<C> out[6], const cx<C> in[6], const Clov<C> &F) {
+    const cx<C> d01 = F.f[0], d23 = F.f[1], d45 = F.f[2];
+    const cx<C> a10 = F.f[3], a20 = F.f[4], a21 = F.f[5], c10 = F.f[6], c20 = F.f[7], c21 = F.f[8];
+    const cx<C> *B = F.f + 9;
+    const cx<C> u0 = in[0], u1 = in[1], u2 = in[2], l0 = in[3], l1 = in[4], l2 = in[5];
     out[0] = cfma(B[2], l2, cfma(B[1], l1, cfma(B[0], l0, cfmac(a20, u2, cfmac(a10, u1, d01.r * u0)))));
     out[1] = cfma(B[5], l2, cfma(B[4], l1, cfma(B[3], l0, cfmac(a21, u2, cfma(a10, u0, d01.i * u1)))));
     out[2] = cfma(B[8], l2, cfma(B[7], l1, cfma(B[6], l0, cfma(a21, u1, cfma(a20, u0, d23.r * u2)))));
@@ -81,14 +83,14 @@ __device__ __forceinline__ void clover_apply(cx<float> out[6], const cx<float> i
     out[5] = cfma(c21, l1, cfma(c20, l0, cfmac(B[8], u2, cfmac(B[5], u1, cfmac(B[2], u0, d45.i * l2)))));
 }
 
-template <typename S2>
-__device__ __forceinline__ void clover_block(cx<float> out[6], const cx<float> in[6], const S2 *p, int Vb) {
-    Clov F;
+template <typename S2, typename C>
+__device__ __forceinline__ void clover_block(cx<C> out[6], const cx<C> in[6], const S2 *p, int Vb) {
+    Clov<C> F;
     load_clov(F, p, Vb);
     clover_apply(out, in, F);
 }
 
-__device__ __forceinline__ void pair_reduce(cx<float> acc[12]) {
+template <typename C> __device__ __forceinline__ void pair_reduce(cx<C> acc[12]) {
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
         acc[c].r += quad_get<QUAD_XOR1>(acc[c].r);
@@ -97,14 +99,14 @@ __device__ __forceinline__ void pair_reduce(cx<float> acc[12]) {
 }
 
 // the six components (spins 2d, 2d + 1) of site (ib, s) owned by lane d
-template <typename S2>
-__device__ __forceinline__ void load6(cx<float> v[6], const S2 *f, int ib, int s, int d, int Vb) {
+template <typename S2, typename C>
+__device__ __forceinline__ void load6(cx<C> v[6], const S2 *f, int ib, int s, int d, int Vb) {
     const S2 *p = f + ((size_t)ib * 12 + 6 * d) * Vb + s;
 #pragma unroll
     for (int e = 0; e < 6; ++e) v[e] = ld(p + (size_t)e * Vb);
 }
-template <typename S2>
-__device__ __forceinline__ void store6(S2 *f, int ib, int s, int d, int Vb, const cx<float> v[6]) {
+template <typename S2, typename C>
+__device__ __forceinline__ void store6(S2 *f, int ib, int s, int d, int Vb, const cx<C> v[6]) {
     S2 *p = f + ((size_t)ib * 12 + 6 * d) * Vb + s;
 #pragma unroll
     for (int e = 0; e < 6; ++e) st(p + (size_t)e * Vb, v[e]);
@@ -163,6 +165,31 @@ __device__ __forceinline__ void gather_hop(cx<float> acc[12], const GeomDev &g, 
     const int sn = (int)(hw & 0x7fffu), ibn = bl & BLK_MASK;
     const float ph = (bl & WRAP_BIT) ? g.bc[MU] : 1.f;
     cx<float> psi[12], u[9];
+    load_spinor(psi, x, g, ibn, sn);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) psi[c] = ph * psi[c];
+    const bool at_site = d == 0;
+    link_rows(u, U + ((size_t)(at_site ? ib : ibn) * 4 + MU) * 6 * g.Vb + (at_site ? s : sn), g.Vb);
+    dagger_if(u, d != 0);
+    hop_lane<MU>(acc, psi, u, sg);
+}
+
+// one hop of the lane to a neighbour inside or outside the block, read from the global field x
+// (the full operator); outside neighbours across the lattice boundary take the fermion phase
+template <int MU, typename S2, typename C>
+__device__ __forceinline__ void hop_any(cx<C> acc[12], const GeomDev &g, const S2 *x, const S2 *U, int ib, int s, int d,
+                                        C sg) {
+    const unsigned w = g.nbr16[MU * g.Vb + s];
+    const unsigned hw = d ? (w >> 16) : (w & 0xffffu);
+    const int sn = (int)(hw & 0x7fffu);
+    int ibn = ib;
+    C ph = C(1);
+    if (!(hw & 0x8000u)) {
+        const int bl = g.blk_nbr[(2 * MU + d) * g.NB + ib];
+        ibn = bl & BLK_MASK;
+        ph = (bl & WRAP_BIT) ? C(g.bc[MU]) : C(1);
+    }
+    cx<C> psi[12], u[9];
     load_spinor(psi, x, g, ibn, sn);
 #pragma unroll
     for (int c = 0; c < 12; ++c) psi[c] = ph * psi[c];
