@@ -637,6 +637,9 @@ def nn_study(args):
             print(f"# batched {batched[-1]}", file=sys.stderr, flush=True)
         s.close()
         del s
+        # the batched solver keeps its work memory between calls: hand it back before the next
+        # precision's batch sizes its own
+        sapq.release_batch_arena()
         torch.cuda.empty_cache()
     base = results[0]["time_s"]
     for r in results + batched:
