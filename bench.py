@@ -463,7 +463,13 @@ def batch_study(args):
     # the batched kernels' sources per workgroup and inner iterations per graph replay, timed
     # on the batch itself (median of 3 solves per candidate, to 1e-6 to keep the tuning short)
     t0 = time.time()
-    nr, k_inner = sapq.autotune_batch(solvers, srcs, tol=1e-6)
+    # a fresh cache file, so that the autotuner times every candidate and records them
+    import tempfile
+
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "batch_tune.jsonl")
+        nr, k_inner = sapq.autotune_batch(solvers, srcs, tol=1e-6, cache_path=cache)
+        tune_rec = json.loads(open(cache).read().strip().splitlines()[-1])
     tune_batch_s = time.time() - t0
     print(f"# batch autotune: {nr} sources per workgroup, {k_inner} inner iterations per replay "
           f"({tune_batch_s:.1f} s)", file=sys.stderr, flush=True)
@@ -494,6 +500,8 @@ def batch_study(args):
         "kappa": kappa, "block": list(B), "subblock": list(S), "autotune_s": tune_s,
         "batch_sources_per_workgroup": nr, "batch_inner_iterations_per_replay": k_inner,
         "autotune_batch_s": tune_batch_s,
+        "autotune_batch_candidates": [dict(sources_per_workgroup=c[0], inner_iterations_per_replay=c[1],
+                                           median_s_to_1e6=c[2]) for c in tune_rec.get("candidates", [])],
         "batched_s": t_batch, "one_at_a_time_s": t_seq, "speedup": t_seq / t_batch,
         "batched_max_true_relres": max(x["true_relres"] for x in st),
         "batched_outer_its_max": max(x["outer_its"] for x in st),

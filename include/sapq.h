@@ -293,7 +293,8 @@ int sapq_solve_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double *c
  * sapq_solve_batch calls use it, and returned in *nr_out, *k_out (host, nullable).  x holds
  * the last solve's solutions.  cache_json_path (host, nullable): JSON lines keyed by the
  * lattices, right-hand-side counts, block, sub-block, prec_inner and learned stage; a hit skips
- * the timing, a miss appends the result.  SAPQ_ENOTCONV if no candidate reaches tol.
+ * the timing, a miss appends the result with every timed candidate's median
+ * ("candidates": [[nr, k, seconds], ...]).  SAPQ_ENOTCONV if no candidate reaches tol.
  * The sub-block shape is sapq_autotune's (per context); the environment switch SAPQ_BATCH_NR,
  * when set, overrides NR.
  */

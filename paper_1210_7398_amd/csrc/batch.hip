@@ -1338,6 +1338,8 @@ int sapq_autotune_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double
     double best_t = 1e300;
     int best_nr = 1, best_k = 2, rc = SAPQ_OK;
     const int K[3] = {1, 2, 4};
+    std::string cand;  // every timed candidate, for the cache record
+
     for (int nr = 1; nr <= 4; ++nr)
         for (int ki = 0; ki < 3; ++ki) {
             set_all(nr, K[ki]);
@@ -1356,6 +1358,9 @@ int sapq_autotune_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double
             if (rc) { set_all(0, 0); return rc; }
             if (!ok) continue;
             std::sort(t, t + 3);
+            char cb[64];
+            snprintf(cb, sizeof cb, "%s[%d, %d, %.6f]", cand.empty() ? "" : ", ", nr, K[ki], t[1]);
+            cand += cb;
             if (t[1] < best_t) {
                 best_t = t[1];
                 best_nr = nr;
@@ -1368,8 +1373,8 @@ int sapq_autotune_batch(sapq_ctx *const *ctxs, int nctx, const int *nrhs, double
     if (k_out) *k_out = best_k;
     if (cache_json_path) {
         if (FILE *fp = fopen(cache_json_path, "a")) {
-            fprintf(fp, "{\"key\": \"%s\", \"nr\": %d, \"k_inner\": %d, \"time_s\": %.6f}\n", key.c_str(), best_nr,
-                    best_k, best_t);
+            fprintf(fp, "{\"key\": \"%s\", \"nr\": %d, \"k_inner\": %d, \"time_s\": %.6f, \"candidates\": [%s]}\n",
+                    key.c_str(), best_nr, best_k, best_t, cand.c_str());
             fclose(fp);
         }
     }

@@ -1,5 +1,7 @@
 """Batched solve (several fields of different sizes, several sources each) and the sub-block
 autotuner, through the C ABI, against the FP64 oracle and the one-source solver."""
+import json
+
 import numpy as np
 import pytest
 
@@ -282,6 +284,11 @@ def test_autotune_batch_picks_and_caches(torch_cuda, orc, tmp_path):
     nr, k = sapq.autotune_batch(solvers, srcs, tol=1e-10, cache_path=cache)
     assert 1 <= nr <= 4 and k in (1, 2, 4)
     assert len(open(cache).read().strip().splitlines()) == 1
+    rec = json.loads(open(cache).read().strip())
+    cand = rec["candidates"]  # every timed (nr, k, median seconds); the chosen pair is the fastest
+    assert cand and all(c[0] in (1, 2, 3, 4) and c[1] in (1, 2, 4) and c[2] > 0 for c in cand)
+    fastest = min(cand, key=lambda c: c[2])
+    assert (fastest[0], fastest[1]) == (nr, k) == (rec["nr"], rec["k_inner"])
     assert sapq.autotune_batch(solvers, srcs, tol=1e-10, cache_path=cache) == (nr, k)
     assert len(open(cache).read().strip().splitlines()) == 1
     xs, st = sapq.solve_batch(solvers, srcs, tol=1e-10)
