@@ -625,6 +625,10 @@ def nn_study(args):
         s.nn_set_weights(w)
         for use in (False, True):
             s.use_nn(use)
+            # one untimed batched solve first (the work memory is allocated on the first call)
+            bb = point_sources(V, list(range(min(sub, n_apply))), dev)
+            sapq.solve_batch([s], [bb], tol=1e-10)
+            del bb
             tot, its, worst = 0.0, 0, 0.0
             for k0 in range(0, n_apply, sub):
                 ks = list(range(k0, min(k0 + sub, n_apply)))
@@ -781,6 +785,11 @@ def learned_stage_headline(args):
         s.load_clover(F)
         s.nn_set_weights(w)
         s.use_nn(use)
+        # one untimed batched solve first: the batched solver's work memory is allocated on its
+        # first call (the one-source solver's arena is allocated with the solver, untimed too)
+        bb = point_sources(V, ks[:sub], dev)
+        sapq.solve_batch([s], [bb], tol=tol)
+        del bb
         tot, its, xs = 0.0, 0, []
         for k0 in range(0, len(ks), sub):
             bb = point_sources(V, ks[k0 : k0 + sub], dev)
