@@ -129,17 +129,20 @@ __global__ void k_pack_clover(GeomDev g, const double2 *src, double2 *F64, typen
 
 // ================================================================ full operator D
 // out = in - kappa F H in; two lanes per site (lane 0 the four forward hops, lane 1 the four
-// backward ones, as in the SAP phase kernels), 128 sites per workgroup.  Workgroups are dealt
+// backward ones, as in the SAP phase kernels), DSLASH_SITES(P) sites per workgroup (64 in FP64,
+// whose 248 VGPRs allow two waves per SIMD, else 128).  Workgroups are dealt
 // to the 8 XCDs in turn (each with its own L2); the grid is a multiple of 8 and XCD x takes
 // the x-th eighth of the sites, blocks in lexicographic order, so that most neighbours a
 // workgroup reads were fetched into the same L2 by its neighbouring workgroups.
+constexpr int dslash_sites(int P) { return P == SAPQ_FP64 ? 64 : 128; }
+
 template <int P>
-__global__ void __launch_bounds__(256) k_dslash(GeomDev g, typename Prec<P>::S2 *__restrict__ out,
+__global__ void __launch_bounds__(2 * dslash_sites(P)) k_dslash(GeomDev g, typename Prec<P>::S2 *__restrict__ out,
                                                const typename Prec<P>::S2 *__restrict__ in,
                                                const typename Prec<P>::S2 *__restrict__ U,
                                                const typename Prec<P>::S2 *__restrict__ F, double kappa) {
     using C = typename Prec<P>::C;
-    const long i = xcd_site_base(128) + (threadIdx.x >> 1);
+    const long i = xcd_site_base(dslash_sites(P)) + (threadIdx.x >> 1);
     const int d = threadIdx.x & 1;
     if (i >= g.V) return;
     const int bl = (int)(i / g.Vb), s = (int)(i - (long)bl * g.Vb);
@@ -626,13 +629,15 @@ bool launch_permute_fields(Ctx *c, const int *perm) {
 }
 
 void launch_dslash(Ctx *c, int prec, void *out, const void *in) {
-    const unsigned grid = (grid_for(2 * c->V, 256) + N_XCD - 1) / N_XCD * N_XCD;
     if (prec == SAPQ_FP64) {
-        k_dslash<SAPQ_FP64><<<grid, 256, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in, c->U64, c->F64,
+        constexpr int nt = 2 * dslash_sites(SAPQ_FP64);
+        const unsigned grid = (grid_for(2 * c->V, nt) + N_XCD - 1) / N_XCD * N_XCD;
+        k_dslash<SAPQ_FP64><<<grid, nt, 0, c->stream>>>(c->g, (double2 *)out, (const double2 *)in, c->U64, c->F64,
                                                          c->prm.kappa);
         return;
     }
-    INNER_SWITCH(prec, (k_dslash<P_><<<grid, 256, 0, c->stream>>>(
+    const unsigned grid = (grid_for(2 * c->V, 256) + N_XCD - 1) / N_XCD * N_XCD;
+    INNER_SWITCH(prec, (k_dslash<P_><<<grid, 2 * dslash_sites(P_), 0, c->stream>>>(
                            c->g, (typename Prec<P_>::S2 *)out, (const typename Prec<P_>::S2 *)in,
                            (const typename Prec<P_>::S2 *)c->Uin, (const typename Prec<P_>::S2 *)c->Fin, c->prm.kappa)));
 }
