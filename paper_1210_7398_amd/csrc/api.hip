@@ -712,13 +712,14 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
         zc beta = (rho / rho_old) * (alpha / om);
         blas_bicg_p(c, pi, c->i_p, c->i_r, D2(beta), D2(om), c->i_v);
         precondition(c, c->i_p, c->i_ph);                             // p^ = M p
-        blas_xpay(c, pi, c->i_v, c->i_p, make_double2(-1, 0), c->sap_r);  // v = D p^ = p - r_N
-        zc rv = Z(dot1(c, pi, c->i_rt, c->i_v));
+        double2 d3[3];
+        blas_xpay_dots(c, pi, c->i_v, c->i_p, make_double2(-1, 0), c->sap_r, c->i_rt, 0, 0, d3);  // v = D p^ = p - r_N
+        zc rv = Z(d3[0]);                                             // <r~, v>
         if (!finite(rv)) { *iters = it; return SAPQ_EBREAKDOWN; }
         if (std::abs(rv) == 0) break;
         alpha = rho / rv;
-        blas_xpay(c, pi, c->i_s, c->i_r, D2(-alpha), c->i_v);          // s = r - alpha v
-        double ss = dot1(c, pi, c->i_s, c->i_s).x;
+        blas_xpay_dots(c, pi, c->i_s, c->i_r, D2(-alpha), c->i_v, nullptr, 1, 0, d3);  // s = r - alpha v
+        double ss = d3[1].x;                                          // |s|^2
         ++it;
         if (!std::isfinite(ss)) { *iters = it; return SAPQ_EBREAKDOWN; }
         if (std::sqrt(ss) <= tol) {
@@ -726,11 +727,9 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
             break;
         }
         precondition(c, c->i_s, c->i_sh);                             // s^ = M s
-        blas_xpay(c, pi, c->i_t, c->i_s, make_double2(-1, 0), c->sap_r);  // t = D s^
-        {
-            const void *A[2] = {c->i_t, c->i_t}, *B[2] = {c->i_s, c->i_t};
-            blas_dots(c, pi, 2, A, B, res);
-        }
+        blas_xpay_dots(c, pi, c->i_t, c->i_s, make_double2(-1, 0), c->sap_r, nullptr, 1, 1, d3);  // t = D s^
+        res[0] = d3[2];                                               // <t, s>
+        res[1] = d3[1];                                               // |t|^2
         if (!finite(Z(res[0])) || !std::isfinite(res[1].x)) { *iters = it; return SAPQ_EBREAKDOWN; }
         if (res[1].x == 0) {
             blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, make_double2(0, 0), c->i_ph);
@@ -738,11 +737,9 @@ static int inner_bicgstab(Ctx *c, void *e, const void *rhs, int *iters) {
         }
         om = Z(res[0]) / res[1].x;
         blas_axpbypz(c, pi, e, D2(alpha), c->i_ph, D2(om), c->i_sh);    // e += alpha p^ + om s^
-        blas_xpay(c, pi, c->i_r, c->i_s, D2(-om), c->i_t);             // r = s - om t
-        {
-            const void *A[2] = {c->i_rt, c->i_r}, *B[2] = {c->i_r, c->i_r};
-            blas_dots(c, pi, 2, A, B, res);
-        }
+        blas_xpay_dots(c, pi, c->i_r, c->i_s, D2(-om), c->i_t, c->i_rt, 1, 0, d3);  // r = s - om t
+        res[0] = d3[0];                                               // <r~, r>
+        res[1] = d3[1];                                               // |r|^2
         rho_old = rho;
         rho = Z(res[0]);
         if (!finite(rho) || !std::isfinite(res[1].x)) { *iters = it; return SAPQ_EBREAKDOWN; }
@@ -808,8 +805,9 @@ static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
     // the residual of the iterate in d_x: r = b - D x, |r| / |b|
     auto true_residual = [&]() {
         d64(c, c->d_tmp, c->d_x);
-        blas_xpay(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp);
-        relres = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x) / bn;
+        double2 d3[3];
+        blas_xpay_dots(c, SAPQ_FP64, c->d_r, c->d_b, make_double2(-1, 0), c->d_tmp, nullptr, 1, 0, d3);
+        relres = std::sqrt(d3[1].x) / bn;
     };
     if (!std::isfinite(bn)) {
         set_error("the source is not finite");
@@ -858,8 +856,9 @@ static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
                 if (std::abs(rv) == 0) { restart = true; }
                 else {
                     alpha = rho / rv;
-                    blas_xpay(c, SAPQ_FP64, c->d_s, c->d_r, D2(-alpha), c->d_v);  // s = r - alpha v
-                    double sn = std::sqrt(dot1(c, SAPQ_FP64, c->d_s, c->d_s).x);
+                    double2 d3[3];
+                    blas_xpay_dots(c, SAPQ_FP64, c->d_s, c->d_r, D2(-alpha), c->d_v, nullptr, 1, 0, d3);  // s = r - alpha v
+                    double sn = std::sqrt(d3[1].x);
                     if (!std::isfinite(sn)) { set_error("non-finite outer norm |s|"); rc = SAPQ_EBREAKDOWN; break; }
                     if (sn <= tol * bn) {
                         blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, make_double2(0, 0), c->d_ph);
@@ -889,9 +888,9 @@ static int outer_solve(Ctx *c, double tol, sapq_stats *st) {
                         } else {
                             om = Z(res[0]) / res[1].x;
                             blas_axpbypz(c, SAPQ_FP64, c->d_x, D2(alpha), c->d_ph, D2(om), c->d_sh);
-                            blas_xpay(c, SAPQ_FP64, c->d_r, c->d_s, D2(-om), c->d_t);
+                            blas_xpay_dots(c, SAPQ_FP64, c->d_r, c->d_s, D2(-om), c->d_t, nullptr, 1, 0, d3);
                             rho_old = rho;
-                            double rn = std::sqrt(dot1(c, SAPQ_FP64, c->d_r, c->d_r).x);
+                            double rn = std::sqrt(d3[1].x);
                             if (nh < 256) hist[nh++] = rn / bn;
                             if (!std::isfinite(rn)) { set_error("non-finite outer residual"); rc = SAPQ_EBREAKDOWN; break; }
                             if (rn <= tol * bn || std::abs(om) == 0) restart = true;

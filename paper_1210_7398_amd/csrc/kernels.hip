@@ -480,6 +480,60 @@ __global__ void __launch_bounds__(RED_THREADS) k_dots(size_t n, int nd, const ty
     }
 }
 
+// the value a store rounds v to (the storage precision), as a later load would read it
+__device__ __forceinline__ cx<double> as_stored(const double2 *, cx<double> v) { return v; }
+__device__ __forceinline__ cx<float> as_stored(const float2 *, cx<float> v) { return v; }
+__device__ __forceinline__ cx<float> as_stored(const __half2 *, cx<float> v) {
+    const float2 f = __half22float2(__floats2half2_rn(v.r, v.i));
+    return {f.x, f.y};
+}
+__device__ __forceinline__ cx<float> as_stored(const __hip_bfloat162 *, cx<float> v) {
+    return {__bfloat162float(__float2bfloat16(v.r)), __bfloat162float(__float2bfloat16(v.i))};
+}
+
+// z = x + a y, and in the same pass the partial sums per workgroup, in double, of <w, z> (w
+// not null), <z, z> (zz) and <z, x> (zx), taken on z as stored: the Krylov update and the inner
+// products that follow it read the vectors once
+template <int P>
+__global__ void __launch_bounds__(RED_THREADS) k_xpay_dots(size_t n, typename Prec<P>::S2 *z,
+                                                          const typename Prec<P>::S2 *x, double ar, double ai,
+                                                          const typename Prec<P>::S2 *y,
+                                                          const typename Prec<P>::S2 *w, int zz, int zx,
+                                                          double2 *partials) {
+    using C = typename Prec<P>::C;
+    const cx<C> a{C(ar), C(ai)};
+    __shared__ double sm[RED_THREADS / 64][6];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const cx<C> xv = ld(x + i);
+        const cx<C> zn = as_stored(z, xv + cmul(a, ld(y + i)));
+        st(z + i, zn);
+        if (w) {
+            const cx<C> wv = ld(w + i);
+            acc[0] += (double)wv.r * zn.r + (double)wv.i * zn.i;
+            acc[1] += (double)wv.r * zn.i - (double)wv.i * zn.r;
+        }
+        if (zz) acc[2] += (double)zn.r * zn.r + (double)zn.i * zn.i;
+        if (zx) {
+            acc[4] += (double)zn.r * xv.r + (double)zn.i * xv.i;
+            acc[5] += (double)zn.r * xv.i - (double)zn.i * xv.r;
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        double v = wave_sum(acc[k]);
+        if (lane == 0) sm[wave][k] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        double v = 0;
+        for (int j = 0; j < RED_THREADS / 64; ++j) v += sm[j][threadIdx.x];
+        double *pp = reinterpret_cast<double *>(partials + (size_t)blockIdx.x * 3);
+        pp[threadIdx.x] = v;
+    }
+}
+
 // final sum of the partials: a fixed pairwise tree (256 threads)
 __global__ void __launch_bounds__(256) k_dots_final(int nblocks, const double2 *partials, double2 *out) {
     __shared__ double sm[6][256];
@@ -763,6 +817,20 @@ void blas_dots(Ctx *c, int prec, int nd, const void *const *a, const void *const
     (void)hipMemcpyAsync(c->host_res, c->dev_res, sizeof(double2) * 3, hipMemcpyDeviceToHost, c->stream);
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < nd; ++k) host_out[k] = c->host_res[k];
+    prof_harvest(c);
+}
+
+void blas_xpay_dots(Ctx *c, int prec, void *z, const void *x, double2 a, const void *y, const void *w, int zz, int zx,
+                    double2 host_out[3]) {
+    PREC_SWITCH(prec, ({
+                    using S2 = typename Prec<P_>::S2;
+                    k_xpay_dots<P_><<<c->red_blocks, RED_THREADS, 0, c->stream>>>(
+                        c->nvec, (S2 *)z, (const S2 *)x, a.x, a.y, (const S2 *)y, (const S2 *)w, zz, zx, c->partials);
+                }));
+    k_dots_final<<<1, 256, 0, c->stream>>>(c->red_blocks, c->partials, c->dev_res);
+    (void)hipMemcpyAsync(c->host_res, c->dev_res, sizeof(double2) * 3, hipMemcpyDeviceToHost, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < 3; ++k) host_out[k] = c->host_res[k];
     prof_harvest(c);
 }
 

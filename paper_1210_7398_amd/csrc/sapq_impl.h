@@ -196,6 +196,10 @@ void blas_copy(Ctx *c, int prec, void *dst, const void *src);
 void blas_zero(Ctx *c, int prec, void *dst);
 // z = x + a*y  (complex a)
 void blas_xpay(Ctx *c, int prec, void *z, const void *x, double2 a, const void *y);
+// z = x + a y and, in the same pass, out[0] = <w, z> (w not null), out[1] = <z, z> (zz),
+// out[2] = <z, x> (zx), read back to the host (synchronizes the stream)
+void blas_xpay_dots(Ctx *c, int prec, void *z, const void *x, double2 a, const void *y, const void *w, int zz, int zx,
+                    double2 out[3]);
 // p = r + beta*(p - om*v)
 void blas_bicg_p(Ctx *c, int prec, void *p, const void *r, double2 beta, double2 om, const void *v);
 // e += a*ph + b*sh
