@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_eomr(GeomDev g, EomrArgs a, c
         for (int e = 0; e < 6; ++e) xe[k][e] = cxz<float>();
         if (i < Ve) {
             cx<float> out[6], v[6];
-            block_hop_clover(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
+            block_hop_clover_seq(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
             load6(v, vb, ib, i, d, Vb);
 #pragma unroll
             for (int e = 0; e < 6; ++e) v[e] = v[e] + kappa * out[e];
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_eomr(GeomDev g, EomrArgs a, c
         // (a) t_o = K_oe r_e onto the odd slots
         for (int i = Ve + q0; i < Vb; i += nq) {
             cx<float> out[6];
-            block_hop_clover(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
+            block_hop_clover_seq(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
 #pragma unroll
             for (int e = 0; e < 6; ++e) out[e] = kappa * out[e];
             lds_put6(xs, NS, d, i, out);
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_eomr(GeomDev g, EomrArgs a, c
             for (int e = 0; e < 6; ++e) pe[k][e] = cxz<float>();
             if (i < Ve) {
                 cx<float> out[6], rv[6];
-                block_hop_clover(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
+                block_hop_clover_seq(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
                 lds_get6(rv, xs, NS, d, i);
 #pragma unroll
                 for (int e = 0; e < 6; ++e) {
@@ -207,7 +207,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_eomr(GeomDev g, EomrArgs a, c
     __syncthreads();
     for (int i = Ve + q0; i < Vb; i += nq) {
         cx<float> out[6], v[6];
-        block_hop_clover(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
+        block_hop_clover_seq(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
         load6(v, vb, ib, i, d, Vb);
 #pragma unroll
         for (int e = 0; e < 6; ++e) v[e] = v[e] + kappa * out[e];
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_eomr(GeomDev g, EomrArgs a, c
         }
         store6(y, ib, i, d, Vb, yv);
         cx<float> out[6], v[6];
-        block_hop_clover(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
+        block_hop_clover_seq(out, xs, NS, a.pnb[2 * i + d], a.gnb[i], U, Fk, ib, i, d, Vb, sg);
         load6(v, r, ib, i, d, Vb);
 #pragma unroll
         for (int e = 0; e < 6; ++e) v[e] = v[e] - xv[e] + kappa * out[e];

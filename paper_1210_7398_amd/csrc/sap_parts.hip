@@ -219,8 +219,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     }
                 } else {
                 cx<float> out[6], v[6];
-                block_hop_clover(out, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
-                load6(v, vb, ib, s, d, Vb);
+                block_hop_clover_v(out, v, vb, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     float4 *o = &xs[(3 * d + q) * NS + i];
@@ -295,8 +294,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
         }
         store6(y, ib, s, d, Vb, yv);
         cx<float> out[6], v[6];
-        block_hop_clover(out, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
-        load6(v, r, ib, s, d, Vb);
+        block_hop_clover_v(out, v, r, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
 #pragma unroll
         for (int e = 0; e < 6; ++e) v[e] = v[e] - xv[e] + kappa * out[e];
         store6(r, ib, s, d, Vb, v);

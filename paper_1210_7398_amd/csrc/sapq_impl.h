@@ -61,12 +61,6 @@ template <typename T> __device__ __forceinline__ cx<T> cxz() { return {T(0), T(0
 template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.r + b.r, a.i + b.i}; }
 template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.r - b.r, a.i - b.i}; }
 template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.r, s * a.i}; }
-template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-    return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
-}
-template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
-    return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
-}
 template <typename T> __device__ __forceinline__ cx<T> conjx(cx<T> a) { return {a.r, -a.i}; }
 template <typename T> __device__ __forceinline__ cx<T> itimes(cx<T> a) { return {-a.i, a.r}; }
 
@@ -75,6 +69,16 @@ template <typename T> __device__ __forceinline__ cx<T> itimes(cx<T> a) { return 
 // being rounded and added separately.
 __device__ __forceinline__ float fmx(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmx(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// complex products, with the fused multiply-add spelled out: left to contraction, which of
+// the two products of a component gets fused would depend on the instruction order around
+// it, and so would the rounding
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {fmx(a.r, b.r, -(a.i * b.i)), fmx(a.r, b.i, a.i * b.r)};
+}
+template <typename T> __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {  // conj(a) * b
+    return {fmx(a.r, b.r, a.i * b.i), fmx(a.r, b.i, -(a.i * b.r))};
+}
 template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {  // acc + a b
     return {fmx(-a.i, b.i, fmx(a.r, b.r, acc.r)), fmx(a.i, b.r, fmx(a.r, b.i, acc.i))};
 }

@@ -122,37 +122,91 @@ __device__ __forceinline__ void lds_spinor(cx<float> psi[12], const float4 *xs, 
     }
 }
 
-// One in-block hop of the lane: the neighbour spinor from LDS slot `slot`, the link U_mu
-// at block slot sl (the site for lane 0, the backward neighbour for lane 1, daggered there).
-template <int MU, typename S2>
-__device__ __forceinline__ void lds_hop(cx<float> acc[12], const float4 *xs, int NS, unsigned slot, const S2 *U,
-                                        int ib, int sl, int Vb, float sg) {
-    cx<float> psi[12], u[9];
+// One in-block hop of the lane: the neighbour spinor from LDS slot `slot` and the lane's
+// link rows u (U_mu at the site for lane 0, at the backward neighbour for lane 1, where they
+// are daggered), already loaded.
+template <int MU>
+__device__ __forceinline__ void lds_hop(cx<float> acc[12], const float4 *xs, int NS, unsigned slot, cx<float> u[9],
+                                        float sg) {
+    cx<float> psi[12];
     lds_spinor(psi, xs, NS, (int)slot);
-    link_rows(u, U + ((size_t)ib * 4 + MU) * 6 * Vb + sl, Vb);
+    link_rebuild(u);
     dagger_if(u, sg < 0.f);
     hop_lane<MU>(acc, psi, u, sg);
 }
 
-// sum over the lane's in-block hops of site (ib, s), reduced over the pair, and F of the
-// lane's chiral half:  out = (F sum_{m in block} H_nm x_m) restricted to spins 2d, 2d + 1
-// gl: block slots of the backward neighbours, where lane 1 finds its links
+// the six stored rows of link U_mu at block slot sl of block ib
 template <typename S2>
-__device__ __forceinline__ void block_hop_clover(cx<float> out[6], const float4 *xs, int NS, uint2 nb, uint2 gl,
-                                                 const S2 *U, const S2 *Fk, int ib, int s, int d, int Vb, float sg) {
+__device__ __forceinline__ void link_load(cx<float> u[9], const S2 *U, int ib, int mu, int sl, int Vb) {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u[e] = ld(U + ((size_t)ib * 4 + mu) * 6 * Vb + sl + (size_t)e * Vb);
+}
+
+// sum over the lane's in-block hops of site (ib, s), reduced over the pair, and F of the
+// lane's chiral half:  out = (F sum_{m in block} H_nm x_m) restricted to spins 2d, 2d + 1;
+// with WITH_V also the lane's six components of the field vf at the site.
+// gl: block slots of the backward neighbours, where lane 1 finds its links.
+// Load order (STAGED): the link rows of all four hops before any product, the clover rows
+// after the second hop, v after the third, so that each group arrives while earlier hops
+// compute.  A wait on a load also waits on every load issued before it, so the groups are
+// issued in the order they are used; issuing everything at once, or each hop's links just
+// before the hop (the unstaged order, for kernels short of registers), leaves more of the
+// latency exposed.  Both orders compute the same values.
+template <bool WITH_V, bool STAGED, typename S2>
+__device__ __forceinline__ void block_hop_clover_impl(cx<float> out[6], cx<float> v[6], const S2 *vf, const float4 *xs,
+                                                      int NS, uint2 nb, uint2 gl, const S2 *U, const S2 *Fk, int ib,
+                                                      int s, int d, int Vb, float sg) {
     cx<float> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = cxz<float>();
     const bool at_site = d == 0;
-    lds_hop<0>(acc, xs, NS, nb.x & 0xffffu, U, ib, at_site ? s : (int)(gl.x & 0xffffu), Vb, sg);
-    lds_hop<1>(acc, xs, NS, nb.x >> 16, U, ib, at_site ? s : (int)(gl.x >> 16), Vb, sg);
-    lds_hop<2>(acc, xs, NS, nb.y & 0xffffu, U, ib, at_site ? s : (int)(gl.y & 0xffffu), Vb, sg);
-    lds_hop<3>(acc, xs, NS, nb.y >> 16, U, ib, at_site ? s : (int)(gl.y >> 16), Vb, sg);
+    const int sl[4] = {at_site ? s : (int)(gl.x & 0xffffu), at_site ? s : (int)(gl.x >> 16),
+                       at_site ? s : (int)(gl.y & 0xffffu), at_site ? s : (int)(gl.y >> 16)};
+    cx<float> u[4][9];
+    Clov<float> F;
+    if constexpr (STAGED) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) link_load(u[m], U, ib, m, sl[m], Vb);
+    }
+    if constexpr (!STAGED) link_load(u[0], U, ib, 0, sl[0], Vb);
+    lds_hop<0>(acc, xs, NS, nb.x & 0xffffu, u[0], sg);
+    if constexpr (!STAGED) link_load(u[1], U, ib, 1, sl[1], Vb);
+    lds_hop<1>(acc, xs, NS, nb.x >> 16, u[1], sg);
+    if constexpr (STAGED) load_clov(F, Fk + s, Vb);
+    if constexpr (!STAGED) link_load(u[2], U, ib, 2, sl[2], Vb);
+    lds_hop<2>(acc, xs, NS, nb.y & 0xffffu, u[2], sg);
+    if constexpr (STAGED && WITH_V) load6(v, vf, ib, s, d, Vb);
+    if constexpr (!STAGED) link_load(u[3], U, ib, 3, sl[3], Vb);
+    lds_hop<3>(acc, xs, NS, nb.y >> 16, u[3], sg);
     pair_reduce(acc);
+    if constexpr (!STAGED) {
+        load_clov(F, Fk + s, Vb);
+        if constexpr (WITH_V) load6(v, vf, ib, s, d, Vb);
+    }
     cx<float> own[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) own[e] = sel(d != 0, acc[6 + e], acc[e]);
-    clover_block(out, own, Fk + s, Vb);
+    clover_apply(out, own, F);
+}
+template <typename S2>
+__device__ __forceinline__ void block_hop_clover(cx<float> out[6], const float4 *xs, int NS, uint2 nb, uint2 gl,
+                                                 const S2 *U, const S2 *Fk, int ib, int s, int d, int Vb, float sg) {
+    block_hop_clover_impl<false, true>(out, (cx<float> *)nullptr, (const S2 *)nullptr, xs, NS, nb, gl, U, Fk, ib, s, d,
+                                       Vb, sg);
+}
+// the unstaged order
+template <typename S2>
+__device__ __forceinline__ void block_hop_clover_seq(cx<float> out[6], const float4 *xs, int NS, uint2 nb, uint2 gl,
+                                                     const S2 *U, const S2 *Fk, int ib, int s, int d, int Vb, float sg) {
+    block_hop_clover_impl<false, false>(out, (cx<float> *)nullptr, (const S2 *)nullptr, xs, NS, nb, gl, U, Fk, ib, s, d,
+                                        Vb, sg);
+}
+// staged, and v = the lane's six components of vf at (ib, s)
+template <typename S2>
+__device__ __forceinline__ void block_hop_clover_v(cx<float> out[6], cx<float> v[6], const S2 *vf, const float4 *xs,
+                                                   int NS, uint2 nb, uint2 gl, const S2 *U, const S2 *Fk, int ib, int s,
+                                                   int d, int Vb, float sg) {
+    block_hop_clover_impl<true, true>(out, v, vf, xs, NS, nb, gl, U, Fk, ib, s, d, Vb, sg);
 }
 
 // one hop leaving the block (neighbour in another block, from the global iterate x)
