@@ -264,6 +264,8 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
             c->part_Hp = PT.Hp;
             c->part_threads = std::min(512, std::max(64, ((2 * PT.max_plane + 63) / 64) * 64));
             c->parts_lds = lds;
+            // one workgroup per CU by LDS (a gfx950 workgroup may take all of its CU's LDS)
+            c->parts_staged = (long)lds > (long)max_lds / 2;
             c->ssor_staged = false;
         }
     }

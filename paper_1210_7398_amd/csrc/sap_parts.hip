@@ -81,7 +81,10 @@ __device__ __forceinline__ float xch_wait(unsigned long long w, unsigned long lo
 // barrier for LDS traffic only: global loads (halo words) and stores stay in flight
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <int P>
+// STAGED: the load order of a site update (block_hop_clover_impl); the staged order holds
+// about 40 more registers, which costs nothing where a workgroup's LDS already keeps the CU
+// to one workgroup, and occupancy where several workgroups share a CU
+template <int P, bool STAGED>
 __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, const typename Prec<P>::S2 *rsrc,
                                                          typename Prec<P>::S2 *r, typename Prec<P>::S2 *x,
                                                          typename Prec<P>::S2 *y,
@@ -219,7 +222,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     }
                 } else {
                 cx<float> out[6], v[6];
-                block_hop_clover_v(out, v, vb, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
+                block_hop_clover_v<STAGED>(out, v, vb, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     float4 *o = &xs[(3 * d + q) * NS + i];
@@ -294,7 +297,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
         }
         store6(y, ib, s, d, Vb, yv);
         cx<float> out[6], v[6];
-        block_hop_clover_v(out, v, r, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
+        block_hop_clover_v<STAGED>(out, v, r, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
 #pragma unroll
         for (int e = 0; e < 6; ++e) v[e] = v[e] - xv[e] + kappa * out[e];
         store6(r, ib, s, d, Vb, v);
@@ -389,16 +392,24 @@ void launch_sap_phase_parts(Ctx *c, int colour, int gather, int first, int ssor_
     const dim3 grid(c->g.NBc * c->sap_np), block(c->part_threads);
     INNER_SWITCH(c->prm.prec_inner, ({
                      using S2 = typename Prec<P_>::S2;
-                     k_sap_phase_parts<P_><<<grid, block, c->parts_lds, c->stream>>>(
-                         c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin);
+                     if (c->parts_staged)
+                         k_sap_phase_parts<P_, true><<<grid, block, c->parts_lds, c->stream>>>(
+                             c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin);
+                     else
+                         k_sap_phase_parts<P_, false><<<grid, block, c->parts_lds, c->stream>>>(
+                             c->g, a, (const S2 *)rsrc, (S2 *)r, (S2 *)x, (S2 *)y, (const S2 *)c->Uin, (const S2 *)c->Fin);
                  }));
 }
 
 int set_parts_lds_limit(Ctx *c) {
     if (!c->use_parts || c->parts_lds <= 65536) return 0;
     const int bytes = (int)c->parts_lds;
-    INNER_SWITCH(c->prm.prec_inner, (void)hipFuncSetAttribute((const void *)k_sap_phase_parts<P_>,
-                                                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    INNER_SWITCH(c->prm.prec_inner, ({
+                     (void)hipFuncSetAttribute((const void *)k_sap_phase_parts<P_, true>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+                     (void)hipFuncSetAttribute((const void *)k_sap_phase_parts<P_, false>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+                 }));
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

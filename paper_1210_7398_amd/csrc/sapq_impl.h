@@ -244,6 +244,7 @@ struct Ctx {
     bool use_parts = false;
     int sap_np = 1, part_Vp = 0, part_Hp = 0, part_threads = 512;
     size_t parts_lds = 0;
+    bool parts_staged = false;  // phase kernel in the staged load order (one workgroup per CU by LDS)
     int *part_gslot, *part_pstart, *part_exp, *part_imp, *part_imps;
     uint2 *part_nb, *part_gnb;
     unsigned long long *xch;  // tagged halo words exchanged between the two workgroups of a block

@@ -201,12 +201,12 @@ __device__ __forceinline__ void block_hop_clover_seq(cx<float> out[6], const flo
     block_hop_clover_impl<false, false>(out, (cx<float> *)nullptr, (const S2 *)nullptr, xs, NS, nb, gl, U, Fk, ib, s, d,
                                         Vb, sg);
 }
-// staged, and v = the lane's six components of vf at (ib, s)
-template <typename S2>
+// the same and v = the lane's six components of vf at (ib, s), in either order
+template <bool STAGED, typename S2>
 __device__ __forceinline__ void block_hop_clover_v(cx<float> out[6], cx<float> v[6], const S2 *vf, const float4 *xs,
                                                    int NS, uint2 nb, uint2 gl, const S2 *U, const S2 *Fk, int ib, int s,
                                                    int d, int Vb, float sg) {
-    block_hop_clover_impl<true, true>(out, v, vf, xs, NS, nb, gl, U, Fk, ib, s, d, Vb, sg);
+    block_hop_clover_impl<true, STAGED>(out, v, vf, xs, NS, nb, gl, U, Fk, ib, s, d, Vb, sg);
 }
 
 // one hop leaving the block (neighbour in another block, from the global iterate x)
