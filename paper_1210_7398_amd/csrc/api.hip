@@ -256,7 +256,8 @@ static size_t plan(const sapq_geom *geom, const sapq_params *prm, Ctx *c, HostTa
     for (int np = 1; np <= 2 && !c->use_parts; ++np) {
         if (mode == 0 || (mode > 0 && mode != np)) continue;
         if (!build_parts(geom, T, np, PT)) continue;
-        const size_t lds = 6 * sizeof(float4) * (size_t)(PT.Vp + PT.Hp + 1);
+        // the iterate and halo slots, then the hyperplane and halo-import starts
+        const size_t lds = 6 * sizeof(float4) * (size_t)(PT.Vp + PT.Hp + 1) + 2 * (MAX_PLANES + 1) * sizeof(int);
         if ((long)lds <= (long)max_lds) {
             c->use_parts = true;
             c->sap_np = np;

@@ -118,6 +118,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
     const int *expi = a.exp_idx + (size_t)part * Vp;
     const int *imp = a.imp + (size_t)part * Hp;
     const int *imps = a.imp_start + (size_t)part * (MAX_PLANES + 1);
+    int *xsi = reinterpret_cast<int *>(xs);
     const size_t xstride = (size_t)3 * 24 * Hp;
     unsigned long long *xo = a.xch + ((size_t)blk * a.NP + part) * xstride;
     unsigned long long *xi = a.xch + ((size_t)blk * a.NP + (part ^ 1)) * xstride;
@@ -160,12 +161,35 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
         }
         for (int t = threadIdx.x; t < 6 * (Hp + 1); t += blockDim.x)
             xs[(t / (Hp + 1)) * NS + Vp + t % (Hp + 1)] = make_float4(0.f, 0.f, 0.f, 0.f);
+        // the hyperplane and halo-import starts into LDS behind the iterate: every step reads
+        // them, and from global memory (which the kernel writes, so they cannot go through the
+        // scalar cache) each read would be a load round trip at the head of the step
+        for (int t = threadIdx.x; t < MAX_PLANES + 1; t += blockDim.x) {
+            xsi[6 * 4 * NS + t] = a.pstart[t];
+            xsi[6 * 4 * NS + MAX_PLANES + 1 + t] = imps[t];
+        }
     }
     __syncthreads();
 
     // 2. sweeps: x_n <- (1 - omega) x_n + omega (v_n + kappa F(n) sum_{m in block} H_nm x_m)
     const int H = g.nplanes, nsw = 2 * a.n_ssor;
-    const int *pst = a.pstart;
+    const int *pst = xsi + 6 * 4 * NS;  // the hyperplane starts, copied to LDS in step 1
+    imps = pst + MAX_PLANES + 1;         // and this part's halo-import starts
+    // The table entries of a site (LDS slots of its neighbours, block slots of its backward
+    // neighbours, boundary index) are read one step ahead, for this thread's first site of
+    // the coming hyperplane, right after its current update: read at the start of their own
+    // step they would put a load round trip ahead of every other load of the step.
+    uint2 nb_n = make_uint2(0u, 0u), gl_n = make_uint2(0u, 0u);
+    int kx_n = -1;
+    auto tables_for = [&](int hh) {
+        const int i = pst[hh] + q0;
+        if (i < pst[hh + 1]) {
+            nb_n = pnb[2 * i + d];
+            gl_n = gnb[i];
+            kx_n = a.NP == 2 ? expi[i] : -1;
+        }
+    };
+    tables_for(0);
     for (int w = 0; w < nsw; ++w) {
         const bool fwd = (w & 1) == 0;
         for (int pi = 0; pi < H; ++pi) {
@@ -177,6 +201,12 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
             unsigned tag = 0;
             unsigned long long *src = nullptr;
             unsigned long long pre[IMP_REGS];
+            // every thread issues IMP_REGS loads in every step (a harmless read of the hyperplane
+            // table where there is no word to fetch), so that the number of loads in flight after
+            // the tables read a step ahead is fixed and waiting for those does not wait for these
+            const unsigned long long *pre_p[IMP_REGS];
+#pragma unroll
+            for (int u = 0; u < IMP_REGS; ++u) pre_p[u] = reinterpret_cast<const unsigned long long *>(pst);
             if (a.NP == 2 && pi + 1 < H) {
                 const int nh = fwd ? h + 1 : h - 1;
                 // part 0 reads part 1 through +t (lower hyperplane: this sweep's values in a
@@ -193,11 +223,13 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                         const int t = threadIdx.x + u * blockDim.x;
                         if (t < nw) {
                             const int c = t / ne, e = t - c * ne;
-                            pre[u] = xch_get(src + (size_t)c * Hp + imp[e0 + e]);
+                            pre_p[u] = src + (size_t)c * Hp + imp[e0 + e];
                         }
                     }
                 }
             }
+#pragma unroll
+            for (int u = 0; u < IMP_REGS; ++u) pre[u] = xch_get(const_cast<unsigned long long *>(pre_p[u]));
             // (2) the updates; a part-local site i of plane h sits at block slot
             // i + pst[h] + part (pst[h + 1] - pst[h]) (each part owns one contiguous slot
             // range of every hyperplane, part 0 first)
@@ -209,9 +241,8 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
             // the same value bit for bit: it is skipped and only the boundary words are
             // published again under the new sweep's tag.
             const bool repeat = omega == 1.f && w > 0 && pi == 0;
-            for (int i = pst[h] + q0; i < pst[h + 1]; i += nq) {
+            auto update = [&](int i, uint2 nb, uint2 gl, int kx) {
                 const int s = i + shift;
-                const int kx = a.NP == 2 ? expi[i] : -1;
                 cx<float> xn[6];
                 if (repeat) {
 #pragma unroll
@@ -222,7 +253,7 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                     }
                 } else {
                 cx<float> out[6], v[6];
-                block_hop_clover_v<STAGED>(out, v, vb, xs, NS, pnb[2 * i + d], gnb[i], U, Fk, ib, s, d, Vb, sg);
+                block_hop_clover_v<STAGED>(out, v, vb, xs, NS, nb, gl, U, Fk, ib, s, d, Vb, sg);
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     float4 *o = &xs[(3 * d + q) * NS + i];
@@ -242,7 +273,16 @@ __global__ void __launch_bounds__(512) k_sap_phase_parts(GeomDev g, PartArgs a, 
                         xch_put(dst + (size_t)(12 * d + 2 * e + 1) * Hp, xn[e].i, wt);
                     }
                 }
-            }
+            };
+            // this thread's first site with the tables read a step ahead, then those of the
+            // coming step (at a turn the plane repeats, and so do its tables), then any further
+            // sites (a hyperplane with more sites than the workgroup has lane pairs)
+            const uint2 nb0 = nb_n, gl0 = gl_n;
+            const int kx0 = kx_n, i0 = pst[h] + q0;
+            if (i0 < pst[h + 1]) update(i0, nb0, gl0, kx0);
+            if (pi + 1 < H) tables_for(fwd ? h + 1 : h - 1);
+            for (int i = i0 + nq; i < pst[h + 1]; i += nq)
+                update(i, pnb[2 * i + d], gnb[i], a.NP == 2 ? expi[i] : -1);
             // (3) the halo words into LDS
             if (nw) {
 #pragma unroll
